@@ -1,0 +1,294 @@
+"""CPU oracle for the trigger-station triplet selection (paper Sec. 3.2).
+
+TEST INFRASTRUCTURE ONLY: imported by the test-suite, by the smoke check and by
+the benchmark's CPU-baseline leg, never by the product library, which shares no
+code with it.
+
+Contents
+  * ``OracleConfig``             the parameters of the selection.
+  * ``select``                   the plain C oracle (trig_oracle.c) over a batch
+                                 of events: per-event passing-triplet counts,
+                                 accept flags, error bits; fp32 decisions.
+  * ``select_numpy``             an independent NumPy float32 implementation of
+                                 the same fp32 decisions (vectorised per event).
+  * ``fit_msd_exact``            the paper's fit through the vertex in exact
+                                 rational arithmetic (``fractions.Fraction``).
+  * ``fit_msd_f64``              the same fit in float64 (vectorised).
+  * ``fp32_error_bound``         a rigorous bound on |Q_fp32 - Q_exact| for the
+                                 basis-form fp32 evaluation, used by the pins.
+  * ``accepted_ids``             ascending ids of accepted events.
+
+The fp32 decision contract, MSD test (default), per plane c in {x, y} with the
+hits c_i, c_j, c_k of layers 0, 1, 2 (every line one rounding to binary32):
+    a   = U0*c_i + U1*c_j                      (two products, then one sum)
+    b   = (V0*c_i + V1*c_j) + V2*c_k
+    Q   = a*a + b*b
+    pass_c  <=>  Q / ndf <= T_c                (fp32 division, equality passes)
+with U0 = f32(z1/n01), U1 = f32(-z0/n01), V0 = f32(z0 z2/d), V1 = f32(z1 z2/d),
+V2 = f32(-s01/d), s01 = z0^2 + z1^2, n01 = sqrt(s01), d = n01 * sqrt(s01 + z2^2),
+all of it in float64 before the final rounding.  (u, v) is an orthonormal basis
+of the plane orthogonal to (z0, z1, z2), so that in exact arithmetic
+a^2 + b^2 equals the residual sum of squares of the least-squares line
+c = m z through the vertex.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+import subprocess
+from dataclasses import dataclass
+from fractions import Fraction
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(HERE, "trig_oracle.c")
+LIB = os.path.join(HERE, "liboracle.so")
+
+TESTS = {"msd": 0, "window": 1, "msd_fit": 2}
+INT32_MAX = 2 ** 31 - 1
+
+
+@dataclass(frozen=True)
+class OracleConfig:
+    """Selection parameters.  Defaults: the paper's thresholds (0.03 in x-z,
+    0.025 in y-z, per degree of freedom), two degrees of freedom, accept at two
+    or more passing triplets; layers at 400/410/420 cm."""
+
+    test: str = "msd"
+    z: tuple = (400.0, 410.0, 420.0)
+    msd_max: tuple = (0.03, 0.025)
+    ndf: int = 2
+    window: tuple = (0.005, 0.005)
+    min_triplets: int = 2
+
+
+class _Cfg(ctypes.Structure):
+    _fields_ = [("test", ctypes.c_int32), ("z", ctypes.c_float * 3),
+                ("msd_max", ctypes.c_float * 2), ("ndf", ctypes.c_int32),
+                ("window", ctypes.c_float * 2), ("min_triplets", ctypes.c_int32)]
+
+
+def _to_c(cfg: OracleConfig) -> _Cfg:
+    c = _Cfg()
+    c.test = TESTS[cfg.test]
+    for i in range(3):
+        c.z[i] = cfg.z[i]
+    c.msd_max[0], c.msd_max[1] = cfg.msd_max
+    c.ndf = cfg.ndf
+    c.window[0], c.window[1] = cfg.window
+    c.min_triplets = cfg.min_triplets
+    return c
+
+
+GCC_FLAGS = ["-O2", "-march=x86-64-v3", "-ffp-contract=off", "-fno-fast-math",
+             "-fPIC", "-shared", "-pthread", "-std=c11", "-Wall"]
+
+
+def build(force: bool = False) -> str:
+    """Compile trig_oracle.c into liboracle.so (plain gcc, contraction off)."""
+    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
+        tmp = LIB + ".tmp%d" % os.getpid()
+        subprocess.run(["gcc", *GCC_FLAGS, SRC, "-o", tmp, "-lm"], check=True)
+        os.replace(tmp, LIB)
+    return LIB
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB):
+            build()
+        lib = ctypes.CDLL(LIB)
+        lib.oracle_select.restype = ctypes.c_double
+        lib.oracle_select.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+                                      ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Cfg),
+                                      ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.POINTER(ctypes.c_uint32), ctypes.c_int32]
+        lib.oracle_triplet_msd.restype = ctypes.c_float
+        lib.oracle_triplet_msd.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_float,
+                                           ctypes.c_float, ctypes.c_float]
+        lib.oracle_basis.restype = None
+        lib.oracle_basis.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_void_p]
+        _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p) if a.size else None
+
+
+def select(offsets, x, y, cfg: OracleConfig = OracleConfig(), n_threads: int = 1):
+    """C oracle over a CSR batch.
+
+    Returns (counts int32[E], accept uint8[E], status uint32, seconds).
+    counts[e] is the number of passing triplets, -1 for a malformed layer
+    range, -2 if n0*n1*n2 exceeds INT32_MAX; accept[e] = counts[e] >= min."""
+    lib = _load()
+    off = np.ascontiguousarray(offsets, dtype=np.int32)
+    xs = np.ascontiguousarray(x, dtype=np.float32)
+    ys = np.ascontiguousarray(y, dtype=np.float32)
+    n_ev = (len(off) - 1) // 3
+    counts = np.zeros(n_ev, np.int32)
+    accept = np.zeros(n_ev, np.uint8)
+    st = ctypes.c_uint32(0)
+    c = _to_c(cfg)
+    dt = lib.oracle_select(n_ev, _ptr(off), len(xs), _ptr(xs), _ptr(ys), ctypes.byref(c),
+                           _ptr(counts), _ptr(accept), ctypes.byref(st), int(n_threads))
+    if dt < 0:
+        raise ValueError("oracle_select rejected its arguments")
+    return counts, accept, int(st.value), float(dt)
+
+
+def select_set(evset, cfg: OracleConfig = OracleConfig(), n_threads: int = 1):
+    return select(evset.offsets, evset.x, evset.y, cfg, n_threads)
+
+
+def triplet_msd_c(cfg: OracleConfig, ci: float, cj: float, ck: float) -> float:
+    """fl(Q/ndf) of one triplet in one plane as the C oracle computes it."""
+    c = _to_c(cfg)
+    return float(_load().oracle_triplet_msd(ctypes.byref(c), ci, cj, ck))
+
+
+def basis_c(cfg: OracleConfig) -> np.ndarray:
+    out = np.zeros(5, np.float32)
+    c = _to_c(cfg)
+    _load().oracle_basis(ctypes.byref(c), _ptr(out))
+    return out
+
+
+def accepted_ids(accept: np.ndarray) -> np.ndarray:
+    """Ascending ids of accepted events (the list of selected events that the
+    paper transfers back to the host, Sec. 4.3 step 6)."""
+    return np.flatnonzero(np.asarray(accept) != 0).astype(np.int32)
+
+
+# --------------------------------------------------------------------------
+# Independent NumPy float32 implementation of the same decisions
+# --------------------------------------------------------------------------
+
+def basis_f32(z):
+    """(U0, U1, V0, V1, V2) as float32, from the float64 formulas above."""
+    z0, z1, z2 = (float(np.float32(v)) for v in z)
+    s01 = z0 * z0 + z1 * z1
+    n01 = math.sqrt(s01)
+    d = n01 * math.sqrt(s01 + z2 * z2)
+    return tuple(np.float32(v) for v in (z1 / n01, -z0 / n01, (z0 * z2) / d,
+                                          (z1 * z2) / d, -s01 / d))
+
+
+def _plane_pass_np(ci, cj, ck, cfg: OracleConfig, plane: int):
+    """Boolean [n0, n1, n2] array of plane decisions for one event."""
+    f32 = np.float32
+    T = f32(cfg.msd_max[plane]) if cfg.test != "window" else None
+    if cfg.test == "msd":
+        U0, U1, V0, V1, V2 = basis_f32(cfg.z)
+        a = (U0 * ci)[:, None] + (U1 * cj)[None, :]
+        b = ((V0 * ci)[:, None] + (V1 * cj)[None, :])[:, :, None] + (V2 * ck)[None, None, :]
+        q = (a * a)[:, :, None] + b * b
+        return (q / f32(cfg.ndf)) <= T
+    if cfg.test == "msd_fit":
+        z = [f32(v) for v in cfg.z]
+        szz = (z[0] * z[0] + z[1] * z[1]) + z[2] * z[2]
+        w = f32(1.0 / float(szz))
+        p0, p1, p2 = ci * z[0], cj * z[1], ck * z[2]
+        s = (p0[:, None] + p1[None, :])[:, :, None] + p2[None, None, :]
+        m = s * w
+        r0 = ci[:, None, None] - m * z[0]
+        r1 = cj[None, :, None] - m * z[1]
+        r2 = ck[None, None, :] - m * z[2]
+        q = (r0 * r0 + r1 * r1) + r2 * r2
+        return (q / f32(cfg.ndf)) <= T
+    W = f32(cfg.window[plane])
+    z = [f32(v) for v in cfg.z]
+    si, sj, sk = ci / z[0], cj / z[1], ck / z[2]
+    ok_j = np.abs(sj[None, :] - si[:, None]) < W
+    ok_k = np.abs(sk[None, :] - si[:, None]) < W
+    return ok_j[:, :, None] & ok_k[:, None, :]
+
+
+def select_numpy(offsets, x, y, cfg: OracleConfig = OracleConfig()):
+    """Same outputs as ``select`` (without timing), event by event in NumPy."""
+    off = np.asarray(offsets, dtype=np.int64)
+    xs = np.asarray(x, dtype=np.float32)
+    ys = np.asarray(y, dtype=np.float32)
+    n_ev = (len(off) - 1) // 3
+    counts = np.zeros(n_ev, np.int32)
+    status = 0
+    with np.errstate(all="ignore"):
+        for e in range(n_ev):
+            o = off[3 * e: 3 * e + 4]
+            if not (0 <= o[0] <= o[1] <= o[2] <= o[3] <= len(xs)):
+                counts[e] = -1
+                status |= 1
+                continue
+            n = np.diff(o)
+            if int(n[0]) * int(n[1]) * int(n[2]) > INT32_MAX:
+                counts[e] = -2
+                status |= 2
+                continue
+            if n.min() == 0:
+                continue
+            seg = [slice(o[l], o[l + 1]) for l in range(3)]
+            px = _plane_pass_np(xs[seg[0]], xs[seg[1]], xs[seg[2]], cfg, 0)
+            py = _plane_pass_np(ys[seg[0]], ys[seg[1]], ys[seg[2]], cfg, 1)
+            counts[e] = int(np.count_nonzero(px & py))
+    accept = ((counts >= 0) & (counts >= cfg.min_triplets)).astype(np.uint8)
+    return counts, accept, status
+
+
+# --------------------------------------------------------------------------
+# The fit as the paper states it, in exact and in float64 arithmetic
+# --------------------------------------------------------------------------
+
+def fit_msd_exact(ci, cj, ck, z, ndf) -> Fraction:
+    """MSD per degree of freedom of the least-squares line c = m z through
+    the vertex, fitted to the three hits of one plane (paper Sec. 3.2, step
+    2a/2b), in exact rational arithmetic on the binary32 input values."""
+    c = [Fraction(float(np.float32(v))) for v in (ci, cj, ck)]
+    zz = [Fraction(float(np.float32(v))) for v in z]
+    m = sum(cl * zl for cl, zl in zip(c, zz)) / sum(zl * zl for zl in zz)
+    q = sum((cl - m * zl) ** 2 for cl, zl in zip(c, zz))
+    return q / ndf
+
+
+def fit_msd_f64(ci, cj, ck, z, ndf):
+    """Same fit in float64, vectorised over arrays of triplets."""
+    ci, cj, ck = (np.asarray(v, dtype=np.float32).astype(np.float64) for v in (ci, cj, ck))
+    z0, z1, z2 = (float(np.float32(v)) for v in z)
+    m = (ci * z0 + cj * z1 + ck * z2) / (z0 * z0 + z1 * z1 + z2 * z2)
+    q = (ci - m * z0) ** 2 + (cj - m * z1) ** 2 + (ck - m * z2) ** 2
+    return q / ndf
+
+
+def fp32_error_bound(ci, cj, ck, z):
+    """Upper bound on |Q_fp32 - Q_exact| for the basis-form evaluation
+    (before the division by ndf), vectorised.
+
+    With u = 2^-24 and exact basis (u0, u1, v0, v1, v2): each fp32 constant
+    carries a relative error <= u(1 + 2^-28) (float64 evaluation, then one
+    rounding); a is a two-term dot product with two roundings on top, b a
+    three-term one with three; so |a_fp - a| <= 4u (|u0 ci| + |u1 cj|) and
+    |b_fp - b| <= 5u (|v0 ci| + |v1 cj| + |v2 ck|) (generous).  Squaring and
+    the final sum add at most 3u |Q| (+ O(u^2)).  The bound returned is
+    2|a|da + da^2 + 2|b|db + db^2 + 4u(a^2 + b^2 + da^2 + db^2) with a, b
+    taken from the float64 evaluation plus their own error."""
+    u = 2.0 ** -24
+    z0, z1, z2 = (float(np.float32(v)) for v in z)
+    s01 = z0 * z0 + z1 * z1
+    n01 = math.sqrt(s01)
+    d = n01 * math.sqrt(s01 + z2 * z2)
+    bu = (z1 / n01, -z0 / n01)
+    bv = ((z0 * z2) / d, (z1 * z2) / d, -s01 / d)
+    ci, cj, ck = (np.asarray(v, dtype=np.float32).astype(np.float64) for v in (ci, cj, ck))
+    a = bu[0] * ci + bu[1] * cj
+    b = bv[0] * ci + bv[1] * cj + bv[2] * ck
+    da = 4 * u * (abs(bu[0] * ci) + abs(bu[1] * cj)) * (1 + 1e-6)
+    db = 5 * u * (abs(bv[0] * ci) + abs(bv[1] * cj) + abs(bv[2] * ck)) * (1 + 1e-6)
+    aa = np.abs(a) + da
+    bb = np.abs(b) + db
+    return 2 * aa * da + da * da + 2 * bb * db + db * db + 4 * u * (aa * aa + bb * bb)

@@ -1,0 +1,249 @@
+/*
+ * CPU oracle for the first-level J/psi trigger-station triplet selection.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, includes
+ * or calls this file; only the test-suite, the smoke check and the CPU
+ * baseline of the benchmark load it.  It shares no source with the GPU
+ * library: its structs, constants and arithmetic are written here from the
+ * paper.
+ *
+ * What it computes (paper, Sec. 3.2 "Algorithm", steps 1-3):
+ *   1. every triplet (i, j, k) with one hit from each of the three
+ *      trigger-station layers;
+ *   2. (a) a straight-line fit through the event vertex, separately in the
+ *      x-z and y-z planes (x = m0 z, y = m1 z);
+ *      (b) the mean square deviation of that fit per degree of freedom; the
+ *      triplet is rejected if it exceeds the plane's threshold;
+ *   3. the event is selected if at least two triplets pass.
+ *
+ * Floating point.  The paper fixes no precision.  The decision is taken in
+ * IEEE-754 binary32 (round to nearest even, subnormals kept, no fused
+ * multiply-add: build with -ffp-contract=off and without -ffast-math), in the
+ * operation order written out below, so that an independent implementation
+ * can reproduce every decision bit for bit.  The exact-arithmetic definition
+ * of the same fit lives in reference.py and pins these decisions.
+ *
+ * Three tests are provided:
+ *   MSD (default)  the fit's residual sum of squares Q evaluated as the squared
+ *                  length of the measurement vector's component orthogonal to
+ *                  the layer vector z = (z0, z1, z2), in the orthonormal basis
+ *                  (u, v) of that plane with u = (z1, -z0, 0)/|(z0, z1)| and
+ *                  v = (z0 z2, z1 z2, -(z0^2 + z1^2)) / (|(z0, z1)| |z|).
+ *                  In exact arithmetic Q = min_m sum_l (c_l - m z_l)^2.
+ *   MSD_FIT        the same fit written out literally: slope m = sum(c z) /
+ *                  sum(z^2), residuals r_l = c_l - m z_l, Q = sum r_l^2.
+ *   WINDOW         slope-window test: |c_l/z_l - c_0/z_0| < W for l = 1, 2.
+ * For the MSD tests the triplet passes a plane iff fl(Q / ndf) <= T.
+ */
+#include <math.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <time.h>
+
+enum { OR_TEST_MSD = 0, OR_TEST_WINDOW = 1, OR_TEST_MSD_FIT = 2 };
+
+typedef struct {
+    int32_t test;
+    float z[3];
+    float msd_max[2]; /* per degree of freedom: x-z plane, y-z plane */
+    int32_t ndf;
+    float window[2];
+    int32_t min_triplets;
+} oracle_cfg;
+
+typedef struct {
+    /* MSD (orthonormal basis of the plane orthogonal to z) */
+    float U0, U1, V0, V1, V2;
+    /* MSD_FIT */
+    float zf[3], w;
+} oracle_consts;
+
+static void make_consts(const oracle_cfg *c, oracle_consts *k) {
+    double z0 = c->z[0], z1 = c->z[1], z2 = c->z[2];
+    double s01 = z0 * z0 + z1 * z1;
+    double n01 = sqrt(s01);
+    double szz = s01 + z2 * z2;
+    double nz = sqrt(szz);
+    double d = n01 * nz;
+    k->U0 = (float)(z1 / n01);
+    k->U1 = (float)(-z0 / n01);
+    k->V0 = (float)((z0 * z2) / d);
+    k->V1 = (float)((z1 * z2) / d);
+    k->V2 = (float)(-s01 / d);
+    for (int l = 0; l < 3; ++l) k->zf[l] = c->z[l];
+    float sz = (c->z[0] * c->z[0] + c->z[1] * c->z[1]) + c->z[2] * c->z[2];
+    k->w = (float)(1.0 / (double)sz);
+}
+
+/* One plane of the MSD test, basis form. */
+static int plane_msd(float ci, float cj, float ck, const oracle_consts *k, float T, float ndf) {
+    float a = k->U0 * ci + k->U1 * cj;
+    float b = (k->V0 * ci + k->V1 * cj) + k->V2 * ck;
+    float q = a * a + b * b;
+    float msd = q / ndf;
+    return msd <= T;
+}
+
+/* One plane of the MSD test, fit written out. */
+static int plane_fit(float ci, float cj, float ck, const oracle_consts *k, float T, float ndf) {
+    float p0 = ci * k->zf[0], p1 = cj * k->zf[1], p2 = ck * k->zf[2];
+    float m = ((p0 + p1) + p2) * k->w;
+    float r0 = ci - m * k->zf[0];
+    float r1 = cj - m * k->zf[1];
+    float r2 = ck - m * k->zf[2];
+    float q = (r0 * r0 + r1 * r1) + r2 * r2;
+    float msd = q / ndf;
+    return msd <= T;
+}
+
+/* One plane of the slope-window test. */
+static int plane_window(float ci, float cj, float ck, const oracle_consts *k, float W) {
+    float si = ci / k->zf[0], sj = cj / k->zf[1], sk = ck / k->zf[2];
+    return fabsf(sj - si) < W && fabsf(sk - si) < W;
+}
+
+static int32_t event_count(const oracle_cfg *c, const oracle_consts *k, const int32_t *off,
+                           int64_t e, int32_t n_hits, const float *x, const float *y,
+                           uint32_t *status) {
+    int64_t o0 = off[3 * e], o1 = off[3 * e + 1], o2 = off[3 * e + 2], o3 = off[3 * e + 3];
+    if (!(0 <= o0 && o0 <= o1 && o1 <= o2 && o2 <= o3 && o3 <= n_hits)) {
+        *status |= 1u;
+        return -1;
+    }
+    int64_t n0 = o1 - o0, n1 = o2 - o1, n2 = o3 - o2;
+    /* n0*n1 <= 2^62 fits; compare the full product without forming it */
+    if (n2 > 0 && n0 * n1 > (int64_t)INT32_MAX / n2) {
+        *status |= 2u;
+        return -2;
+    }
+    const float ndf = (float)c->ndf;
+    int32_t cnt = 0;
+    for (int64_t i = o0; i < o1; ++i)
+        for (int64_t j = o1; j < o2; ++j)
+            for (int64_t kk = o2; kk < o3; ++kk) {
+                int pass;
+                if (c->test == OR_TEST_WINDOW) {
+                    pass = plane_window(x[i], x[j], x[kk], k, c->window[0]) &&
+                           plane_window(y[i], y[j], y[kk], k, c->window[1]);
+                } else if (c->test == OR_TEST_MSD_FIT) {
+                    pass = plane_fit(x[i], x[j], x[kk], k, c->msd_max[0], ndf) &&
+                           plane_fit(y[i], y[j], y[kk], k, c->msd_max[1], ndf);
+                } else {
+                    pass = plane_msd(x[i], x[j], x[kk], k, c->msd_max[0], ndf) &&
+                           plane_msd(y[i], y[j], y[kk], k, c->msd_max[1], ndf);
+                }
+                cnt += pass;
+            }
+    return cnt;
+}
+
+typedef struct {
+    const oracle_cfg *cfg;
+    const oracle_consts *k;
+    const int32_t *off;
+    int32_t n_hits;
+    const float *x, *y;
+    int32_t *counts;
+    uint8_t *accept;
+    int64_t e0, e1;
+    uint32_t status;
+} worker_arg;
+
+static void *worker(void *p) {
+    worker_arg *a = (worker_arg *)p;
+    uint32_t st = 0;
+    for (int64_t e = a->e0; e < a->e1; ++e) {
+        int32_t cnt = event_count(a->cfg, a->k, a->off, e, a->n_hits, a->x, a->y, &st);
+        a->counts[e] = cnt;
+        a->accept[e] = (uint8_t)(cnt >= 0 && cnt >= a->cfg->min_triplets);
+    }
+    a->status = st;
+    return NULL;
+}
+
+static double now_s(void) {
+    struct timespec ts;
+    clock_gettime(CLOCK_MONOTONIC, &ts);
+    return (double)ts.tv_sec + 1e-9 * (double)ts.tv_nsec;
+}
+
+/* Cost of an event for splitting work between threads (whole events per
+ * thread, contiguous ranges of roughly equal triplet count). */
+static int64_t event_cost(const int32_t *off, int64_t e) {
+    double n0 = (double)off[3 * e + 1] - off[3 * e];
+    double n1 = (double)off[3 * e + 2] - off[3 * e + 1];
+    double n2 = (double)off[3 * e + 3] - off[3 * e + 2];
+    if (n0 < 0 || n1 < 0 || n2 < 0) return 1;
+    double c = n0 * n1 * n2;
+    return 1 + (c > 1e15 ? (int64_t)1e15 : (int64_t)c);
+}
+
+/* Counts and accept flags for events [0, n_events).  Returns the elapsed
+ * compute time in seconds (thread start to join), or a negative value on bad
+ * arguments.  *status receives the OR of per-event error bits (1 malformed
+ * CSR range, 2 triplet count not representable in int32). */
+double oracle_select(int32_t n_events, const int32_t *off, int32_t n_hits, const float *x,
+                     const float *y, const oracle_cfg *cfg, int32_t *counts, uint8_t *accept,
+                     uint32_t *status, int32_t n_threads) {
+    if (n_events < 0 || (n_events > 0 && (!off || !counts || !accept)) || !cfg || !status)
+        return -1.0;
+    if (n_threads < 1) n_threads = 1;
+    oracle_consts k;
+    make_consts(cfg, &k);
+    double t0 = now_s();
+    if (n_threads == 1 || n_events < 2) {
+        worker_arg a = {cfg, &k, off, n_hits, x, y, counts, accept, 0, n_events, 0};
+        worker(&a);
+        *status = a.status;
+        return now_s() - t0;
+    }
+    int64_t total = 0;
+    for (int64_t e = 0; e < n_events; ++e) total += event_cost(off, e);
+    worker_arg *args = (worker_arg *)calloc((size_t)n_threads, sizeof(worker_arg));
+    pthread_t *th = (pthread_t *)calloc((size_t)n_threads, sizeof(pthread_t));
+    int64_t e = 0, acc = 0;
+    for (int t = 0; t < n_threads; ++t) {
+        int64_t target = total * (t + 1) / n_threads;
+        int64_t e0 = e;
+        while (e < n_events && (acc < target || t == n_threads - 1)) acc += event_cost(off, e++);
+        worker_arg a = {cfg, &k, off, n_hits, x, y, counts, accept, e0, e, 0};
+        args[t] = a;
+        pthread_create(&th[t], NULL, worker, &args[t]);
+    }
+    uint32_t st = 0;
+    for (int t = 0; t < n_threads; ++t) {
+        pthread_join(th[t], NULL);
+        st |= args[t].status;
+    }
+    double dt = now_s() - t0;
+    *status = st;
+    free(args);
+    free(th);
+    return dt;
+}
+
+/* The MSD of one triplet in one plane, as the tests above compute it before
+ * the threshold comparison (fl(Q / ndf)).  For pin tests. */
+float oracle_triplet_msd(const oracle_cfg *cfg, float ci, float cj, float ck) {
+    oracle_consts k;
+    make_consts(cfg, &k);
+    const float ndf = (float)cfg->ndf;
+    if (cfg->test == OR_TEST_MSD_FIT) {
+        float p0 = ci * k.zf[0], p1 = cj * k.zf[1], p2 = ck * k.zf[2];
+        float m = ((p0 + p1) + p2) * k.w;
+        float r0 = ci - m * k.zf[0], r1 = cj - m * k.zf[1], r2 = ck - m * k.zf[2];
+        return ((r0 * r0 + r1 * r1) + r2 * r2) / ndf;
+    }
+    float a = k.U0 * ci + k.U1 * cj;
+    float b = (k.V0 * ci + k.V1 * cj) + k.V2 * ck;
+    return (a * a + b * b) / ndf;
+}
+
+/* The fp32 basis constants (U0, U1, V0, V1, V2), for pin tests. */
+void oracle_basis(const oracle_cfg *cfg, float out[5]) {
+    oracle_consts k;
+    make_consts(cfg, &k);
+    out[0] = k.U0; out[1] = k.U1; out[2] = k.V0; out[3] = k.V1; out[4] = k.V2;
+}
