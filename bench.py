@@ -1,0 +1,269 @@
+#!/usr/bin/env python3
+"""Throughput of the trigger-station triplet selection on one MI355X.
+
+One step = one trig_select call over the whole resident batch (validation,
+triplet counting, accept flags and the ordered accepted-id list) in the
+production form (persistent work stealing with exact pair pruning).  The plain
+one-wave-per-event brute-force form is timed beside it on the same input, and
+both must produce identical counts.  Inputs are generated on the host
+(seeded, synthetic), copied to HBM before the timed region, and outputs stay
+in HBM.
+
+Prints ONE JSON line (stdout).  Progress goes to stderr.
+
+    python bench.py [--steps K] [--warmup W] [--workload medium_1m]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published peaks and the derived fp32 VALU peak (256 CUs x 4 SIMD x
+# 16 lanes x 2.4 GHz, one non-fused, non-packed fp32 op per lane per clock).
+HBM_PEAK_GBS = 8000.0
+VALU_F32_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.32
+OPS_PER_TRIPLET = {"msd": 8, "msd_fit": 28, "window": 4}
+
+WORKLOAD_TEXT = {
+    "medium_1m": "1,000,000 events; Poisson(30) noise hits per layer in r=[20,200] cm; "
+                 "muon pair injected with p=0.01, sigma 0.3 cm; z=400/410/420 cm; MSD cut "
+                 "0.03/0.025 per dof, ndf 2; accept at >=2 triplets",
+    "small_10k": "10,000 events; Poisson(8) hits per layer; pair injection p=0.05",
+    "mixture_4m": "4,000,000 events; Poisson(120(1-b^2)) hits per layer, b~U[0,1]; p=0.01",
+    "dense_100k": "100,000 events; Poisson(200) hits per layer; 10% events with 1-3 pairs",
+}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="medium_1m", choices=sorted(WORKLOAD_TEXT))
+    ap.add_argument("--test", default="msd", choices=["msd", "msd_fit", "window"])
+    ap.add_argument("--form", default="persistent_pruned")
+    ap.add_argument("--plain-steps", type=int, default=5, help="timed steps of the plain form")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0,
+                    help="target wall time of the CPU-oracle baseline sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--only-form", action="store_true", help="time only --form (profiling runs)")
+    return ap.parse_args()
+
+
+def algorithmic(sets_counts, n_events):
+    """Per-launch algorithmic quantities from the layer counts."""
+    n = sets_counts.astype(np.int64)
+    triplets = int((n[:, 0] * n[:, 1] * n[:, 2]).sum())
+    hits = int(n.sum())
+    # dominant kernel: reads 3 offsets + 8 B per hit, writes the 4-byte count
+    # (+1-byte flag in the plain kernel)
+    return triplets, hits
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for p in ("paper_1810_11966_amd/csrc/trig.hip", "paper_1810_11966_amd/csrc/trig_device.hpp"):
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel: str, workload: str, form: str):
+    """HBM bytes per launch from committed rocprofv3 counter runs, if they were
+    taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        with open(path) as f:
+            rec = json.load(f).get(f"{kernel}/{workload}/{form}")
+    except (OSError, ValueError):
+        return None
+    if not rec or rec.get("source_hash") != kernel_source_hash():
+        return None
+    return float(rec["bytes_per_launch"])
+
+
+def time_form(torch, trig, hip_events, dev_in, n_events, form, test, steps, warmup, compact=True):
+    off, x, y = dev_in
+    stream = torch.cuda.current_stream().cuda_stream
+    counts = torch.empty(n_events, dtype=torch.int32, device="cuda")
+    accept = torch.empty(n_events, dtype=torch.uint8, device="cuda")
+    ids = torch.empty(n_events, dtype=torch.int32, device="cuda")
+    n_acc = torch.zeros(1, dtype=torch.int32, device="cuda")
+    p = trig.make_params(test=test, flags=trig.FORMS[form] | (trig.TRIG_OUT_COMPACT if compact else 0))
+    p.out_accepted_ids = ids.data_ptr()
+    p.out_n_accepted = n_acc.data_ptr()
+    ws_bytes = trig.trig_workspace_bytes(n_events, p)
+    ws = torch.empty(max(ws_bytes, 1) + 256, dtype=torch.uint8, device="cuda")
+    addr = (ws.data_ptr() + 255) & ~255
+    p.workspace = addr if ws_bytes else None
+    p.workspace_bytes = ws_bytes
+    ev = trig.TrigEventsCsr(n_events, off.data_ptr())
+    hits = trig.TrigHits(x.numel(), x.data_ptr(), y.data_ptr())
+
+    def call():
+        rc = trig.trig_select(ev, hits, p, counts.data_ptr(), accept.data_ptr(), stream)
+        if rc:
+            raise trig.TrigError(rc, trig.trig_last_error_detail())
+
+    for _ in range(warmup):
+        call()
+    torch.cuda.synchronize()
+    starts = [hip_events.HipEvent() for _ in range(steps)]
+    stops = [hip_events.HipEvent() for _ in range(steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(steps):
+        trig.trig_set_kernel_events(starts[k].handle, stops[k].handle)
+        call()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    trig.trig_set_kernel_events(0, 0)
+    kern_ms = [starts[k].elapsed_ms(stops[k]) for k in range(steps)]
+    return {
+        "elapsed_s": t1 - t0,
+        "kernel_ms_mean": float(np.mean(kern_ms)),
+        "kernel_ms_min": float(np.min(kern_ms)),
+        "counts": counts,
+        "accept": accept,
+        "ids": ids[: int(n_acc.item())],
+        "n_accepted": int(n_acc.item()),
+    }
+
+
+def cpu_baseline(s, test, target_s):
+    from oracle import reference as R
+    threads = max(1, len(os.sched_getaffinity(0)))
+    cfg = R.OracleConfig(test=test)
+    probe = min(s.n_events, 5000)
+    _, _, _, dt = R.select_set(s.subset(0, probe), cfg, n_threads=threads)
+    per_event = max(dt, 1e-6) / probe
+    n = int(min(s.n_events, max(probe, target_s / per_event)))
+    sub = s.subset(0, n)
+    counts, _, _, dt = R.select_set(sub, cfg, n_threads=threads)
+    return {"value": n / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {n} events of the workload, plain C oracle (gcc -O2, fp contraction "
+                      f"off), {threads} threads, compute only, {dt:.2f} s"}, counts
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the selection is per event and shards trivially by "
+              "event range, and this build has no multi-GPU path; run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1810_11966_amd import hip_events, synth, trig
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(2)
+    trig.load()
+
+    spec = synth.WORKLOADS[args.workload]
+    log(f"[bench] generating {args.workload}")
+    t = time.perf_counter()
+    s = synth.make_event_set(spec)
+    log(f"[bench] generated {s.n_events} events, {s.n_hits} hits in {time.perf_counter() - t:.1f}s")
+    n_ev = s.n_events
+    layer_n = s.layer_counts()
+    triplets, hits = algorithmic(layer_n, n_ev)
+
+    dev_in = tuple(torch.from_numpy(a).to("cuda") for a in (s.offsets, s.x, s.y))
+    torch.cuda.synchronize()
+
+    log(f"[bench] timing form={args.form} steps={args.steps} warmup={args.warmup}")
+    main_r = time_form(torch, trig, hip_events, dev_in, n_ev, args.form, args.test, args.steps, args.warmup)
+    ms_per_step = 1e3 * main_r["elapsed_s"] / args.steps
+    value = n_ev * args.steps / main_r["elapsed_s"]
+    log(f"[bench] {args.form}: {ms_per_step:.3f} ms/step, {value:.4g} events/s, "
+        f"dominant kernel {main_r['kernel_ms_mean']:.3f} ms")
+
+    # algorithmic bytes of the dominant kernel: 12 B of offsets per event,
+    # 8 B per hit, 4 B count per event (plain kernel: +1 B flag)
+    kern_bytes = 12 * n_ev + 8 * hits + 4 * n_ev
+    kern_s = main_r["kernel_ms_mean"] / 1e3
+    dominant = "k_persistent" if "persistent" in args.form else "k_plain"
+    traffic = load_traffic(dominant, args.workload, args.form)
+    roofline = {"kernel": dominant, "bound": "hbm", "achieved": kern_bytes / kern_s / 1e9,
+                "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": kern_bytes / kern_s / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
+                "algorithmic_bytes": kern_bytes}
+
+    extra = {}
+    plain_info = None
+    if not args.only_form and args.form != "plain":
+        log(f"[bench] timing form=plain steps={args.plain_steps}")
+        pr = time_form(torch, trig, hip_events, dev_in, n_ev, "plain", args.test, args.plain_steps, 1)
+        same = bool(torch.equal(pr["counts"], main_r["counts"]) and torch.equal(pr["ids"], main_r["ids"]))
+        if not same:
+            print("bench.py: plain and batched forms disagree", file=sys.stderr)
+            sys.exit(1)
+        pk_s = pr["kernel_ms_mean"] / 1e3
+        ops = OPS_PER_TRIPLET[args.test] * triplets
+        plain_info = {
+            "events_per_s": n_ev * args.plain_steps / pr["elapsed_s"],
+            "ms_per_step": 1e3 * pr["elapsed_s"] / args.plain_steps,
+            "kernel_ms": pr["kernel_ms_mean"],
+            "roofline": {"kernel": "k_plain", "bound": "alu", "achieved": ops / pk_s / 1e12,
+                         "peak": VALU_F32_PEAK_TOPS, "unit": "TFLOP/s",
+                         "frac": ops / pk_s / 1e12 / VALU_F32_PEAK_TOPS,
+                         "traffic": load_traffic("k_plain", args.workload, "plain"),
+                         "ops_per_triplet": OPS_PER_TRIPLET[args.test]},
+            "counts_identical": same,
+        }
+        extra["batched_vs_plain"] = value / plain_info["events_per_s"]
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline")
+        cpu, cpu_counts = cpu_baseline(s, args.test, args.cpu_seconds)
+        got = main_r["counts"][: len(cpu_counts)].cpu().numpy()
+        if not np.array_equal(got, cpu_counts):
+            print("bench.py: GPU counts differ from the oracle on the baseline sample", file=sys.stderr)
+            sys.exit(1)
+        extra["oracle_sample_bit_exact"] = True
+
+    out = {
+        "metric": "events/s (batched vs plain, bit-exact decisions); p99 timeslice latency",
+        "value": value,
+        "unit": "events/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic (seeded generator; stands in for the paper's simulated CBM events)",
+        "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}", "n_events": n_ev,
+                   "n_hits": hits, "test": args.test, "form": args.form, "seed": 0},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "triplet_tests_per_s_effective": triplets * args.steps / main_r["elapsed_s"],
+        "n_accepted": main_r["n_accepted"],
+        "plain": plain_info,
+        "p99_slice_latency_ms": None,
+        **extra,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,205 @@
+/*
+ * trig.h - C ABI of the MI355X trigger-station triplet selection library.
+ *
+ * Method (Singhal, Chattopadhyay, Friese, "Investigation of heterogeneous
+ * computing platforms for real-time data analysis in the CBM experiment",
+ * Sec. 3.2 "Algorithm"):
+ *   1. form every triplet of hits with one hit from each of the three layers of
+ *      the MUCH trigger station;
+ *   2. fit each triplet together with the event vertex (0, 0) by a straight
+ *      line through the vertex, separately in the x-z (bending) and y-z planes
+ *      (x = m0 z, y = m1 z), and reject the triplet if the mean square
+ *      deviation per degree of freedom exceeds the plane's threshold
+ *      (0.03 for x-z, 0.025 for y-z);
+ *   3. select the event if at least two triplets pass.
+ * Input hits are grouped into events and carry coordinates (Sec. 3.2, last
+ * paragraph; Sec. 4.3, trigger-station hits only and one coordinate array per
+ * axis); the output is the per-event decision and the list of selected events
+ * (Sec. 4.3, step 6).
+ *
+ * Conventions for every entry point:
+ *   - Pointers are DEVICE memory unless a comment says "host".  The caller
+ *     owns every buffer; the library never allocates, frees or synchronises
+ *     inside trig_select.
+ *   - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
+ *     is complete once that stream has been synchronised.
+ *   - Return codes: TRIG_OK, or a negative TRIG_E* code; trig_strerror()
+ *     describes a code, trig_last_error_detail() the last failure of the
+ *     calling host thread.
+ *
+ * Floating point contract (the paper fixes none): decisions are taken in IEEE
+ * binary32 with round-to-nearest-even, subnormals preserved and no fused
+ * multiply-add, in the operation order below, so that an independent
+ * implementation reproduces every count bit for bit.  Per plane c in {x, y},
+ * for hits c_i, c_j, c_k of layers 0, 1, 2 (each line one binary32 rounding):
+ *
+ *   TRIG_TEST_MSD (default) - the fit's residual sum of squares Q, evaluated
+ *     as the squared length of (c_i, c_j, c_k) projected on the plane
+ *     orthogonal to z = (z0, z1, z2), in the orthonormal basis
+ *       u = (z1, -z0, 0) / n01,   v = (z0 z2, z1 z2, -s01) / (n01 |z|),
+ *       s01 = z0^2 + z1^2, n01 = sqrt(s01), |z| = sqrt(s01 + z2^2):
+ *         a = U0*c_i + U1*c_j
+ *         b = (V0*c_i + V1*c_j) + V2*c_k
+ *         Q = a*a + b*b
+ *     with U0 = f32(z1/n01), U1 = f32(-z0/n01), V0 = f32(z0 z2/d),
+ *     V1 = f32(z1 z2/d), V2 = f32(-s01/d), d = n01 |z|, everything before the
+ *     final rounding evaluated in binary64 in the order written.
+ *   TRIG_TEST_MSD_FIT - the same fit written out:
+ *         m = ((c_i*z0 + c_j*z1) + c_k*z2) * w,  w = f32(1 / f64(Szz)),
+ *         Szz = (z0*z0 + z1*z1) + z2*z2 in binary32,
+ *         r_l = c_l - m*z_l,   Q = (r0*r0 + r1*r1) + r2*r2
+ *   For both MSD tests the plane passes iff  f32(Q / ndf) <= msd_max[c]
+ *   (a triplet is rejected only if its MSD is above the threshold).
+ *   TRIG_TEST_SLOPE_WINDOW - s_l = c_l / z_l (binary32 division); the plane
+ *     passes iff |s_j - s_i| < W_c and |s_k - s_i| < W_c.
+ * A triplet passes iff both planes pass.  Every passing triplet is counted,
+ * including triplets that share hits.
+ */
+#ifndef TRIG_H
+#define TRIG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TRIG_ABI_VERSION 1u
+
+/* Return codes. */
+#define TRIG_OK 0
+#define TRIG_EINVAL (-1)       /* bad argument (see trig_select) */
+#define TRIG_EWORKSPACE (-2)   /* workspace missing or smaller than trig_workspace_bytes */
+#define TRIG_EHIP (-3)         /* a HIP runtime call or kernel launch failed */
+#define TRIG_EUNSUPPORTED (-4) /* flag/test combination not provided */
+
+/* Per-event error values written to out_counts (accept is 0 for them). */
+#define TRIG_COUNT_MALFORMED (-1) /* layer range reversed or outside [0, n_hits] */
+#define TRIG_COUNT_OVERFLOW (-2)  /* n0*n1*n2 > INT32_MAX: count not representable */
+
+/* Sticky bits OR-ed into *out_status (device) when such events occur. */
+#define TRIG_STATUS_MALFORMED 1u
+#define TRIG_STATUS_OVERFLOW 2u
+
+/* Events in CSR form.  layer_offsets: device int32[3*n_events + 1]; the hits
+ * of event e in layer l (l = 0, 1, 2 from the target outwards) are
+ * [layer_offsets[3e+l], layer_offsets[3e+l+1]).  Offsets need not start at 0;
+ * each event is checked on its own (0 <= o0 <= o1 <= o2 <= o3 <= n_hits). */
+typedef struct {
+    int32_t n_events;
+    const int32_t *layer_offsets;
+} trig_events_csr;
+
+/* Hit coordinates, structure of arrays: device float32[n_hits] each, cm. */
+typedef struct {
+    int32_t n_hits;
+    const float *x;
+    const float *y;
+} trig_hits;
+
+/* Triplet test (see the floating point contract above). */
+enum {
+    TRIG_TEST_MSD = 0,
+    TRIG_TEST_SLOPE_WINDOW = 1,
+    TRIG_TEST_MSD_FIT = 2
+};
+
+/* Execution form and output flags (bitwise OR).  Every form computes the same
+ * counts and flags bit for bit. */
+enum {
+    TRIG_EXEC_PLAIN = 0u,       /* one wave per event, every triplet tested */
+    TRIG_EXEC_PERSISTENT = 1u,  /* one persistent launch; waves steal (event,
+                                   pair-range) work units from a global counter;
+                                   needs workspace */
+    TRIG_EXEC_PRUNED = 2u,      /* skip 64-pair tiles whose pairs provably cannot
+                                   pass (MSD: f32(a*a) > Qmax in a plane, since
+                                   Q >= a*a in binary32; window: the layer-1
+                                   window fails); not for TRIG_TEST_MSD_FIT */
+    TRIG_EXEC_BINNED = 4u,      /* slope-cell binning of layer-1 hits so that
+                                   only candidate pairs are formed; MSD and
+                                   window tests */
+    TRIG_EXEC_AUTOTUNE = 8u,    /* let the library pick the form and launch
+                                   shape (tuned table for gfx950) */
+    TRIG_OUT_COMPACT = 16u      /* also write the ascending ids of accepted
+                                   events; needs workspace */
+};
+
+typedef struct {
+    uint32_t abi_version;     /* TRIG_ABI_VERSION */
+    int32_t test;             /* TRIG_TEST_*; default TRIG_TEST_MSD */
+    float z[3];               /* layer positions, cm, finite and > 0;
+                                 default 400, 410, 420 */
+    float msd_max[2];         /* MSD thresholds per degree of freedom, cm^2,
+                                 x-z then y-z; >= 0, not NaN; default
+                                 0.03f, 0.025f */
+    int32_t ndf;              /* degrees of freedom of the fit, >= 1; default 2
+                                 (three measurements, one slope) */
+    float slope_window[2];    /* window test only: W_x, W_y >= 0; default
+                                 0.005f, 0.005f */
+    int32_t min_triplets;     /* accept iff count >= min_triplets (>= 0);
+                                 default 2 */
+    uint32_t flags;           /* TRIG_EXEC_* | TRIG_OUT_* */
+    void *workspace;          /* device scratch owned by the caller, at least
+                                 trig_workspace_bytes() bytes, 256-byte
+                                 aligned; may be NULL when that is 0 */
+    size_t workspace_bytes;
+    int32_t *out_accepted_ids;  /* TRIG_OUT_COMPACT: device int32[n_events] */
+    int32_t *out_n_accepted;    /* TRIG_OUT_COMPACT: device int32[1] */
+    uint32_t *out_status;       /* optional device word; error bits are OR-ed
+                                   in (never cleared by the library) */
+    int32_t tile_pairs;         /* persistent form: pairs per work unit
+                                   (multiple of 64; 0 = library default) */
+    int32_t reserved[7];        /* must be zero */
+} trig_params;
+
+/* Fill *p (host) with the defaults above.  Returns TRIG_OK or TRIG_EINVAL for
+ * a NULL pointer. */
+int trig_params_init(trig_params *p);
+
+/* Bytes of device workspace trig_select needs for this batch and these
+ * parameters (0 for the plain form without compaction).  Host-only call: it
+ * reads ev->n_events and p->flags, never device memory.  Returns 0 for invalid
+ * arguments as well; trig_select then reports the error. */
+size_t trig_workspace_bytes(const trig_events_csr *ev, const trig_params *p);
+
+/* Count the passing triplets of every event and decide acceptance.
+ *   ev, hits, p   host pointers to the descriptors above.
+ *   out_counts    device int32[n_events]: passing triplets, or
+ *                 TRIG_COUNT_MALFORMED / TRIG_COUNT_OVERFLOW.
+ *   out_accept    device uint8[n_events]: 1 iff out_counts[e] >= min_triplets
+ *                 (never for a negative count).
+ *   stream        hipStream_t or NULL.
+ * Errors (returned before anything is enqueued): TRIG_EINVAL for a NULL
+ * required pointer, n_events < 0, n_hits < 0, an ABI mismatch, non-finite or
+ * non-positive z, a negative or NaN threshold or window, ndf < 1,
+ * min_triplets < 0, tile_pairs not a non-negative multiple of 64, non-zero
+ * reserved fields; TRIG_EWORKSPACE; TRIG_EUNSUPPORTED.  TRIG_EHIP if a launch
+ * fails.  n_events == 0 enqueues only the compaction count (0), if requested.
+ * Data-dependent problems are reported per event (see TRIG_COUNT_*) without a
+ * host synchronisation.  Concurrent calls on different streams need distinct
+ * workspaces. */
+int trig_select(const trig_events_csr *ev, const trig_hits *hits, const trig_params *p,
+                int32_t *out_counts, uint8_t *out_accept, void *stream);
+
+/* Profiling hook (host, per calling thread): the following trig_select calls
+ * of this thread record `start` immediately before and `stop` immediately
+ * after the launch of their dominant kernel (the triplet kernel of the chosen
+ * form), on the call's stream, so that hipEventElapsedTime(start, stop) is
+ * that kernel's duration.  Both are hipEvent_t handles created and owned by
+ * the caller; NULL, NULL switches the hook off.  Returns TRIG_OK, or
+ * TRIG_EINVAL if exactly one of them is NULL. */
+int trig_set_kernel_events(void *start, void *stop);
+
+/* Static description of a return code (host). */
+const char *trig_strerror(int code);
+
+/* Detail of the last failed call on this host thread (host), e.g. the HIP
+ * error text; empty string if none. */
+const char *trig_last_error_detail(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TRIG_H */

@@ -1,0 +1,567 @@
+// HIP kernels and C ABI of the trigger-station triplet selection (gfx950).
+//
+// Paper Sec. 3.2 "Algorithm": every one-hit-per-layer triplet is fitted by a
+// line through the vertex in x-z and y-z, rejected if the mean square
+// deviation per degree of freedom is above the plane's cut, and the event is
+// selected with at least two passing triplets.  The selected-event list is
+// what the paper copies back to the host (Sec. 4.3, step 6).
+//
+// Kernels
+//   k_plain        one wave per event, all pair tiles, layer-2 hits in LDS
+//   k_units        persistent form, step 1: per-event validation and the
+//                  number of work units (ceil(pair tiles / tile units))
+//   k_scan_*       exclusive scans of per-block partial sums
+//   k_persistent   persistent grid; waves take batches of work units from one
+//                  global counter and add their counts with integer atomics
+//   k_finalize     accept flags from the accumulated counts
+//   k_compact_*    ordered list of accepted event ids
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <mutex>
+#include <string>
+
+#include "trig.h"
+#include "trig_device.hpp"
+
+using namespace trig;
+
+namespace {
+
+constexpr int kPlainWaves = 4;      // waves (events) per workgroup, plain form
+constexpr int kChunkMsd = 512;      // layer-2 hits per LDS chunk (2 floats each)
+constexpr int kChunkFit = 256;      // layer-2 hits per LDS chunk (4 floats each)
+constexpr int kScanBlock = 256;     // threads of the scan/compaction kernels
+constexpr int kCompactItems = 4;    // events per thread in compaction
+constexpr int kPersistWaves = 4;    // waves per workgroup, persistent form
+constexpr int kPersistBatch = 4;    // work units taken per atomic
+constexpr int kDefaultTileUnits = 8;  // pair tiles (of 64 pairs) per work unit
+
+template <class T>
+struct Chunk;
+template <>
+struct Chunk<MsdTest> { static constexpr int value = kChunkMsd; };
+template <>
+struct Chunk<WindowTest> { static constexpr int value = kChunkMsd; };
+template <>
+struct Chunk<MsdFitTest> { static constexpr int value = kChunkFit; };
+
+__device__ __forceinline__ void write_result(int e, int32_t cnt, const Consts& c,
+                                             int32_t* counts, uint8_t* accept,
+                                             uint32_t* status) {
+    counts[e] = cnt;
+    accept[e] = (uint8_t)(cnt >= 0 && cnt >= c.min_triplets);
+    if (cnt < 0 && status) atomicOr(status, cnt == -1 ? TRIG_STATUS_MALFORMED : TRIG_STATUS_OVERFLOW);
+}
+
+// ---------------------------------------------------------------- plain ---
+
+template <class T, int WPB>
+__global__ __launch_bounds__(WPB * kWave) void k_plain(const int32_t* __restrict__ off,
+                                                       int n_events, const float* __restrict__ x,
+                                                       const float* __restrict__ y, Consts c,
+                                                       int32_t* __restrict__ counts,
+                                                       uint8_t* __restrict__ accept,
+                                                       uint32_t* status, int prune) {
+    constexpr int KCH = Chunk<T>::value;
+    __shared__ __align__(16) float lds_all[WPB][KCH * T::HF];
+    const int w = uniform_i(threadIdx.x / kWave);
+    const int e = uniform_i(blockIdx.x) * WPB + w;
+    if (e >= n_events) return;
+    EventRange ev;
+    int32_t cnt = load_event(off, e, c.n_hits, ev);
+    if (cnt == 0) {
+        const uint32_t tiles = pair_tiles(ev);
+        if (tiles) cnt = (int32_t)wave_count<T, KCH>(x, y, ev, 0, tiles, c, lds_all[w], prune != 0);
+    }
+    if (lane_id() == 0) write_result(e, cnt, c, counts, accept, status);
+}
+
+// ---------------------------------------------------------------- scans ---
+
+// Exclusive scan of one value per thread over a workgroup of kScanBlock
+// threads; also returns the workgroup total.
+template <typename V>
+__device__ V block_exclusive_scan(V v, V& total) {
+    __shared__ V wave_sums[kScanBlock / kWave];
+    const unsigned lane = lane_id();
+    const int w = threadIdx.x / kWave;
+    V incl = v;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const V o = __shfl_up(incl, d, kWave);
+        if ((int)lane >= d) incl += o;
+    }
+    if (lane == kWave - 1) wave_sums[w] = incl;
+    __syncthreads();
+    V before = 0, sum = 0;
+#pragma unroll
+    for (int k = 0; k < kScanBlock / kWave; ++k) {
+        const V s = wave_sums[k];
+        if (k < w) before += s;
+        sum += s;
+    }
+    __syncthreads();
+    total = sum;
+    return before + incl - v;
+}
+
+// In-place exclusive scan of partials[0..n); partials[n] receives the total.
+// One workgroup.
+template <typename V>
+__global__ __launch_bounds__(kScanBlock) void k_scan_partials(V* partials, int n) {
+    V carry = 0;
+    for (int base = 0; base < n; base += kScanBlock) {
+        const int i = base + (int)threadIdx.x;
+        const V v = i < n ? partials[i] : V(0);
+        V total;
+        const V ex = block_exclusive_scan<V>(v, total);
+        if (i < n) partials[i] = carry + ex;
+        carry += total;
+    }
+    if (threadIdx.x == 0) partials[n] = carry;
+}
+
+// ------------------------------------------------------------ compaction ---
+
+__global__ __launch_bounds__(kScanBlock) void k_compact_count(const uint8_t* __restrict__ accept,
+                                                              int n_events,
+                                                              int32_t* __restrict__ partials) {
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock * kCompactItems +
+                         (int64_t)threadIdx.x * kCompactItems;
+    int32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kCompactItems; ++k)
+        if (base + k < n_events) c += accept[base + k] != 0;
+    int32_t total;
+    block_exclusive_scan<int32_t>(c, total);
+    if (threadIdx.x == 0) partials[blockIdx.x] = total;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_compact_write(const uint8_t* __restrict__ accept,
+                                                              int n_events,
+                                                              const int32_t* __restrict__ partials,
+                                                              int n_blocks,
+                                                              int32_t* __restrict__ ids,
+                                                              int32_t* __restrict__ n_out) {
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock * kCompactItems +
+                         (int64_t)threadIdx.x * kCompactItems;
+    uint8_t f[kCompactItems];
+    int32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kCompactItems; ++k) {
+        f[k] = (base + k < n_events) ? (accept[base + k] != 0) : 0;
+        c += f[k];
+    }
+    int32_t total;
+    int32_t pos = partials[blockIdx.x] + block_exclusive_scan<int32_t>(c, total);
+#pragma unroll
+    for (int k = 0; k < kCompactItems; ++k)
+        if (f[k]) ids[pos++] = (int32_t)(base + k);
+    if (blockIdx.x == 0 && threadIdx.x == 0) *n_out = partials[n_blocks];
+}
+
+__global__ void k_store_zero(int32_t* p) { *p = 0; }
+
+// ------------------------------------------------------------ persistent ---
+
+// Per event: validation (error counts written here), count initialised to 0,
+// number of work units stored in ustart[e]; per-block unit totals.
+__global__ __launch_bounds__(kScanBlock) void k_units(const int32_t* __restrict__ off,
+                                                      int n_events, Consts c, int tile_units,
+                                                      int32_t* __restrict__ counts,
+                                                      uint8_t* __restrict__ accept,
+                                                      uint32_t* status,
+                                                      int64_t* __restrict__ ustart,
+                                                      int64_t* __restrict__ partials,
+                                                      unsigned long long* counter) {
+    const int64_t e = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+    int64_t units = 0;
+    if (e < n_events) {
+        int32_t cnt = 0;
+        const int64_t b = 3 * e;
+        const int a0 = off[b], a1 = off[b + 1], a2 = off[b + 2], a3 = off[b + 3];
+        if (!(0 <= a0 && a0 <= a1 && a1 <= a2 && a2 <= a3 && a3 <= c.n_hits)) {
+            cnt = -1;
+        } else {
+            const int64_t n0 = a1 - a0, n1 = a2 - a1, n2 = a3 - a2;
+            if (n2 > 0 && n0 * n1 > (int64_t)INT32_MAX / n2) {
+                cnt = -2;
+            } else if (n2 > 0) {
+                const int64_t tiles = (n0 * n1 + kWave - 1) / kWave;
+                units = (tiles + tile_units - 1) / tile_units;
+            }
+        }
+        counts[e] = cnt;
+        if (cnt < 0) {
+            accept[e] = 0;
+            if (status) atomicOr(status, cnt == -1 ? TRIG_STATUS_MALFORMED : TRIG_STATUS_OVERFLOW);
+        }
+        ustart[e] = units;
+    }
+    int64_t total;
+    block_exclusive_scan<int64_t>(units, total);
+    if (threadIdx.x == 0) partials[blockIdx.x] = total;
+    if (e == 0) *counter = 0ull;
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_units_apply(int n_events,
+                                                            int64_t* __restrict__ ustart,
+                                                            const int64_t* __restrict__ partials,
+                                                            int n_blocks) {
+    const int64_t e = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+    const int64_t units = e < n_events ? ustart[e] : 0;
+    int64_t total;
+    const int64_t ex = block_exclusive_scan<int64_t>(units, total);
+    if (e < n_events) ustart[e] = partials[blockIdx.x] + ex;
+    if (blockIdx.x == 0 && threadIdx.x == 0) ustart[n_events] = partials[n_blocks];
+}
+
+// Largest event e in [0, n) with ustart[e] <= u, for ustart non-decreasing,
+// ustart[0] = 0 <= u < ustart[n].  64-ary search: each round probes 64
+// evenly spaced entries with one load per lane.
+__device__ int wave_find_event(const int64_t* __restrict__ ustart, int n, int64_t u) {
+    const unsigned lane = lane_id();
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int len = hi - lo;
+        const int step = (len + kWave - 1) / kWave;
+        const int64_t idx = (int64_t)lo + (int64_t)lane * step;
+        const bool ok = (idx < hi) && (ustart[idx] <= u);
+        const int cnt = __popcll(__ballot(ok));  // lane 0 always true: cnt >= 1
+        const int nlo = lo + (cnt - 1) * step;
+        const int nhi = (int)min((int64_t)hi, (int64_t)lo + (int64_t)cnt * step);
+        lo = uniform_i(nlo);
+        hi = uniform_i(nhi);
+    }
+    return lo;
+}
+
+template <class T, int WPB>
+__global__ __launch_bounds__(WPB * kWave) void k_persistent(
+    const int32_t* __restrict__ off, int n_events, const float* __restrict__ x,
+    const float* __restrict__ y, Consts c, const int64_t* __restrict__ ustart, int tile_units,
+    unsigned long long* counter, int32_t* counts, int prune) {
+    constexpr int KCH = Chunk<T>::value;
+    __shared__ __align__(16) float lds_all[WPB][KCH * T::HF];
+    const int w = uniform_i(threadIdx.x / kWave);
+    float* lds = lds_all[w];
+    const int64_t total = ustart[n_events];
+    for (;;) {
+        unsigned long long first = 0;
+        if (lane_id() == 0) first = atomicAdd(counter, (unsigned long long)kPersistBatch);
+        first = __shfl(first, 0, kWave);
+        if ((int64_t)first >= total) break;
+        const int64_t last = min((int64_t)first + kPersistBatch, total);
+        int e = wave_find_event(ustart, n_events, (int64_t)first);
+        for (int64_t u = (int64_t)first; u < last; ++u) {
+            while (ustart[e + 1] <= u) ++e;  // next non-empty event
+            EventRange ev;
+            load_event(off, e, c.n_hits, ev);  // valid: only such events own units
+            const uint32_t tiles = pair_tiles(ev);
+            const uint32_t tb = (uint32_t)((u - ustart[e]) * tile_units);
+            const uint32_t te = min(tiles, tb + (uint32_t)tile_units);
+            const uint32_t cnt = wave_count<T, KCH>(x, y, ev, tb, te, c, lds, prune != 0);
+            if (lane_id() == 0 && cnt) atomicAdd(&counts[e], (int32_t)cnt);
+        }
+    }
+}
+
+__global__ __launch_bounds__(kScanBlock) void k_finalize(int n_events, Consts c,
+                                                         const int32_t* __restrict__ counts,
+                                                         uint8_t* __restrict__ accept) {
+    const int64_t e = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
+    if (e < n_events) {
+        const int32_t cnt = counts[e];
+        accept[e] = (uint8_t)(cnt >= 0 && cnt >= c.min_triplets);
+    }
+}
+
+// ------------------------------------------------------------------ host ---
+
+thread_local std::string g_detail;
+thread_local hipEvent_t g_ev_start = nullptr, g_ev_stop = nullptr;
+
+// Records the profiling hook's start event before the dominant kernel.
+int mark_start(hipStream_t s) {
+    if (g_ev_start && hipEventRecord(g_ev_start, s) != hipSuccess) return -1;
+    return 0;
+}
+int mark_stop(hipStream_t s) {
+    if (g_ev_stop && hipEventRecord(g_ev_stop, s) != hipSuccess) return -1;
+    return 0;
+}
+
+int fail(int code, const std::string& why) {
+    g_detail = why;
+    return code;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Largest binary32 q with f32(q / ndf) <= t.  f32(q / ndf) is non-decreasing
+// in q, so {q : f32(q / ndf) <= t} is exactly {q <= Qmax}.
+float fold_threshold(float t, int ndf) {
+    const float n = (float)ndf;
+    if (std::isinf(t)) return t;
+    volatile float q = t * n;
+    while (!((float)(q / n) <= t)) q = std::nextafter((float)q, -INFINITY);
+    for (;;) {
+        const float up = std::nextafter((float)q, INFINITY);
+        if (std::isinf(up) || !((float)(up / n) <= t)) break;
+        q = up;
+    }
+    return q;
+}
+
+Consts make_consts(const trig_params* p, int n_hits) {
+    Consts c;
+    const double z0 = p->z[0], z1 = p->z[1], z2 = p->z[2];
+    const double s01 = z0 * z0 + z1 * z1;
+    const double n01 = std::sqrt(s01);
+    const double d = n01 * std::sqrt(s01 + z2 * z2);
+    c.U0 = (float)(z1 / n01);
+    c.U1 = (float)(-z0 / n01);
+    c.V0 = (float)((z0 * z2) / d);
+    c.V1 = (float)((z1 * z2) / d);
+    c.V2 = (float)(-s01 / d);
+    c.z0 = p->z[0];
+    c.z1 = p->z[1];
+    c.z2 = p->z[2];
+    const float szz = (c.z0 * c.z0 + c.z1 * c.z1) + c.z2 * c.z2;
+    c.w = (float)(1.0 / (double)szz);
+    c.qmax_x = fold_threshold(p->msd_max[0], p->ndf);
+    c.qmax_y = fold_threshold(p->msd_max[1], p->ndf);
+    c.win_x = p->slope_window[0];
+    c.win_y = p->slope_window[1];
+    c.min_triplets = p->min_triplets;
+    c.n_hits = n_hits;
+    return c;
+}
+
+int validate(const trig_events_csr* ev, const trig_hits* hits, const trig_params* p) {
+    if (!ev || !hits || !p) return fail(TRIG_EINVAL, "NULL descriptor");
+    if (p->abi_version != TRIG_ABI_VERSION) return fail(TRIG_EINVAL, "abi_version mismatch");
+    if (ev->n_events < 0) return fail(TRIG_EINVAL, "n_events < 0");
+    if (hits->n_hits < 0) return fail(TRIG_EINVAL, "n_hits < 0");
+    if (ev->n_events > 0 && !ev->layer_offsets) return fail(TRIG_EINVAL, "layer_offsets is NULL");
+    if (hits->n_hits > 0 && (!hits->x || !hits->y)) return fail(TRIG_EINVAL, "x or y is NULL");
+    if (p->test != TRIG_TEST_MSD && p->test != TRIG_TEST_MSD_FIT && p->test != TRIG_TEST_SLOPE_WINDOW)
+        return fail(TRIG_EINVAL, "unknown test");
+    for (int l = 0; l < 3; ++l)
+        if (!std::isfinite(p->z[l]) || !(p->z[l] > 0.0f)) return fail(TRIG_EINVAL, "z must be finite and > 0");
+    for (int k = 0; k < 2; ++k) {
+        if (std::isnan(p->msd_max[k]) || p->msd_max[k] < 0.0f) return fail(TRIG_EINVAL, "msd_max must be >= 0");
+        if (std::isnan(p->slope_window[k]) || p->slope_window[k] < 0.0f)
+            return fail(TRIG_EINVAL, "slope_window must be >= 0");
+    }
+    if (p->ndf < 1) return fail(TRIG_EINVAL, "ndf < 1");
+    if (p->min_triplets < 0) return fail(TRIG_EINVAL, "min_triplets < 0");
+    if (p->tile_pairs < 0 || p->tile_pairs % kWave) return fail(TRIG_EINVAL, "tile_pairs not a multiple of 64");
+    for (int r : p->reserved)
+        if (r) return fail(TRIG_EINVAL, "reserved fields must be zero");
+    const uint32_t known = TRIG_EXEC_PERSISTENT | TRIG_EXEC_PRUNED | TRIG_EXEC_BINNED |
+                           TRIG_EXEC_AUTOTUNE | TRIG_OUT_COMPACT;
+    if (p->flags & ~known) return fail(TRIG_EINVAL, "unknown flag bits");
+    if ((p->flags & TRIG_OUT_COMPACT) && (!p->out_accepted_ids || !p->out_n_accepted))
+        return fail(TRIG_EINVAL, "TRIG_OUT_COMPACT needs out_accepted_ids and out_n_accepted");
+    if ((p->flags & TRIG_EXEC_PRUNED) && p->test == TRIG_TEST_MSD_FIT)
+        return fail(TRIG_EUNSUPPORTED, "pruning is not provided for TRIG_TEST_MSD_FIT");
+    if (p->flags & (TRIG_EXEC_BINNED | TRIG_EXEC_AUTOTUNE))
+        return fail(TRIG_EUNSUPPORTED, "binned/autotuned forms are not built in this library version");
+    return TRIG_OK;
+}
+
+struct Layout {
+    size_t compact_off = 0, units_off = 0, upart_off = 0, counter_off = 0, total = 0;
+    int compact_blocks = 0, unit_blocks = 0;
+};
+
+Layout layout(int n_events, uint32_t flags) {
+    Layout L;
+    size_t at = 0;
+    if (flags & TRIG_OUT_COMPACT) {
+        L.compact_blocks = (int)std::max<int64_t>(1, cdiv(n_events, (int64_t)kScanBlock * kCompactItems));
+        L.compact_off = at;
+        at += align256(sizeof(int32_t) * (size_t)(L.compact_blocks + 1));
+    }
+    if (flags & TRIG_EXEC_PERSISTENT) {
+        L.unit_blocks = (int)std::max<int64_t>(1, cdiv(n_events, kScanBlock));
+        L.counter_off = at;
+        at += 256;
+        L.units_off = at;
+        at += align256(sizeof(int64_t) * ((size_t)n_events + 1));
+        L.upart_off = at;
+        at += align256(sizeof(int64_t) * (size_t)(L.unit_blocks + 1));
+    }
+    L.total = at;
+    return L;
+}
+
+int check_launch(const char* what) {
+    const hipError_t err = hipGetLastError();
+    if (err != hipSuccess) return fail(TRIG_EHIP, std::string(what) + ": " + hipGetErrorString(err));
+    return TRIG_OK;
+}
+
+int device_cus() {
+    static std::mutex mu;
+    static int cached[64] = {0};
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!cached[dev]) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+        cached[dev] = v;
+    }
+    return cached[dev];
+}
+
+template <class T>
+int launch_plain(const trig_events_csr* ev, const trig_hits* h, const Consts& c, bool prune,
+                 int32_t* counts, uint8_t* accept, uint32_t* status, hipStream_t s) {
+    const int n = ev->n_events;
+    const unsigned grid = (unsigned)cdiv(n, kPlainWaves);
+    if (mark_start(s)) return fail(TRIG_EHIP, "hipEventRecord(start)");
+    hipLaunchKernelGGL((k_plain<T, kPlainWaves>), dim3(grid), dim3(kPlainWaves * kWave), 0, s,
+                       ev->layer_offsets, n, h->x, h->y, c, counts, accept, status, prune ? 1 : 0);
+    if (int r = check_launch("k_plain")) return r;
+    if (mark_stop(s)) return fail(TRIG_EHIP, "hipEventRecord(stop)");
+    return TRIG_OK;
+}
+
+template <class T>
+int launch_persistent(const trig_events_csr* ev, const trig_hits* h, const Consts& c, bool prune,
+                      int tile_units, const Layout& L, char* ws, int32_t* counts, uint8_t* accept,
+                      uint32_t* status, hipStream_t s) {
+    const int n = ev->n_events;
+    auto* counter = reinterpret_cast<unsigned long long*>(ws + L.counter_off);
+    auto* ustart = reinterpret_cast<int64_t*>(ws + L.units_off);
+    auto* upart = reinterpret_cast<int64_t*>(ws + L.upart_off);
+    hipLaunchKernelGGL(k_units, dim3(L.unit_blocks), dim3(kScanBlock), 0, s, ev->layer_offsets, n, c,
+                       tile_units, counts, accept, status, ustart, upart, counter);
+    if (int r = check_launch("k_units")) return r;
+    hipLaunchKernelGGL(k_scan_partials<int64_t>, dim3(1), dim3(kScanBlock), 0, s, upart, L.unit_blocks);
+    if (int r = check_launch("k_scan_partials")) return r;
+    hipLaunchKernelGGL(k_units_apply, dim3(L.unit_blocks), dim3(kScanBlock), 0, s, n, ustart, upart,
+                       L.unit_blocks);
+    if (int r = check_launch("k_units_apply")) return r;
+    // Enough resident waves to fill every CU; each exits once the counter
+    // passes the unit total.
+    const unsigned grid = (unsigned)device_cus() * 8u;
+    if (mark_start(s)) return fail(TRIG_EHIP, "hipEventRecord(start)");
+    hipLaunchKernelGGL((k_persistent<T, kPersistWaves>), dim3(grid), dim3(kPersistWaves * kWave), 0, s,
+                       ev->layer_offsets, n, h->x, h->y, c, ustart, tile_units, counter, counts,
+                       prune ? 1 : 0);
+    if (int r = check_launch("k_persistent")) return r;
+    if (mark_stop(s)) return fail(TRIG_EHIP, "hipEventRecord(stop)");
+    hipLaunchKernelGGL(k_finalize, dim3(L.unit_blocks), dim3(kScanBlock), 0, s, n, c, counts, accept);
+    return check_launch("k_finalize");
+}
+
+template <class T>
+int run_form(const trig_events_csr* ev, const trig_hits* h, const trig_params* p, const Consts& c,
+             const Layout& L, char* ws, int32_t* counts, uint8_t* accept, hipStream_t s) {
+    const bool prune = (p->flags & TRIG_EXEC_PRUNED) != 0;
+    if (p->flags & TRIG_EXEC_PERSISTENT) {
+        const int tile_units = p->tile_pairs ? p->tile_pairs / kWave : kDefaultTileUnits;
+        return launch_persistent<T>(ev, h, c, prune, tile_units, L, ws, counts, accept, p->out_status, s);
+    }
+    return launch_plain<T>(ev, h, c, prune, counts, accept, p->out_status, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int trig_params_init(trig_params* p) {
+    if (!p) return fail(TRIG_EINVAL, "NULL params");
+    std::memset(p, 0, sizeof(*p));
+    p->abi_version = TRIG_ABI_VERSION;
+    p->test = TRIG_TEST_MSD;
+    p->z[0] = 400.0f;
+    p->z[1] = 410.0f;
+    p->z[2] = 420.0f;
+    p->msd_max[0] = 0.03f;
+    p->msd_max[1] = 0.025f;
+    p->ndf = 2;
+    p->slope_window[0] = 0.005f;
+    p->slope_window[1] = 0.005f;
+    p->min_triplets = 2;
+    p->flags = TRIG_EXEC_PLAIN;
+    return TRIG_OK;
+}
+
+size_t trig_workspace_bytes(const trig_events_csr* ev, const trig_params* p) {
+    if (!ev || !p || ev->n_events < 0) return 0;
+    return layout(ev->n_events, p->flags).total;
+}
+
+int trig_select(const trig_events_csr* ev, const trig_hits* hits, const trig_params* p,
+                int32_t* out_counts, uint8_t* out_accept, void* stream) {
+    if (int r = validate(ev, hits, p)) return r;
+    const int n = ev->n_events;
+    if (n > 0 && (!out_counts || !out_accept)) return fail(TRIG_EINVAL, "out_counts or out_accept is NULL");
+    const Layout L = layout(n, p->flags);
+    if (L.total && (!p->workspace || p->workspace_bytes < L.total))
+        return fail(TRIG_EWORKSPACE, "workspace smaller than trig_workspace_bytes()");
+    if (L.total && (reinterpret_cast<uintptr_t>(p->workspace) & 255))
+        return fail(TRIG_EWORKSPACE, "workspace must be 256-byte aligned");
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    char* ws = static_cast<char*>(p->workspace);
+    const Consts c = make_consts(p, hits->n_hits);
+
+    if (n > 0) {
+        int r = TRIG_OK;
+        switch (p->test) {
+            case TRIG_TEST_MSD: r = run_form<MsdTest>(ev, hits, p, c, L, ws, out_counts, out_accept, s); break;
+            case TRIG_TEST_MSD_FIT: r = run_form<MsdFitTest>(ev, hits, p, c, L, ws, out_counts, out_accept, s); break;
+            default: r = run_form<WindowTest>(ev, hits, p, c, L, ws, out_counts, out_accept, s); break;
+        }
+        if (r) return r;
+    }
+    if (p->flags & TRIG_OUT_COMPACT) {
+        if (n == 0) {
+            hipLaunchKernelGGL(k_store_zero, dim3(1), dim3(1), 0, s, p->out_n_accepted);
+            return check_launch("k_store_zero");
+        }
+        auto* part = reinterpret_cast<int32_t*>(ws + L.compact_off);
+        hipLaunchKernelGGL(k_compact_count, dim3(L.compact_blocks), dim3(kScanBlock), 0, s, out_accept, n, part);
+        if (int r = check_launch("k_compact_count")) return r;
+        hipLaunchKernelGGL(k_scan_partials<int32_t>, dim3(1), dim3(kScanBlock), 0, s, part, L.compact_blocks);
+        if (int r = check_launch("k_scan_partials")) return r;
+        hipLaunchKernelGGL(k_compact_write, dim3(L.compact_blocks), dim3(kScanBlock), 0, s, out_accept, n, part,
+                           L.compact_blocks, p->out_accepted_ids, p->out_n_accepted);
+        if (int r = check_launch("k_compact_write")) return r;
+    }
+    g_detail.clear();
+    return TRIG_OK;
+}
+
+int trig_set_kernel_events(void* start, void* stop) {
+    if ((start == nullptr) != (stop == nullptr)) return fail(TRIG_EINVAL, "give both events or neither");
+    g_ev_start = reinterpret_cast<hipEvent_t>(start);
+    g_ev_stop = reinterpret_cast<hipEvent_t>(stop);
+    return TRIG_OK;
+}
+
+const char* trig_strerror(int code) {
+    switch (code) {
+        case TRIG_OK: return "success";
+        case TRIG_EINVAL: return "invalid argument";
+        case TRIG_EWORKSPACE: return "workspace missing, too small or misaligned";
+        case TRIG_EHIP: return "HIP runtime or kernel launch failure";
+        case TRIG_EUNSUPPORTED: return "unsupported test/flag combination";
+        default: return "unknown error code";
+    }
+}
+
+const char* trig_last_error_detail(void) { return g_detail.c_str(); }
+
+}  // extern "C"

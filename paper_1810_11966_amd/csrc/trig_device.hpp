@@ -1,0 +1,267 @@
+// Device-side building blocks of the trigger-station triplet selection:
+// per-plane test policies, per-event CSR loading and the wave-level triplet
+// loop shared by the plain and the persistent kernels.
+//
+// Method: paper Sec. 3.2 "Algorithm" - all one-hit-per-layer triplets (step
+// 1), straight-line fit through the vertex in x-z and y-z and a cut on its
+// mean square deviation per degree of freedom (step 2), event selected with at
+// least two passing triplets (step 3).  The binary32 operation order is the
+// one fixed in include/trig.h; this file must be compiled with
+// -ffp-contract=off and without flushing fp32 subnormals.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace trig {
+
+constexpr int kWave = 64;
+
+// Everything a kernel needs from the parameters, derived on the host.
+struct Consts {
+    // TRIG_TEST_MSD: orthonormal basis of the plane orthogonal to (z0, z1, z2)
+    float U0, U1, V0, V1, V2;
+    // TRIG_TEST_MSD_FIT: layer positions and w = 1 / sum z^2
+    float z0, z1, z2, w;
+    // MSD tests: largest binary32 Q with f32(Q / ndf) <= msd_max, per plane
+    float qmax_x, qmax_y;
+    // TRIG_TEST_SLOPE_WINDOW
+    float win_x, win_y;
+    int32_t min_triplets;
+    int32_t n_hits;
+};
+
+__device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ unsigned lane_id() { return threadIdx.x & (kWave - 1); }
+
+// Order this wave's LDS writes before its later LDS reads (and keep the
+// compiler from moving memory operations across).
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+}
+
+// Number of lanes of the wave with pred set (the lane mask goes straight to
+// scalar registers: one compare per predicate, popcount on the scalar unit).
+__device__ __forceinline__ uint32_t wave_popc(bool pred) {
+    return (uint32_t)__builtin_popcountll(__builtin_amdgcn_ballot_w64(pred));
+}
+
+__device__ __forceinline__ bool wave_any(bool pred) { return __builtin_amdgcn_ballot_w64(pred) != 0ull; }
+
+// Lane mask of a single comparison.  Combining two comparisons with a scalar
+// AND of their masks (rather than a ballot of `a & b`) keeps each predicate a
+// plain vector compare writing scalar registers.
+__device__ __forceinline__ uint64_t lanes(bool cmp) { return __builtin_amdgcn_ballot_w64(cmp); }
+
+// ----------------------------------------------------------------------------
+// Test policies.  HF = floats staged in LDS per layer-2 hit; Pair = the part
+// of the test that depends on (i, j) only; pass() completes it with hit k and
+// returns the mask of lanes whose triplet passes.
+// Staged padding and invalid pairs are NaN, which fails every comparison.
+// ----------------------------------------------------------------------------
+
+struct MsdTest {
+    static constexpr int HF = 2;
+    struct Pair {
+        float ax2, bx0, ay2, by0;
+    };
+    __device__ static __forceinline__ void stage(const Consts& c, float x, float y, float* h) {
+        h[0] = c.V2 * x;
+        h[1] = c.V2 * y;
+    }
+    __device__ static __forceinline__ void pad(float* h) {
+        h[0] = __builtin_nanf("");
+        h[1] = __builtin_nanf("");
+    }
+    __device__ static __forceinline__ Pair pair(const Consts& c, float xi, float yi, float xj,
+                                                float yj) {
+        Pair p;
+        const float ax = c.U0 * xi + c.U1 * xj;
+        const float ay = c.U0 * yi + c.U1 * yj;
+        p.ax2 = ax * ax;
+        p.ay2 = ay * ay;
+        p.bx0 = c.V0 * xi + c.V1 * xj;
+        p.by0 = c.V0 * yi + c.V1 * yj;
+        return p;
+    }
+    __device__ static __forceinline__ Pair invalid() {
+        const float n = __builtin_nanf("");
+        return Pair{n, n, n, n};
+    }
+    // Exact necessary condition: Q = f32(A + f32(b*b)) >= A = f32(a*a) since
+    // rounding is monotone, so a pair with A > Qmax in a plane has no passing k.
+    __device__ static __forceinline__ bool may_pass(const Consts& c, const Pair& p) {
+        return (p.ax2 <= c.qmax_x) & (p.ay2 <= c.qmax_y);
+    }
+    __device__ static __forceinline__ uint64_t pass(const Consts& c, const Pair& p, const float* h) {
+        const float bx = p.bx0 + h[0];
+        const float qx = p.ax2 + bx * bx;
+        const float by = p.by0 + h[1];
+        const float qy = p.ay2 + by * by;
+        return lanes(qx <= c.qmax_x) & lanes(qy <= c.qmax_y);
+    }
+};
+
+struct MsdFitTest {
+    static constexpr int HF = 4;
+    struct Pair {
+        float xi, xj, sx01, yi, yj, sy01;
+    };
+    __device__ static __forceinline__ void stage(const Consts& c, float x, float y, float* h) {
+        h[0] = x;
+        h[1] = y;
+        h[2] = x * c.z2;
+        h[3] = y * c.z2;
+    }
+    __device__ static __forceinline__ void pad(float* h) {
+        const float n = __builtin_nanf("");
+        h[0] = n; h[1] = n; h[2] = n; h[3] = n;
+    }
+    __device__ static __forceinline__ Pair pair(const Consts& c, float xi, float yi, float xj,
+                                                float yj) {
+        Pair p;
+        p.xi = xi; p.xj = xj; p.yi = yi; p.yj = yj;
+        p.sx01 = xi * c.z0 + xj * c.z1;
+        p.sy01 = yi * c.z0 + yj * c.z1;
+        return p;
+    }
+    __device__ static __forceinline__ Pair invalid() {
+        const float n = __builtin_nanf("");
+        return Pair{n, n, n, n, n, n};
+    }
+    __device__ static __forceinline__ bool may_pass(const Consts&, const Pair&) { return true; }
+    __device__ static __forceinline__ float plane_q(const Consts& c, float ci, float cj, float s01,
+                                                    float ck, float pk) {
+        const float m = (s01 + pk) * c.w;
+        const float r0 = ci - m * c.z0;
+        const float r1 = cj - m * c.z1;
+        const float r2 = ck - m * c.z2;
+        return (r0 * r0 + r1 * r1) + r2 * r2;
+    }
+    __device__ static __forceinline__ uint64_t pass(const Consts& c, const Pair& p, const float* h) {
+        const float qx = plane_q(c, p.xi, p.xj, p.sx01, h[0], h[2]);
+        const float qy = plane_q(c, p.yi, p.yj, p.sy01, h[1], h[3]);
+        return lanes(qx <= c.qmax_x) & lanes(qy <= c.qmax_y);
+    }
+};
+
+struct WindowTest {
+    static constexpr int HF = 2;
+    struct Pair {
+        float sxi, syi;  // NaN when the layer-1 window already fails
+    };
+    __device__ static __forceinline__ void stage(const Consts& c, float x, float y, float* h) {
+        h[0] = x / c.z2;
+        h[1] = y / c.z2;
+    }
+    __device__ static __forceinline__ void pad(float* h) {
+        h[0] = __builtin_nanf("");
+        h[1] = __builtin_nanf("");
+    }
+    __device__ static __forceinline__ Pair pair(const Consts& c, float xi, float yi, float xj,
+                                                float yj) {
+        const float sxi = xi / c.z0, syi = yi / c.z0;
+        const float sxj = xj / c.z1, syj = yj / c.z1;
+        const bool ok = (__builtin_fabsf(sxj - sxi) < c.win_x) & (__builtin_fabsf(syj - syi) < c.win_y);
+        const float n = __builtin_nanf("");
+        return Pair{ok ? sxi : n, ok ? syi : n};
+    }
+    __device__ static __forceinline__ Pair invalid() {
+        const float n = __builtin_nanf("");
+        return Pair{n, n};
+    }
+    __device__ static __forceinline__ bool may_pass(const Consts&, const Pair& p) {
+        return p.sxi == p.sxi;  // not NaN
+    }
+    __device__ static __forceinline__ uint64_t pass(const Consts& c, const Pair& p, const float* h) {
+        return lanes(__builtin_fabsf(h[0] - p.sxi) < c.win_x) & lanes(__builtin_fabsf(h[1] - p.syi) < c.win_y);
+    }
+};
+
+// ----------------------------------------------------------------------------
+// Events
+// ----------------------------------------------------------------------------
+
+struct EventRange {
+    int o0, o1, o2;
+    int n0, n1, n2;
+};
+
+// Reads and checks the CSR range of event e (wave-uniform).  Returns 0, or
+// the per-event error count (-1 malformed, -2 count not representable).
+__device__ __forceinline__ int load_event(const int32_t* __restrict__ off, int e, int n_hits,
+                                          EventRange& ev) {
+    const int64_t b = 3 * (int64_t)e;
+    const int a0 = uniform_i(off[b]), a1 = uniform_i(off[b + 1]);
+    const int a2 = uniform_i(off[b + 2]), a3 = uniform_i(off[b + 3]);
+    if (!(0 <= a0 && a0 <= a1 && a1 <= a2 && a2 <= a3 && a3 <= n_hits)) return -1;
+    ev.o0 = a0; ev.o1 = a1; ev.o2 = a2;
+    ev.n0 = a1 - a0; ev.n1 = a2 - a1; ev.n2 = a3 - a2;
+    if (ev.n2 > 0 && (int64_t)ev.n0 * ev.n1 > (int64_t)INT32_MAX / ev.n2) return -2;
+    return 0;
+}
+
+__device__ __forceinline__ uint32_t pair_tiles(const EventRange& ev) {
+    const uint64_t np = (uint64_t)ev.n0 * (uint64_t)ev.n1;
+    return (ev.n2 == 0) ? 0u : (uint32_t)((np + kWave - 1) / kWave);
+}
+
+// Passing triplets of one event over pair tiles [t_begin, t_end); each tile
+// is 64 consecutive (i, j) pairs in row-major order (pair p -> i = p / n1,
+// j = p % n1), one pair per lane, looping over every layer-2 hit staged in
+// this wave's LDS slice (KCH hits per chunk).  Called by a whole wave with
+// uniform arguments; returns the same count on every lane.
+template <class T, int KCH>
+__device__ uint32_t wave_count(const float* __restrict__ x, const float* __restrict__ y,
+                               const EventRange& ev, uint32_t t_begin, uint32_t t_end,
+                               const Consts& c, float* __restrict__ lds, bool prune) {
+    static_assert(KCH % 4 == 0, "chunk must hold whole float4 groups");
+    const unsigned lane = lane_id();
+    const uint32_t n0 = (uint32_t)ev.n0, n1 = (uint32_t)ev.n1;
+    const uint32_t dq = kWave / n1, dr = kWave % n1;
+    uint32_t cnt = 0;
+    for (int k0 = 0; k0 < ev.n2; k0 += KCH) {
+        const int nk = min(KCH, ev.n2 - k0);
+        const int nk_pad = (nk + 3) & ~3;
+        for (int t = (int)lane; t < nk_pad; t += kWave) {
+            float* h = lds + t * T::HF;
+            if (t < nk)
+                T::stage(c, x[ev.o2 + k0 + t], y[ev.o2 + k0 + t], h);
+            else
+                T::pad(h);
+        }
+        wave_lds_sync();
+        const uint32_t p0 = t_begin * (uint32_t)kWave + lane;
+        uint32_t i = p0 / n1, j = p0 - (p0 / n1) * n1;
+        for (uint32_t t = t_begin; t < t_end; ++t) {
+            typename T::Pair pr = T::invalid();
+            if (i < n0) pr = T::pair(c, x[ev.o0 + i], y[ev.o0 + i], x[ev.o1 + j], y[ev.o1 + j]);
+            const bool go = !prune || wave_any(T::may_pass(c, pr));
+            if (go) {
+                // nk_pad is a multiple of 4: four layer-2 hits per iteration
+                for (int k = 0; k < nk_pad; k += 4) {
+                    const float* h = lds + k * T::HF;
+                    const uint64_t m0 = T::pass(c, pr, h);
+                    const uint64_t m1 = T::pass(c, pr, h + T::HF);
+                    const uint64_t m2 = T::pass(c, pr, h + 2 * T::HF);
+                    const uint64_t m3 = T::pass(c, pr, h + 3 * T::HF);
+                    cnt += (uint32_t)(__builtin_popcountll(m0) + __builtin_popcountll(m1) +
+                                      __builtin_popcountll(m2) + __builtin_popcountll(m3));
+                }
+            }
+            j += dr;
+            i += dq;
+            if (j >= n1) {
+                j -= n1;
+                ++i;
+            }
+        }
+        wave_lds_sync();
+    }
+    return cnt;
+}
+
+}  // namespace trig

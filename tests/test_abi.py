@@ -1,0 +1,167 @@
+"""The C ABI library on the host: it loads, exports what include/trig.h
+declares, and rejects bad arguments before touching the GPU.  Also checks
+the gfx950 instructions of the MSD kernels (no fused multiply-add, no packed
+fp32, fp32 subnormals kept).  No test here needs a GPU."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from paper_1810_11966_amd import build, trig
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "trig.h")
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(trig.LIB_PATH):
+        build.build()
+    return trig.load()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(trig_[a-z_]+)\s*\(", src)))
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert set(names) == set(trig.EXPORTED)
+    for n in names:
+        assert hasattr(lib, n), n
+    out = subprocess.run(["nm", "-D", "--defined-only", trig.LIB_PATH], capture_output=True, text=True).stdout
+    for n in names:
+        assert re.search(rf"\bT {n}$", out, re.M), n
+
+
+def test_params_struct_layout_matches_header(lib, tmp_path):
+    """ctypes mirrors of the structs agree with a C compiler's layout."""
+    fields = [f for f, _ in trig.TrigParams._fields_]
+    src = ["#include <stdio.h>", "#include <stddef.h>", '#include "trig.h"', "int main(void) {",
+           'printf("%zu %zu %zu\\n", sizeof(trig_params), sizeof(trig_events_csr), sizeof(trig_hits));']
+    for f in fields:
+        src.append(f'printf("%zu\\n", offsetof(trig_params, {f}));')
+    src.append("return 0; }")
+    c = tmp_path / "layout.c"
+    c.write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    sizes = [int(v) for v in out[:3]]
+    assert sizes == [ctypes.sizeof(trig.TrigParams), ctypes.sizeof(trig.TrigEventsCsr),
+                     ctypes.sizeof(trig.TrigHits)]
+    for f, off in zip(fields, out[3:]):
+        assert getattr(trig.TrigParams, f).offset == int(off), f
+
+
+def test_params_defaults(lib):
+    p = trig.trig_params_init()
+    assert p.abi_version == trig.TRIG_ABI_VERSION and p.test == trig.TRIG_TEST_MSD
+    assert list(p.z) == [400.0, 410.0, 420.0]
+    assert abs(p.msd_max[0] - 0.03) < 1e-9 and abs(p.msd_max[1] - 0.025) < 1e-9
+    assert p.ndf == 2 and p.min_triplets == 2 and p.flags == 0
+
+
+def test_workspace_sizes(lib):
+    p = trig.make_params()
+    assert trig.trig_workspace_bytes(1000, p) == 0
+    p.flags = trig.TRIG_OUT_COMPACT
+    assert trig.trig_workspace_bytes(1000, p) > 0
+    p.flags = trig.TRIG_EXEC_PERSISTENT
+    ws = trig.trig_workspace_bytes(10 ** 6, p)
+    assert ws >= 8 * 10 ** 6 and ws % 256 == 0
+
+
+def _call(p, n_events=4, n_hits=12, offsets=0x1000, x=0x2000, y=0x3000, counts=0x4000, accept=0x5000):
+    ev = trig.TrigEventsCsr(n_events, offsets)
+    hits = trig.TrigHits(n_hits, x, y)
+    return trig.trig_select(ev, hits, p, counts, accept, 0)
+
+
+@pytest.mark.parametrize("mutate,code", [
+    (lambda p: setattr(p, "abi_version", 2), trig.TRIG_EINVAL),
+    (lambda p: setattr(p, "test", 7), trig.TRIG_EINVAL),
+    (lambda p: p.z.__setitem__(1, 0.0), trig.TRIG_EINVAL),
+    (lambda p: p.z.__setitem__(2, float("inf")), trig.TRIG_EINVAL),
+    (lambda p: p.msd_max.__setitem__(0, -1.0), trig.TRIG_EINVAL),
+    (lambda p: p.msd_max.__setitem__(1, float("nan")), trig.TRIG_EINVAL),
+    (lambda p: p.slope_window.__setitem__(0, -0.1), trig.TRIG_EINVAL),
+    (lambda p: setattr(p, "ndf", 0), trig.TRIG_EINVAL),
+    (lambda p: setattr(p, "min_triplets", -1), trig.TRIG_EINVAL),
+    (lambda p: setattr(p, "tile_pairs", 65), trig.TRIG_EINVAL),
+    (lambda p: p.reserved.__setitem__(3, 1), trig.TRIG_EINVAL),
+    (lambda p: setattr(p, "flags", 1 << 20), trig.TRIG_EINVAL),
+    (lambda p: setattr(p, "flags", trig.TRIG_OUT_COMPACT), trig.TRIG_EINVAL),  # no id buffers
+    (lambda p: setattr(p, "flags", trig.TRIG_EXEC_PERSISTENT), trig.TRIG_EWORKSPACE),
+    (lambda p: (setattr(p, "test", trig.TRIG_TEST_MSD_FIT), setattr(p, "flags", trig.TRIG_EXEC_PRUNED)),
+     trig.TRIG_EUNSUPPORTED),
+])
+def test_rejects_bad_params_before_any_launch(lib, mutate, code):
+    p = trig.make_params()
+    mutate(p)
+    assert _call(p) == code
+    assert trig.trig_last_error_detail() != ""
+
+
+def test_rejects_null_and_negative_sizes(lib):
+    p = trig.make_params()
+    assert _call(p, n_events=-1) == trig.TRIG_EINVAL
+    assert _call(p, n_hits=-1) == trig.TRIG_EINVAL
+    assert _call(p, offsets=0) == trig.TRIG_EINVAL
+    assert _call(p, x=0) == trig.TRIG_EINVAL
+    assert _call(p, counts=0) == trig.TRIG_EINVAL
+    assert lib.trig_select(None, None, None, None, None, None) == trig.TRIG_EINVAL
+    p.flags = trig.TRIG_EXEC_PERSISTENT
+    p.workspace = 0x10010  # misaligned
+    p.workspace_bytes = 1 << 30
+    assert _call(p) == trig.TRIG_EWORKSPACE
+
+
+def test_strerror_and_event_hook(lib):
+    for code in (0, -1, -2, -3, -4):
+        assert trig.trig_strerror(code)
+    assert trig.trig_strerror(-99) == "unknown error code"
+    assert trig.trig_set_kernel_events(0x10, 0) == trig.TRIG_EINVAL
+    assert trig.trig_set_kernel_events(0, 0) == trig.TRIG_OK
+
+
+# ------------------------------------------------------------------- ISA ---
+
+@pytest.fixture(scope="module")
+def isa():
+    return open(build.build_isa()).read()
+
+
+def kernel_bodies(isa_text):
+    bodies, name, cur = {}, None, []
+    for line in isa_text.splitlines():
+        m = re.match(r"^(_Z\w+):", line)
+        if m:
+            if name:
+                bodies[name] = "\n".join(cur)
+            name, cur = m.group(1), []
+        elif name:
+            cur.append(line)
+            if line.strip().startswith(".Lfunc_end"):
+                bodies[name] = "\n".join(cur)
+                name = None
+    return bodies
+
+
+def test_msd_kernels_have_no_fma_or_packed_fp32(isa):
+    bodies = kernel_bodies(isa)
+    msd = {k: v for k, v in bodies.items() if "MsdTest" in k or "MsdFitTest" in k}
+    assert len(msd) >= 4
+    for name, body in msd.items():
+        bad = re.findall(r"\b(v_fma\w*|v_fmac\w*|v_mac_f32\w*|v_mad_f32\w*|v_mad_legacy\w*|"
+                         r"v_pk_(?:add|mul|fma)_f32\w*)", body)
+        assert not bad, (name, bad[:5])
+
+
+def test_fp32_subnormals_enabled(isa):
+    modes = re.findall(r"\.amdhsa_float_denorm_mode_32\s+(\d+)", isa)
+    assert modes and all(m == "3" for m in modes)

@@ -1,0 +1,248 @@
+"""GPU parity: the HIP library (through the C ABI) against the CPU oracle,
+element by element, bit-exact for counts, accept flags and accepted ids.
+
+Every case prints its name before it touches the GPU."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import reference as R
+from paper_1810_11966_amd import synth
+from tests import helpers
+
+pytestmark = pytest.mark.gpu
+
+TESTS = ("msd", "msd_fit", "window")
+FORMS = ("plain", "pruned", "persistent", "persistent_pruned")
+
+
+def forms_for(test):
+    return [f for f in FORMS if not (test == "msd_fit" and "pruned" in f)]
+
+
+@pytest.fixture(scope="module")
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1810_11966_amd import trig
+    trig.load()
+    return torch
+
+
+def to_dev(torch, s):
+    d = torch.device("cuda:0")
+    return (torch.from_numpy(np.ascontiguousarray(s.offsets)).to(d),
+            torch.from_numpy(np.ascontiguousarray(s.x)).to(d),
+            torch.from_numpy(np.ascontiguousarray(s.y)).to(d))
+
+
+def run_gpu(torch, s, test="msd", form="plain", compact=True, **kw):
+    from paper_1810_11966_amd import trig
+    off, x, y = to_dev(torch, s)
+    r = trig.select(off, x, y, test=test, form=form, compact=compact, want_status=True, **kw)
+    torch.cuda.synchronize()
+    out = {"counts": r.counts.cpu().numpy(), "accept": r.accept.cpu().numpy(),
+           "status": int(r.status.cpu().numpy()[0]) & 0xFFFFFFFF}
+    if compact:
+        n = int(r.n_accepted.cpu().numpy()[0])
+        out["ids"] = r.ids.cpu().numpy()[:n]
+    return out
+
+
+def oracle_cfg(test, **kw):
+    okw = {}
+    for k_gpu, k_or in (("z", "z"), ("msd_max", "msd_max"), ("ndf", "ndf"),
+                        ("slope_window", "window"), ("min_triplets", "min_triplets")):
+        if k_gpu in kw:
+            okw[k_or] = tuple(kw[k_gpu]) if isinstance(kw[k_gpu], (list, tuple)) else kw[k_gpu]
+    return R.OracleConfig(test=test, **okw)
+
+
+_ORACLE_CACHE = {}
+THREADS = max(1, min(16, len(os.sched_getaffinity(0))))
+
+
+def oracle_result(s, cfg):
+    key = (s.sha256(), cfg)
+    if key not in _ORACLE_CACHE:
+        _ORACLE_CACHE[key] = R.select_set(s, cfg, n_threads=THREADS)
+    return _ORACLE_CACHE[key]
+
+
+def assert_parity(torch, s, test, form, label, **kw):
+    print(f"[parity] {label} test={test} form={form} events={s.n_events} hits={s.n_hits}", flush=True)
+    got = run_gpu(torch, s, test, form, **kw)
+    c, a, st, _ = oracle_result(s, oracle_cfg(test, **kw))
+    bad = np.flatnonzero(got["counts"] != c)
+    assert bad.size == 0, f"{label}: {bad.size} events differ, first {bad[:5]} gpu {got['counts'][bad[:5]]} cpu {c[bad[:5]]}"
+    assert np.array_equal(got["accept"], a), label
+    assert np.array_equal(got["ids"], R.accepted_ids(a)), label
+    assert got["status"] == st, label
+    return c
+
+
+# ------------------------------------------------------------ hand-built ---
+
+@pytest.mark.parametrize("form", FORMS)
+def test_golden_cases(gpu, form):
+    for case in helpers.golden_cases():
+        s = helpers.golden_set(case)
+        cfg = dict(case.get("cfg", {}))
+        test = cfg.pop("test", "msd")
+        kw = {}
+        if "msd_max" in cfg:
+            kw["msd_max"] = cfg["msd_max"]
+        if "ndf" in cfg:
+            kw["ndf"] = cfg["ndf"]
+        if "window" in cfg:
+            kw["slope_window"] = cfg["window"]
+        for t in ([test] if test == "window" else ["msd", "msd_fit"]):
+            if t == "msd_fit" and "pruned" in form:
+                continue
+            print(f"[golden] {case['name']} {t} {form}", flush=True)
+            got = run_gpu(gpu, s, t, form, **kw)
+            assert got["counts"][0] == case["expected_count"], (case["name"], t, form)
+
+
+# -------------------------------------------------------------- workloads ---
+
+@pytest.mark.parametrize("test", TESTS)
+def test_small_10k_all_forms(gpu, test):
+    s = synth.make_event_set(synth.SMALL_10K)
+    for form in forms_for(test):
+        assert_parity(gpu, s, test, form, "small_10k")
+
+
+@pytest.mark.parametrize("test", TESTS)
+def test_near_threshold_stress(gpu, test):
+    s = synth.concat([helpers.near_threshold_events(300, 8, seed=3, rel=1e-4),
+                      helpers.near_threshold_events(100, 20, seed=4, rel=1e-6)])
+    for form in forms_for(test):
+        c = assert_parity(gpu, s, test, form, "near_threshold")
+    assert c.sum() > 0
+
+
+def test_near_threshold_other_ndf_and_thresholds(gpu):
+    s = helpers.near_threshold_events(200, 8, seed=9, rel=1e-4)
+    for kw in ({"ndf": 3}, {"ndf": 1}, {"ndf": 7, "msd_max": (0.0085714, 0.0071428)},
+               {"msd_max": (0.0300001, 0.0249999)}, {"min_triplets": 0}, {"min_triplets": 5}):
+        for form in ("plain", "persistent_pruned"):
+            assert_parity(gpu, s, "msd", form, f"ndf/threshold {kw}", **kw)
+        assert_parity(gpu, s, "msd_fit", "persistent", f"ndf/threshold {kw}", **kw)
+
+
+def test_other_geometry(gpu):
+    s = synth.make_event_set(synth.EventSetSpec(n_events=3000, hits_mean=10, p_inject=0.3,
+                                                sigma=0.05, z=(100.0, 300.0, 1000.0), salt=77))
+    for test in TESTS:
+        for form in forms_for(test):
+            assert_parity(gpu, s, test, form, "geometry z=100/300/1000", z=(100.0, 300.0, 1000.0),
+                          slope_window=(0.002, 0.003))
+
+
+def test_ragged_layer_sizes(gpu):
+    sizes = []
+    for n in (0, 1, 2, 3, 31, 63, 64, 65, 127, 128, 129):
+        sizes += [(n, 5, 7), (5, n, 7), (5, 7, n), (n, n, 3)]
+    sizes += [(1, 1, 1), (64, 1, 64), (1, 64, 65), (9, 7, 513), (3, 2, 1025), (2, 3, 600)]
+    s = helpers.ragged_sizes_set(sizes, seed=1)
+    for test in TESTS:
+        for form in forms_for(test):
+            assert_parity(gpu, s, test, form, "ragged")
+            for tp in (64, 128, 1024):
+                if "persistent" in form:
+                    assert_parity(gpu, s, test, form, f"ragged tile_pairs={tp}", tile_pairs=tp)
+
+
+def test_dense_and_mixture_samples(gpu):
+    dense = synth.make_event_set(synth.DENSE_100K, n_events=400)
+    mix = synth.make_event_set(synth.MIXTURE_4M, n_events=4000)
+    for s, label in ((dense, "dense_100k[:400]"), (mix, "mixture_4m[:4000]")):
+        for form in ("plain", "pruned", "persistent_pruned"):
+            assert_parity(gpu, s, "msd", form, label)
+        assert_parity(gpu, s, "window", "persistent", label)
+
+
+def test_injected_exact_tracks_accept(gpu):
+    """sigma = 0 pairs: every injected event is accepted (exercises accept and
+    compaction with many accepted events)."""
+    s = synth.make_event_set(synth.EventSetSpec(n_events=20000, hits_mean=8, p_inject=0.3, sigma=0.0,
+                                                salt=55))
+    for form in FORMS:
+        c = assert_parity(gpu, s, "msd", form, "exact pairs")
+    assert (c[s.n_tracks > 0] >= 2).all()
+
+
+# ------------------------------------------------------------ error paths ---
+
+def test_malformed_and_overflow_events(gpu):
+    good = synth.make_event_set(synth.SMALL_10K, n_events=50)
+    off = good.offsets.copy()
+    off[3 * 10 + 1] = off[3 * 10 + 2] + 1      # event 10: layer 0 end past layer 1 end
+    off[3 * 20 + 3] = good.n_hits + 5           # event 20 (and 21 start): beyond n_hits
+    bad = synth.EventSet(off, good.x, good.y, good.n_tracks)
+    for test in TESTS:
+        for form in forms_for(test):
+            assert_parity(gpu, bad, test, form, "malformed")
+    n = 1291
+    big = synth.EventSet(np.array([0, n, 2 * n, 3 * n, 3 * n + 1, 3 * n + 2, 3 * n + 3], np.int32),
+                         np.zeros(3 * n + 3, np.float32), np.zeros(3 * n + 3, np.float32),
+                         np.zeros(2, np.int8))
+    for form in FORMS:
+        got = run_gpu(gpu, big, "msd", form)
+        assert got["counts"][0] == -2 and got["accept"][0] == 0 and got["status"] == 2
+        assert got["counts"][1] == 1 and list(got["ids"]) == []
+
+
+def test_empty_batch(gpu):
+    from paper_1810_11966_amd import trig
+    s = synth.EventSet(np.zeros(1, np.int32), np.zeros(0, np.float32), np.zeros(0, np.float32),
+                       np.zeros(0, np.int8))
+    torch = gpu
+    off = torch.zeros(1, dtype=torch.int32, device="cuda")
+    x = torch.zeros(0, dtype=torch.float32, device="cuda")
+    for form in FORMS:
+        r = trig.select(off, x, x, form=form, compact=True)
+        torch.cuda.synchronize()
+        assert int(r.n_accepted.cpu()[0]) == 0 and r.counts.numel() == 0
+
+
+# ------------------------------------------------ determinism / composition ---
+
+def test_repeatable_and_batch_composition(gpu):
+    s = synth.make_event_set(synth.MIXTURE_4M, n_events=6000)
+    base = run_gpu(gpu, s, "msd", "persistent")["counts"]
+    for _ in range(3):
+        assert np.array_equal(run_gpu(gpu, s, "msd", "persistent")["counts"], base)
+    parts = [s.subset(0, 1000), s.subset(1000, 3000), s.subset(4000, 2000)]
+    got = np.concatenate([run_gpu(gpu, p, "msd", "plain")["counts"] for p in parts])
+    assert np.array_equal(got, base)
+
+
+# ----------------------------------------------------------- full sizes ---
+
+def test_medium_1m_full_size_sampled(gpu):
+    """The 1M-event workload at full size in the benchmark's launch
+    configuration: every form agrees with every other on all events, and the
+    oracle checks a sample of 20k events (three ranges) one by one."""
+    s = synth.make_event_set(synth.MEDIUM_1M)
+    print("[full] medium_1m generated", flush=True)
+    results = {}
+    for form in FORMS:
+        print(f"[full] medium_1m form={form}", flush=True)
+        results[form] = run_gpu(gpu, s, "msd", form)
+    base = results["plain"]
+    for form, r in results.items():
+        assert np.array_equal(r["counts"], base["counts"]), form
+        assert np.array_equal(r["ids"], np.flatnonzero(base["accept"])), form
+    for first in (0, 500_000, s.n_events - 7000):
+        sub = s.subset(first, 7000 if first else 6000)
+        c, a, st, _ = R.select_set(sub, n_threads=THREADS)
+        assert np.array_equal(base["counts"][first:first + sub.n_events], c), first
+    # the window test accepts the injected pairs
+    w = run_gpu(gpu, s, "window", "persistent_pruned")
+    sub = s.subset(0, 6000)
+    c, _, _, _ = R.select_set(sub, R.OracleConfig(test="window"), n_threads=THREADS)
+    assert np.array_equal(w["counts"][:6000], c)
