@@ -27,10 +27,12 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published peaks and the derived fp32 VALU peak (256 CUs x 4 SIMD x
-# 16 lanes x 2.4 GHz, one non-fused, non-packed fp32 op per lane per clock).
+# MI355X published HBM peak, and the fp32 vector-ALU op peak derived from the
+# unit counts: 256 CUs x 128 fp32 lanes per clock (the rate behind the
+# published 157.3 TFLOP/s, which counts an FMA as two) x 2.4 GHz, one
+# non-fused, non-packed fp32 operation per lane per clock.
 HBM_PEAK_GBS = 8000.0
-VALU_F32_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12  # 39.32
+VALU_F32_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12  # 78.64
 OPS_PER_TRIPLET = {"msd": 8, "msd_fit": 28, "window": 4}
 
 WORKLOAD_TEXT = {
@@ -55,7 +57,9 @@ def parse():
     ap.add_argument("--workload", default="medium_1m", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--test", default="msd", choices=["msd", "msd_fit", "window"])
     ap.add_argument("--form", default="persistent_pruned")
-    ap.add_argument("--plain-steps", type=int, default=5, help="timed steps of the plain form")
+    ap.add_argument("--compare", default="plain,pruned,persistent",
+                    help="other forms timed on the same input (comma separated)")
+    ap.add_argument("--compare-steps", type=int, default=5, help="timed steps of each compared form")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target wall time of the CPU-oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -75,7 +79,8 @@ def algorithmic(sets_counts, n_events):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for p in ("paper_1810_11966_amd/csrc/trig.hip", "paper_1810_11966_amd/csrc/trig_device.hpp"):
+    for p in ("paper_1810_11966_amd/csrc/trig.hip", "paper_1810_11966_amd/csrc/trig_device.hpp",
+              "paper_1810_11966_amd/csrc/trig_block.hpp"):
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -198,7 +203,8 @@ def main():
     # 8 B per hit, 4 B count per event (plain kernel: +1 B flag)
     kern_bytes = 12 * n_ev + 8 * hits + 4 * n_ev
     kern_s = main_r["kernel_ms_mean"] / 1e3
-    dominant = "k_persistent" if "persistent" in args.form else "k_plain"
+    dominant = ("k_block" if "pruned" in args.form else
+                "k_persistent" if "persistent" in args.form else "k_plain")
     traffic = load_traffic(dominant, args.workload, args.form)
     roofline = {"kernel": dominant, "bound": "hbm", "achieved": kern_bytes / kern_s / 1e9,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -207,26 +213,29 @@ def main():
 
     extra = {}
     plain_info = None
-    if not args.only_form and args.form != "plain":
-        log(f"[bench] timing form=plain steps={args.plain_steps}")
-        pr = time_form(torch, trig, hip_events, dev_in, n_ev, "plain", args.test, args.plain_steps, 1)
-        same = bool(torch.equal(pr["counts"], main_r["counts"]) and torch.equal(pr["ids"], main_r["ids"]))
+    forms = {}
+    compare = [f for f in args.compare.split(",") if f and f != args.form] if not args.only_form else []
+    for form in compare:
+        log(f"[bench] timing form={form} steps={args.compare_steps}")
+        r = time_form(torch, trig, hip_events, dev_in, n_ev, form, args.test, args.compare_steps, 1)
+        same = bool(torch.equal(r["counts"], main_r["counts"]) and torch.equal(r["ids"], main_r["ids"]))
         if not same:
-            print("bench.py: plain and batched forms disagree", file=sys.stderr)
+            print(f"bench.py: form {form} and form {args.form} disagree", file=sys.stderr)
             sys.exit(1)
-        pk_s = pr["kernel_ms_mean"] / 1e3
-        ops = OPS_PER_TRIPLET[args.test] * triplets
-        plain_info = {
-            "events_per_s": n_ev * args.plain_steps / pr["elapsed_s"],
-            "ms_per_step": 1e3 * pr["elapsed_s"] / args.plain_steps,
-            "kernel_ms": pr["kernel_ms_mean"],
-            "roofline": {"kernel": "k_plain", "bound": "alu", "achieved": ops / pk_s / 1e12,
-                         "peak": VALU_F32_PEAK_TOPS, "unit": "TFLOP/s",
-                         "frac": ops / pk_s / 1e12 / VALU_F32_PEAK_TOPS,
-                         "traffic": load_traffic("k_plain", args.workload, "plain"),
-                         "ops_per_triplet": OPS_PER_TRIPLET[args.test]},
-            "counts_identical": same,
-        }
+        forms[form] = {"events_per_s": n_ev * args.compare_steps / r["elapsed_s"],
+                       "ms_per_step": 1e3 * r["elapsed_s"] / args.compare_steps,
+                       "kernel_ms": r["kernel_ms_mean"], "counts_identical": same}
+        log(f"[bench] {form}: {forms[form]['ms_per_step']:.3f} ms/step, kernel {r['kernel_ms_mean']:.3f} ms")
+        if form == "plain":
+            pk_s = r["kernel_ms_mean"] / 1e3
+            ops = OPS_PER_TRIPLET[args.test] * triplets
+            plain_info = dict(forms[form])
+            plain_info["roofline"] = {"kernel": "k_plain", "bound": "alu", "achieved": ops / pk_s / 1e12,
+                                      "peak": VALU_F32_PEAK_TOPS, "unit": "TFLOP/s",
+                                      "frac": ops / pk_s / 1e12 / VALU_F32_PEAK_TOPS,
+                                      "traffic": load_traffic("k_plain", args.workload, "plain"),
+                                      "ops_per_triplet": OPS_PER_TRIPLET[args.test]}
+    if plain_info:
         extra["batched_vs_plain"] = value / plain_info["events_per_s"]
 
     cpu = None
@@ -259,6 +268,7 @@ def main():
         "triplet_tests_per_s_effective": triplets * args.steps / main_r["elapsed_s"],
         "n_accepted": main_r["n_accepted"],
         "plain": plain_info,
+        "forms": forms,
         "p99_slice_latency_ms": None,
         **extra,
     }

@@ -109,13 +109,18 @@ enum {
  * counts and flags bit for bit. */
 enum {
     TRIG_EXEC_PLAIN = 0u,       /* one wave per event, every triplet tested */
-    TRIG_EXEC_PERSISTENT = 1u,  /* one persistent launch; waves steal (event,
-                                   pair-range) work units from a global counter;
-                                   needs workspace */
-    TRIG_EXEC_PRUNED = 2u,      /* skip 64-pair tiles whose pairs provably cannot
-                                   pass (MSD: f32(a*a) > Qmax in a plane, since
-                                   Q >= a*a in binary32; window: the layer-1
-                                   window fails); not for TRIG_TEST_MSD_FIT */
+    TRIG_EXEC_PERSISTENT = 1u,  /* one persistent launch; alone: waves steal
+                                   (event, pair-range) work units of the
+                                   every-triplet loop from a global counter;
+                                   with TRIG_EXEC_PRUNED: workgroups steal event
+                                   blocks.  Needs workspace */
+    TRIG_EXEC_PRUNED = 2u,      /* batched form: workgroups stage blocks of
+                                   consecutive events in LDS and complete only
+                                   pairs that provably can pass (MSD: a pair
+                                   with f32(a*a) > Qmax in a plane has Q > Qmax
+                                   for every k in binary32; window: the layer-1
+                                   window is part of the test); same counts.
+                                   Not for TRIG_TEST_MSD_FIT */
     TRIG_EXEC_BINNED = 4u,      /* slope-cell binning of layer-1 hits so that
                                    only candidate pairs are formed; MSD and
                                    window tests */
@@ -148,9 +153,13 @@ typedef struct {
     int32_t *out_n_accepted;    /* TRIG_OUT_COMPACT: device int32[1] */
     uint32_t *out_status;       /* optional device word; error bits are OR-ed
                                    in (never cleared by the library) */
-    int32_t tile_pairs;         /* persistent form: pairs per work unit
-                                   (multiple of 64; 0 = library default) */
-    int32_t reserved[7];        /* must be zero */
+    int32_t tile_pairs;         /* TRIG_EXEC_PERSISTENT without pruning: pairs
+                                   per work unit (multiple of 64; 0 = library
+                                   default) */
+    int32_t block_events;       /* TRIG_EXEC_PRUNED: events per workgroup block
+                                   (1..256; 0 = chosen from the mean number of
+                                   hits per event) */
+    int32_t reserved[6];        /* must be zero */
 } trig_params;
 
 /* Fill *p (host) with the defaults above.  Returns TRIG_OK or TRIG_EINVAL for
@@ -173,8 +182,8 @@ size_t trig_workspace_bytes(const trig_events_csr *ev, const trig_params *p);
  * Errors (returned before anything is enqueued): TRIG_EINVAL for a NULL
  * required pointer, n_events < 0, n_hits < 0, an ABI mismatch, non-finite or
  * non-positive z, a negative or NaN threshold or window, ndf < 1,
- * min_triplets < 0, tile_pairs not a non-negative multiple of 64, non-zero
- * reserved fields; TRIG_EWORKSPACE; TRIG_EUNSUPPORTED.  TRIG_EHIP if a launch
+ * min_triplets < 0, tile_pairs not a non-negative multiple of 64,
+ * block_events outside 0..256, non-zero reserved fields; TRIG_EWORKSPACE; TRIG_EUNSUPPORTED.  TRIG_EHIP if a launch
  * fails.  n_events == 0 enqueues only the compaction count (0), if requested.
  * Data-dependent problems are reported per event (see TRIG_COUNT_*) without a
  * host synchronisation.  Concurrent calls on different streams need distinct

@@ -22,8 +22,9 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libtrig.so")
 ISA = os.path.join(ROOT, "_build", "trig-gfx950.s")
-SOURCES = [os.path.join(CSRC, "trig.hip")]
-HEADERS = [os.path.join(CSRC, "trig_device.hpp"), os.path.join(INCLUDE, "trig.h")]
+SOURCES = [os.path.join(CSRC, "trig.hip"), os.path.join(CSRC, "probe.hip")]
+HEADERS = [os.path.join(CSRC, "trig_device.hpp"), os.path.join(INCLUDE, "trig.h"),
+           os.path.join(INCLUDE, "trig_probe.h")]
 ARCH = "gfx950"
 
 COMMON = ["-std=c++17", "-O3", f"--offload-arch={ARCH}", "-ffp-contract=off",

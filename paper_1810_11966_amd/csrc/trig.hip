@@ -14,6 +14,8 @@
 //   k_persistent   persistent grid; waves take batches of work units from one
 //                  global counter and add their counts with integer atomics
 //   k_finalize     accept flags from the accumulated counts
+//   k_block        batched form: blocks of events staged in LDS, exact pair
+//                  pruning (trig_block.hpp); optionally persistent
 //   k_compact_*    ordered list of accepted event ids
 #include <hip/hip_runtime.h>
 
@@ -25,6 +27,7 @@
 #include <string>
 
 #include "trig.h"
+#include "trig_block.hpp"
 #include "trig_device.hpp"
 
 using namespace trig;
@@ -39,6 +42,8 @@ constexpr int kCompactItems = 4;    // events per thread in compaction
 constexpr int kPersistWaves = 4;    // waves per workgroup, persistent form
 constexpr int kPersistBatch = 4;    // work units taken per atomic
 constexpr int kDefaultTileUnits = 8;  // pair tiles (of 64 pairs) per work unit
+constexpr int kBlockHits = 4096;      // LDS hit capacity of a batched-form workgroup
+constexpr int kBlockResident = 3;     // batched workgroups per CU (LDS-limited)
 
 template <class T>
 struct Chunk;
@@ -65,7 +70,7 @@ __global__ __launch_bounds__(WPB * kWave) void k_plain(const int32_t* __restrict
                                                        const float* __restrict__ y, Consts c,
                                                        int32_t* __restrict__ counts,
                                                        uint8_t* __restrict__ accept,
-                                                       uint32_t* status, int prune) {
+                                                       uint32_t* status) {
     constexpr int KCH = Chunk<T>::value;
     __shared__ __align__(16) float lds_all[WPB][KCH * T::HF];
     const int w = uniform_i(threadIdx.x / kWave);
@@ -75,7 +80,7 @@ __global__ __launch_bounds__(WPB * kWave) void k_plain(const int32_t* __restrict
     int32_t cnt = load_event(off, e, c.n_hits, ev);
     if (cnt == 0) {
         const uint32_t tiles = pair_tiles(ev);
-        if (tiles) cnt = (int32_t)wave_count<T, KCH>(x, y, ev, 0, tiles, c, lds_all[w], prune != 0);
+        if (tiles) cnt = (int32_t)wave_count<T, KCH>(x, y, ev, 0, tiles, c, lds_all[w]);
     }
     if (lane_id() == 0) write_result(e, cnt, c, counts, accept, status);
 }
@@ -244,7 +249,7 @@ template <class T, int WPB>
 __global__ __launch_bounds__(WPB * kWave) void k_persistent(
     const int32_t* __restrict__ off, int n_events, const float* __restrict__ x,
     const float* __restrict__ y, Consts c, const int64_t* __restrict__ ustart, int tile_units,
-    unsigned long long* counter, int32_t* counts, int prune) {
+    unsigned long long* counter, int32_t* counts) {
     constexpr int KCH = Chunk<T>::value;
     __shared__ __align__(16) float lds_all[WPB][KCH * T::HF];
     const int w = uniform_i(threadIdx.x / kWave);
@@ -264,7 +269,7 @@ __global__ __launch_bounds__(WPB * kWave) void k_persistent(
             const uint32_t tiles = pair_tiles(ev);
             const uint32_t tb = (uint32_t)((u - ustart[e]) * tile_units);
             const uint32_t te = min(tiles, tb + (uint32_t)tile_units);
-            const uint32_t cnt = wave_count<T, KCH>(x, y, ev, tb, te, c, lds, prune != 0);
+            const uint32_t cnt = wave_count<T, KCH>(x, y, ev, tb, te, c, lds);
             if (lane_id() == 0 && cnt) atomicAdd(&counts[e], (int32_t)cnt);
         }
     }
@@ -304,19 +309,47 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+uint32_t bits_of(float f) {
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    return u;
+}
+float float_of(uint32_t u) {
+    float f;
+    std::memcpy(&f, &u, 4);
+    return f;
+}
+
+// Largest non-negative binary32 v (bit pattern search over [0, +inf]) with
+// pred(v) true, for pred non-increasing in v and pred(0) true.
+template <class Pred>
+float largest_with(Pred pred) {
+    uint32_t lo = 0u, hi = 0x7f800000u;  // pred(lo) true
+    if (pred(float_of(hi))) return float_of(hi);
+    while (hi - lo > 1u) {  // pred(hi) false
+        const uint32_t mid = lo + (hi - lo) / 2u;
+        if (pred(float_of(mid))) lo = mid; else hi = mid;
+    }
+    return float_of(lo);
+}
+
 // Largest binary32 q with f32(q / ndf) <= t.  f32(q / ndf) is non-decreasing
-// in q, so {q : f32(q / ndf) <= t} is exactly {q <= Qmax}.
+// in q, so {q >= 0 : f32(q / ndf) <= t} is exactly {0 <= q <= Qmax}.
 float fold_threshold(float t, int ndf) {
     const float n = (float)ndf;
-    if (std::isinf(t)) return t;
-    volatile float q = t * n;
-    while (!((float)(q / n) <= t)) q = std::nextafter((float)q, -INFINITY);
-    for (;;) {
-        const float up = std::nextafter((float)q, INFINITY);
-        if (std::isinf(up) || !((float)(up / n) <= t)) break;
-        q = up;
-    }
-    return q;
+    return largest_with([&](float q) {
+        volatile float d = q / n;
+        return (float)d <= t;
+    });
+}
+
+// Largest binary32 b >= 0 with f32(b * b) <= qmax (f32(b * b) is
+// non-decreasing in b >= 0).
+float pair_bound(float qmax) {
+    return largest_with([&](float b) {
+        volatile float sq = b * b;
+        return (float)sq <= qmax;
+    });
 }
 
 Consts make_consts(const trig_params* p, int n_hits) {
@@ -337,6 +370,8 @@ Consts make_consts(const trig_params* p, int n_hits) {
     c.w = (float)(1.0 / (double)szz);
     c.qmax_x = fold_threshold(p->msd_max[0], p->ndf);
     c.qmax_y = fold_threshold(p->msd_max[1], p->ndf);
+    c.beta_x = pair_bound(c.qmax_x);
+    c.beta_y = pair_bound(c.qmax_y);
     c.win_x = p->slope_window[0];
     c.win_y = p->slope_window[1];
     c.min_triplets = p->min_triplets;
@@ -363,6 +398,7 @@ int validate(const trig_events_csr* ev, const trig_hits* hits, const trig_params
     if (p->ndf < 1) return fail(TRIG_EINVAL, "ndf < 1");
     if (p->min_triplets < 0) return fail(TRIG_EINVAL, "min_triplets < 0");
     if (p->tile_pairs < 0 || p->tile_pairs % kWave) return fail(TRIG_EINVAL, "tile_pairs not a multiple of 64");
+    if (p->block_events < 0 || p->block_events > kMaxEB) return fail(TRIG_EINVAL, "block_events outside 0..256");
     for (int r : p->reserved)
         if (r) return fail(TRIG_EINVAL, "reserved fields must be zero");
     const uint32_t known = TRIG_EXEC_PERSISTENT | TRIG_EXEC_PRUNED | TRIG_EXEC_BINNED |
@@ -390,7 +426,10 @@ Layout layout(int n_events, uint32_t flags) {
         L.compact_off = at;
         at += align256(sizeof(int32_t) * (size_t)(L.compact_blocks + 1));
     }
-    if (flags & TRIG_EXEC_PERSISTENT) {
+    if ((flags & TRIG_EXEC_PERSISTENT) && (flags & TRIG_EXEC_PRUNED)) {
+        L.counter_off = at;  // block counter only
+        at += 256;
+    } else if (flags & TRIG_EXEC_PERSISTENT) {
         L.unit_blocks = (int)std::max<int64_t>(1, cdiv(n_events, kScanBlock));
         L.counter_off = at;
         at += 256;
@@ -424,22 +463,22 @@ int device_cus() {
 }
 
 template <class T>
-int launch_plain(const trig_events_csr* ev, const trig_hits* h, const Consts& c, bool prune,
-                 int32_t* counts, uint8_t* accept, uint32_t* status, hipStream_t s) {
+int launch_plain(const trig_events_csr* ev, const trig_hits* h, const Consts& c, int32_t* counts,
+                 uint8_t* accept, uint32_t* status, hipStream_t s) {
     const int n = ev->n_events;
     const unsigned grid = (unsigned)cdiv(n, kPlainWaves);
     if (mark_start(s)) return fail(TRIG_EHIP, "hipEventRecord(start)");
     hipLaunchKernelGGL((k_plain<T, kPlainWaves>), dim3(grid), dim3(kPlainWaves * kWave), 0, s,
-                       ev->layer_offsets, n, h->x, h->y, c, counts, accept, status, prune ? 1 : 0);
+                       ev->layer_offsets, n, h->x, h->y, c, counts, accept, status);
     if (int r = check_launch("k_plain")) return r;
     if (mark_stop(s)) return fail(TRIG_EHIP, "hipEventRecord(stop)");
     return TRIG_OK;
 }
 
 template <class T>
-int launch_persistent(const trig_events_csr* ev, const trig_hits* h, const Consts& c, bool prune,
-                      int tile_units, const Layout& L, char* ws, int32_t* counts, uint8_t* accept,
-                      uint32_t* status, hipStream_t s) {
+int launch_persistent(const trig_events_csr* ev, const trig_hits* h, const Consts& c, int tile_units,
+                      const Layout& L, char* ws, int32_t* counts, uint8_t* accept, uint32_t* status,
+                      hipStream_t s) {
     const int n = ev->n_events;
     auto* counter = reinterpret_cast<unsigned long long*>(ws + L.counter_off);
     auto* ustart = reinterpret_cast<int64_t*>(ws + L.units_off);
@@ -457,23 +496,56 @@ int launch_persistent(const trig_events_csr* ev, const trig_hits* h, const Const
     const unsigned grid = (unsigned)device_cus() * 8u;
     if (mark_start(s)) return fail(TRIG_EHIP, "hipEventRecord(start)");
     hipLaunchKernelGGL((k_persistent<T, kPersistWaves>), dim3(grid), dim3(kPersistWaves * kWave), 0, s,
-                       ev->layer_offsets, n, h->x, h->y, c, ustart, tile_units, counter, counts,
-                       prune ? 1 : 0);
+                       ev->layer_offsets, n, h->x, h->y, c, ustart, tile_units, counter, counts);
     if (int r = check_launch("k_persistent")) return r;
     if (mark_stop(s)) return fail(TRIG_EHIP, "hipEventRecord(stop)");
     hipLaunchKernelGGL(k_finalize, dim3(L.unit_blocks), dim3(kScanBlock), 0, s, n, c, counts, accept);
     return check_launch("k_finalize");
 }
 
-template <class T>
+__global__ void k_zero_u32(unsigned* p) { *p = 0u; }
+
+// Events per block for the batched form: about 60 % of the LDS hit capacity
+// at the batch's mean multiplicity, leaving room for fluctuations (blocks
+// that overflow are split into sub-blocks by the kernel).
+int choose_block_events(const trig_params* p, int n_events, int n_hits) {
+    if (p->block_events > 0) return p->block_events;
+    const double mean = n_events > 0 ? (double)n_hits / n_events : 1.0;
+    const double eb = 0.6 * kBlockHits / std::max(mean, 1.0);
+    return (int)std::max(1.0, std::min((double)kMaxEB, std::floor(eb)));
+}
+
+template <class P>
+int launch_block(const trig_events_csr* ev, const trig_hits* h, const trig_params* p, const Consts& c,
+                 const Layout& L, char* ws, int32_t* counts, uint8_t* accept, hipStream_t s) {
+    const int n = ev->n_events;
+    const int eb = choose_block_events(p, n, h->n_hits);
+    const int n_blocks = (int)cdiv(n, eb);
+    unsigned* counter = nullptr;
+    unsigned grid = (unsigned)n_blocks;
+    if (p->flags & TRIG_EXEC_PERSISTENT) {
+        counter = reinterpret_cast<unsigned*>(ws + L.counter_off);
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, counter);
+        if (int r = check_launch("k_zero_u32")) return r;
+        grid = (unsigned)std::min<int64_t>(n_blocks, (int64_t)device_cus() * kBlockResident);
+    }
+    if (mark_start(s)) return fail(TRIG_EHIP, "hipEventRecord(start)");
+    hipLaunchKernelGGL((k_block<P, kBlockHits>), dim3(grid), dim3(kBlockThreads), 0, s, ev->layer_offsets, n,
+                       h->x, h->y, c, eb, n_blocks, counter, counts, accept, p->out_status);
+    if (int r = check_launch("k_block")) return r;
+    if (mark_stop(s)) return fail(TRIG_EHIP, "hipEventRecord(stop)");
+    return TRIG_OK;
+}
+
+template <class T, class P>
 int run_form(const trig_events_csr* ev, const trig_hits* h, const trig_params* p, const Consts& c,
              const Layout& L, char* ws, int32_t* counts, uint8_t* accept, hipStream_t s) {
-    const bool prune = (p->flags & TRIG_EXEC_PRUNED) != 0;
+    if (p->flags & TRIG_EXEC_PRUNED) return launch_block<P>(ev, h, p, c, L, ws, counts, accept, s);
     if (p->flags & TRIG_EXEC_PERSISTENT) {
         const int tile_units = p->tile_pairs ? p->tile_pairs / kWave : kDefaultTileUnits;
-        return launch_persistent<T>(ev, h, c, prune, tile_units, L, ws, counts, accept, p->out_status, s);
+        return launch_persistent<T>(ev, h, c, tile_units, L, ws, counts, accept, p->out_status, s);
     }
-    return launch_plain<T>(ev, h, c, prune, counts, accept, p->out_status, s);
+    return launch_plain<T>(ev, h, c, counts, accept, p->out_status, s);
 }
 
 }  // namespace
@@ -520,9 +592,15 @@ int trig_select(const trig_events_csr* ev, const trig_hits* hits, const trig_par
     if (n > 0) {
         int r = TRIG_OK;
         switch (p->test) {
-            case TRIG_TEST_MSD: r = run_form<MsdTest>(ev, hits, p, c, L, ws, out_counts, out_accept, s); break;
-            case TRIG_TEST_MSD_FIT: r = run_form<MsdFitTest>(ev, hits, p, c, L, ws, out_counts, out_accept, s); break;
-            default: r = run_form<WindowTest>(ev, hits, p, c, L, ws, out_counts, out_accept, s); break;
+            case TRIG_TEST_MSD:
+                r = run_form<MsdTest, MsdPrune>(ev, hits, p, c, L, ws, out_counts, out_accept, s);
+                break;
+            case TRIG_TEST_MSD_FIT:  // validated: never with TRIG_EXEC_PRUNED
+                r = run_form<MsdFitTest, MsdPrune>(ev, hits, p, c, L, ws, out_counts, out_accept, s);
+                break;
+            default:
+                r = run_form<WindowTest, WindowPrune>(ev, hits, p, c, L, ws, out_counts, out_accept, s);
+                break;
         }
         if (r) return r;
     }

@@ -1,0 +1,299 @@
+// Block-staged selection with exact pair pruning (the batched form).
+//
+// A workgroup takes a block of consecutive events, copies their hits (one
+// contiguous CSR range) from HBM into LDS with coalesced loads, and counts
+// every event's passing triplets from LDS.  The count is the same as the
+// brute-force triplet loop (paper Sec. 3.2 steps 1-3), but triplets are only
+// completed for pairs (i, j) that can still pass:
+//
+//   MSD test:  Q = f32(A + f32(b*b)) >= A = f32(a*a) in binary32 (rounding is
+//              monotone and b*b >= 0), so a triplet can pass only if
+//              f32(a*a) <= Qmax in both planes, i.e. |a| <= beta with beta the
+//              largest binary32 value whose rounded square is <= Qmax
+//              (f32(a*a) is non-decreasing in |a|).  a = f32(U0*c_i + U1*c_j)
+//              depends on (i, j) only.
+//   window:    the layer-1 window |s_j - s_i| < W is itself part of the test.
+//
+// Both conditions are exact consequences of the binary32 test, so pruning
+// never changes a count.  Surviving pairs (rare: a is the distance of hit j
+// from the line through the vertex and hit i, in cm) are completed against
+// every layer-2 hit with the full binary32 test, lanes over k.
+//
+// Lane layout of the pair scan: lane L holds layer-1 hit j and its constant
+// part of a; for n1 <= 32 the 64 lanes hold R = floor(64/n1) copies of the
+// layer-1 hits, copy g scanning layer-0 hits i = g, g+R, g+2R, ... so that
+// few lanes idle.  The layer-0 part of a (or the layer-0 slope) is computed
+// once per hit into a per-wave LDS buffer and read with a broadcast.
+#pragma once
+
+#include "trig_device.hpp"
+
+namespace trig {
+
+constexpr int kBlockThreads = 256;
+constexpr int kBlockWaves = kBlockThreads / kWave;
+constexpr int kPBuf = 256;     // per-wave buffer of layer-0 values (float2)
+constexpr int kMaxEB = 256;    // events per block at most
+
+// Hits of the current sub-block in LDS, indexed relative to `base`.
+struct LdsHits {
+    const float2* s;
+    __device__ __forceinline__ float2 at(int h) const { return s[h]; }
+};
+// Hits read straight from HBM (events too large for LDS, irregular blocks).
+struct GlobalHits {
+    const float* x;
+    const float* y;
+    __device__ __forceinline__ float2 at(int h) const { return make_float2(x[h], y[h]); }
+};
+
+__device__ __forceinline__ float2 nan2() {
+    const float n = __builtin_nanf("");
+    return make_float2(n, n);
+}
+
+struct MsdPrune {
+    __device__ static __forceinline__ float2 layer0(const Consts& c, float2 h) {
+        return make_float2(c.U0 * h.x, c.U0 * h.y);
+    }
+    __device__ static __forceinline__ float2 layer1(const Consts& c, float2 h) {
+        return make_float2(c.U1 * h.x, c.U1 * h.y);
+    }
+    // Lanes whose pair can still pass: |f32(P + Q)| <= beta in both planes.
+    __device__ static __forceinline__ uint64_t pair_mask(const Consts& c, float2 p, float2 q) {
+        const float ax = p.x + q.x;
+        const float ay = p.y + q.y;
+        return lanes(__builtin_fabsf(ax) <= c.beta_x) & lanes(__builtin_fabsf(ay) <= c.beta_y);
+    }
+    // Passing triplets of the surviving pair (hi, hj) over layer-2 hits
+    // [o2, o2 + n2): lanes over k, the binary32 test of include/trig.h.
+    template <class H>
+    __device__ static uint32_t complete(const Consts& c, const H& hits, int hi, int hj, int o2, int n2) {
+        const float2 ci = hits.at(hi), cj = hits.at(hj);
+        const float ax = c.U0 * ci.x + c.U1 * cj.x;
+        const float ay = c.U0 * ci.y + c.U1 * cj.y;
+        const float ax2 = ax * ax, ay2 = ay * ay;
+        const float bx0 = c.V0 * ci.x + c.V1 * cj.x;
+        const float by0 = c.V0 * ci.y + c.V1 * cj.y;
+        uint32_t cnt = 0;
+        for (int k0 = 0; k0 < n2; k0 += kWave) {
+            const int k = k0 + (int)lane_id();
+            float2 w = nan2();
+            if (k < n2) {
+                const float2 ck = hits.at(o2 + k);
+                w = make_float2(c.V2 * ck.x, c.V2 * ck.y);
+            }
+            const float bx = bx0 + w.x;
+            const float qx = ax2 + bx * bx;
+            const float by = by0 + w.y;
+            const float qy = ay2 + by * by;
+            cnt += (uint32_t)__builtin_popcountll(lanes(qx <= c.qmax_x) & lanes(qy <= c.qmax_y));
+        }
+        return cnt;
+    }
+};
+
+struct WindowPrune {
+    __device__ static __forceinline__ float2 layer0(const Consts& c, float2 h) {
+        return make_float2(h.x / c.z0, h.y / c.z0);
+    }
+    __device__ static __forceinline__ float2 layer1(const Consts& c, float2 h) {
+        return make_float2(h.x / c.z1, h.y / c.z1);
+    }
+    __device__ static __forceinline__ uint64_t pair_mask(const Consts& c, float2 p, float2 q) {
+        return lanes(__builtin_fabsf(q.x - p.x) < c.win_x) & lanes(__builtin_fabsf(q.y - p.y) < c.win_y);
+    }
+    template <class H>
+    __device__ static uint32_t complete(const Consts& c, const H& hits, int hi, int /*hj*/, int o2, int n2) {
+        const float2 ci = hits.at(hi);
+        const float sxi = ci.x / c.z0, syi = ci.y / c.z0;
+        uint32_t cnt = 0;
+        for (int k0 = 0; k0 < n2; k0 += kWave) {
+            const int k = k0 + (int)lane_id();
+            float2 s = nan2();
+            if (k < n2) {
+                const float2 ck = hits.at(o2 + k);
+                s = make_float2(ck.x / c.z2, ck.y / c.z2);
+            }
+            cnt += (uint32_t)__builtin_popcountll(lanes(__builtin_fabsf(s.x - sxi) < c.win_x) &
+                                                  lanes(__builtin_fabsf(s.y - syi) < c.win_y));
+        }
+        return cnt;
+    }
+};
+
+// Passing triplets of one event (all layers non-empty), by one wave.
+// o0, o1, o2 index `hits`; pbuf is this wave's kPBuf-entry LDS buffer.
+template <class P, class H>
+__device__ uint32_t wave_event_pruned(const Consts& c, const H& hits, int o0, int n0, int o1, int n1,
+                                      int o2, int n2, float2* __restrict__ pbuf) {
+    const int lane = (int)lane_id();
+    const int R = n1 <= kWave / 2 ? kWave / n1 : 1;  // copies of layer 1 per wave
+    uint32_t cnt = 0;
+    for (int jc = 0; jc < n1; jc += kWave) {
+        int g, j;
+        if (R > 1) {
+            g = (int)(((float)lane + 0.5f) * (1.0f / (float)n1));  // floor(lane / n1), exact
+            j = lane - g * n1;
+        } else {
+            g = 0;
+            j = jc + lane;
+        }
+        const bool jv = (g < R) && (j < n1);
+        if (!jv) g = 0;
+        const float2 q = jv ? P::layer1(c, hits.at(o1 + j)) : nan2();
+        const int chunk = (kPBuf / R) * R;  // layer-0 hits per buffer fill
+        for (int ic = 0; ic < n0; ic += chunk) {
+            const int ni = min(chunk, n0 - ic);
+            const int T = (ni + R - 1) / R;
+            const int npad = T * R;  // <= chunk <= kPBuf
+            for (int t = lane; t < npad; t += kWave)
+                pbuf[t] = t < ni ? P::layer0(c, hits.at(o0 + ic + t)) : nan2();
+            wave_lds_sync();
+            // Survivors of 64 pairs (lane -> pair (ic + g + R t, j)).
+            auto finish = [&](uint64_t m, int t) {
+                while (m) {
+                    const int L = __builtin_ctzll(m);
+                    m &= m - 1;
+                    const int iL = __builtin_amdgcn_readlane(g, L) + R * t;
+                    const int jL = __builtin_amdgcn_readlane(j, L);
+                    cnt += P::complete(c, hits, o0 + ic + iL, o1 + jL, o2, n2);
+                }
+            };
+            const float2* pp = pbuf + g;
+            int t = 0;
+            for (; t + 4 <= T; t += 4) {
+                const float2 p0 = pp[R * t], p1 = pp[R * (t + 1)], p2 = pp[R * (t + 2)], p3 = pp[R * (t + 3)];
+                const uint64_t m0 = P::pair_mask(c, p0, q), m1 = P::pair_mask(c, p1, q);
+                const uint64_t m2 = P::pair_mask(c, p2, q), m3 = P::pair_mask(c, p3, q);
+                if ((m0 | m1 | m2 | m3) != 0ull) {
+                    finish(m0, t);
+                    finish(m1, t + 1);
+                    finish(m2, t + 2);
+                    finish(m3, t + 3);
+                }
+            }
+            for (; t < T; ++t) {
+                const uint64_t m = P::pair_mask(c, pp[R * t], q);
+                if (m) finish(m, t);
+            }
+            wave_lds_sync();
+        }
+    }
+    return cnt;
+}
+
+// Count of event e (absolute index) whose CSR range was checked by the
+// caller; writes count and flag.  h_base: index of hits.at(0) in the global
+// hit arrays (0 for GlobalHits).
+template <class P, class H>
+__device__ void wave_event(const Consts& c, const H& hits, int h_base, int o0, int o1, int o2, int o3,
+                           int e, int32_t* counts, uint8_t* accept, uint32_t* status, float2* pbuf) {
+    const int n0 = o1 - o0, n1 = o2 - o1, n2 = o3 - o2;
+    int32_t cnt = 0;
+    if (n2 > 0 && (int64_t)n0 * n1 > (int64_t)INT32_MAX / n2) {
+        cnt = -2;
+    } else if (n0 > 0 && n1 > 0 && n2 > 0) {
+        cnt = (int32_t)wave_event_pruned<P>(c, hits, o0 - h_base, n0, o1 - h_base, n1, o2 - h_base, n2, pbuf);
+    }
+    if (lane_id() == 0) {
+        counts[e] = cnt;
+        accept[e] = (uint8_t)(cnt >= 0 && cnt >= c.min_triplets);
+        if (cnt < 0 && status) atomicOr(status, TRIG_STATUS_OVERFLOW);
+    }
+}
+
+// The block kernel.  Non-persistent when block_counter == nullptr (block =
+// blockIdx.x); otherwise workgroups take blocks from *block_counter until
+// they run out (the counter must be zero at launch).
+template <class P, int HB>
+__global__ __launch_bounds__(kBlockThreads) void k_block(const int32_t* __restrict__ off, int n_events,
+                                                         const float* __restrict__ x,
+                                                         const float* __restrict__ y, Consts c, int eb,
+                                                         int n_blocks, unsigned* block_counter,
+                                                         int32_t* __restrict__ counts,
+                                                         uint8_t* __restrict__ accept, uint32_t* status) {
+    __shared__ float2 stage[HB];
+    __shared__ float2 pbuf_all[kBlockWaves][kPBuf];
+    __shared__ int32_t soff[3 * kMaxEB + 1];
+    __shared__ int s_block, s_next, s_bad;
+    const int w = uniform_i(threadIdx.x / kWave);
+    float2* pbuf = pbuf_all[w];
+    const GlobalHits ghits{x, y};
+    int iter = 0;
+    for (;; ++iter) {
+        if (threadIdx.x == 0) {
+            if (block_counter)
+                s_block = (int)atomicAdd(block_counter, 1u);
+            else
+                s_block = iter == 0 ? (int)blockIdx.x : n_blocks;
+            s_bad = 0;
+        }
+        __syncthreads();
+        const int b = s_block;
+        if (b >= n_blocks) break;
+        const int e0 = b * eb;
+        const int ne = min(eb, n_events - e0);
+        for (int t = threadIdx.x; t <= 3 * ne; t += kBlockThreads) soff[t] = off[3 * (int64_t)e0 + t];
+        __syncthreads();
+        // Per-event CSR checks; malformed events get -1 here.
+        for (int t = threadIdx.x; t < ne; t += kBlockThreads) {
+            const int a0 = soff[3 * t], a1 = soff[3 * t + 1], a2 = soff[3 * t + 2], a3 = soff[3 * t + 3];
+            if (!(0 <= a0 && a0 <= a1 && a1 <= a2 && a2 <= a3 && a3 <= c.n_hits)) {
+                counts[e0 + t] = -1;
+                accept[e0 + t] = 0;
+                if (status) atomicOr(status, TRIG_STATUS_MALFORMED);
+                atomicOr(&s_bad, 1);
+            }
+        }
+        __syncthreads();
+        if (s_bad) {
+            // Irregular block: every well-formed event straight from HBM.
+            for (int t = w; t < ne; t += kBlockWaves) {
+                const int a0 = soff[3 * t], a1 = soff[3 * t + 1], a2 = soff[3 * t + 2], a3 = soff[3 * t + 3];
+                if (0 <= a0 && a0 <= a1 && a1 <= a2 && a2 <= a3 && a3 <= c.n_hits)
+                    wave_event<P>(c, ghits, 0, a0, a1, a2, a3, e0 + t, counts, accept, status, pbuf);
+            }
+            __syncthreads();
+            if (!block_counter) break;
+            continue;
+        }
+        // Well-formed block: offsets are non-decreasing over it.  Stage
+        // sub-blocks of consecutive events whose hits fit in LDS.
+        int cur = 0;
+        while (cur < ne) {
+            const int base = soff[3 * cur];
+            const int t = (int)threadIdx.x;
+            const bool fits = (cur + t < ne) && (soff[3 * (cur + t + 1)] - base <= HB);
+            const int nfit = __syncthreads_count(fits);  // fits is a prefix in t
+            if (nfit == 0) {
+                // One event larger than LDS: wave 0 reads it from HBM.
+                if (w == 0)
+                    wave_event<P>(c, ghits, 0, soff[3 * cur], soff[3 * cur + 1], soff[3 * cur + 2],
+                                  soff[3 * cur + 3], e0 + cur, counts, accept, status, pbuf);
+                __syncthreads();
+                cur += 1;
+                continue;
+            }
+            const int end = cur + nfit;
+            const int nh = soff[3 * end] - base;
+            for (int h = t; h < nh; h += kBlockThreads) stage[h] = make_float2(x[base + h], y[base + h]);
+            if (t == 0) s_next = cur;
+            __syncthreads();
+            const LdsHits lh{stage};
+            for (;;) {
+                int ev = 0;
+                if (lane_id() == 0) ev = atomicAdd(&s_next, 1);
+                ev = uniform_i(ev);
+                if (ev >= end) break;
+                wave_event<P>(c, lh, base, soff[3 * ev], soff[3 * ev + 1], soff[3 * ev + 2], soff[3 * ev + 3],
+                              e0 + ev, counts, accept, status, pbuf);
+            }
+            __syncthreads();
+            cur = end;
+        }
+        if (!block_counter) break;
+    }
+}
+
+}  // namespace trig

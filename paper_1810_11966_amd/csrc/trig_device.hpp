@@ -25,6 +25,8 @@ struct Consts {
     float z0, z1, z2, w;
     // MSD tests: largest binary32 Q with f32(Q / ndf) <= msd_max, per plane
     float qmax_x, qmax_y;
+    // MSD pair bound: largest binary32 b >= 0 with f32(b * b) <= qmax, per plane
+    float beta_x, beta_y;
     // TRIG_TEST_SLOPE_WINDOW
     float win_x, win_y;
     int32_t min_triplets;
@@ -91,11 +93,6 @@ struct MsdTest {
         const float n = __builtin_nanf("");
         return Pair{n, n, n, n};
     }
-    // Exact necessary condition: Q = f32(A + f32(b*b)) >= A = f32(a*a) since
-    // rounding is monotone, so a pair with A > Qmax in a plane has no passing k.
-    __device__ static __forceinline__ bool may_pass(const Consts& c, const Pair& p) {
-        return (p.ax2 <= c.qmax_x) & (p.ay2 <= c.qmax_y);
-    }
     __device__ static __forceinline__ uint64_t pass(const Consts& c, const Pair& p, const float* h) {
         const float bx = p.bx0 + h[0];
         const float qx = p.ax2 + bx * bx;
@@ -132,7 +129,6 @@ struct MsdFitTest {
         const float n = __builtin_nanf("");
         return Pair{n, n, n, n, n, n};
     }
-    __device__ static __forceinline__ bool may_pass(const Consts&, const Pair&) { return true; }
     __device__ static __forceinline__ float plane_q(const Consts& c, float ci, float cj, float s01,
                                                     float ck, float pk) {
         const float m = (s01 + pk) * c.w;
@@ -172,9 +168,6 @@ struct WindowTest {
     __device__ static __forceinline__ Pair invalid() {
         const float n = __builtin_nanf("");
         return Pair{n, n};
-    }
-    __device__ static __forceinline__ bool may_pass(const Consts&, const Pair& p) {
-        return p.sxi == p.sxi;  // not NaN
     }
     __device__ static __forceinline__ uint64_t pass(const Consts& c, const Pair& p, const float* h) {
         return lanes(__builtin_fabsf(h[0] - p.sxi) < c.win_x) & lanes(__builtin_fabsf(h[1] - p.syi) < c.win_y);
@@ -217,7 +210,7 @@ __device__ __forceinline__ uint32_t pair_tiles(const EventRange& ev) {
 template <class T, int KCH>
 __device__ uint32_t wave_count(const float* __restrict__ x, const float* __restrict__ y,
                                const EventRange& ev, uint32_t t_begin, uint32_t t_end,
-                               const Consts& c, float* __restrict__ lds, bool prune) {
+                               const Consts& c, float* __restrict__ lds) {
     static_assert(KCH % 4 == 0, "chunk must hold whole float4 groups");
     const unsigned lane = lane_id();
     const uint32_t n0 = (uint32_t)ev.n0, n1 = (uint32_t)ev.n1;
@@ -239,18 +232,15 @@ __device__ uint32_t wave_count(const float* __restrict__ x, const float* __restr
         for (uint32_t t = t_begin; t < t_end; ++t) {
             typename T::Pair pr = T::invalid();
             if (i < n0) pr = T::pair(c, x[ev.o0 + i], y[ev.o0 + i], x[ev.o1 + j], y[ev.o1 + j]);
-            const bool go = !prune || wave_any(T::may_pass(c, pr));
-            if (go) {
-                // nk_pad is a multiple of 4: four layer-2 hits per iteration
-                for (int k = 0; k < nk_pad; k += 4) {
-                    const float* h = lds + k * T::HF;
-                    const uint64_t m0 = T::pass(c, pr, h);
-                    const uint64_t m1 = T::pass(c, pr, h + T::HF);
-                    const uint64_t m2 = T::pass(c, pr, h + 2 * T::HF);
-                    const uint64_t m3 = T::pass(c, pr, h + 3 * T::HF);
-                    cnt += (uint32_t)(__builtin_popcountll(m0) + __builtin_popcountll(m1) +
-                                      __builtin_popcountll(m2) + __builtin_popcountll(m3));
-                }
+            // nk_pad is a multiple of 4: four layer-2 hits per iteration
+            for (int k = 0; k < nk_pad; k += 4) {
+                const float* h = lds + k * T::HF;
+                const uint64_t m0 = T::pass(c, pr, h);
+                const uint64_t m1 = T::pass(c, pr, h + T::HF);
+                const uint64_t m2 = T::pass(c, pr, h + 2 * T::HF);
+                const uint64_t m3 = T::pass(c, pr, h + 3 * T::HF);
+                cnt += (uint32_t)(__builtin_popcountll(m0) + __builtin_popcountll(m1) +
+                                  __builtin_popcountll(m2) + __builtin_popcountll(m3));
             }
             j += dr;
             i += dq;

@@ -44,7 +44,7 @@ FORMS = {
 
 # Every symbol include/trig.h declares.
 EXPORTED = ("trig_params_init", "trig_workspace_bytes", "trig_select", "trig_set_kernel_events",
-            "trig_strerror", "trig_last_error_detail")
+            "trig_strerror", "trig_last_error_detail", "trig_probe_valu", "trig_probe_copy")
 
 
 class TrigEventsCsr(ctypes.Structure):
@@ -63,7 +63,7 @@ class TrigParams(ctypes.Structure):
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
                 ("out_accepted_ids", ctypes.c_void_p), ("out_n_accepted", ctypes.c_void_p),
                 ("out_status", ctypes.c_void_p), ("tile_pairs", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 7)]
+                ("block_events", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
 
 
 class TrigError(RuntimeError):
@@ -97,6 +97,12 @@ def load(path: str = LIB_PATH):
     lib.trig_strerror.argtypes = [ctypes.c_int]
     lib.trig_last_error_detail.restype = ctypes.c_char_p
     lib.trig_last_error_detail.argtypes = []
+    lib.trig_probe_valu.restype = ctypes.c_int
+    lib.trig_probe_valu.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_float, ctypes.c_void_p,
+                                    ctypes.c_void_p]
+    lib.trig_probe_copy.restype = ctypes.c_int
+    lib.trig_probe_copy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32,
+                                    ctypes.c_void_p]
     _lib = lib
     return lib
 
@@ -111,7 +117,7 @@ def trig_params_init() -> TrigParams:
 
 def make_params(test: str = "msd", z=None, msd_max=None, ndf: Optional[int] = None,
                 slope_window=None, min_triplets: Optional[int] = None, flags: int = 0,
-                tile_pairs: int = 0) -> TrigParams:
+                tile_pairs: int = 0, block_events: int = 0) -> TrigParams:
     """Defaults from trig_params_init(), overridden by the given values."""
     p = trig_params_init()
     p.test = TESTS[test] if isinstance(test, str) else int(test)
@@ -128,6 +134,7 @@ def make_params(test: str = "msd", z=None, msd_max=None, ndf: Optional[int] = No
         p.min_triplets = int(min_triplets)
     p.flags = int(flags)
     p.tile_pairs = int(tile_pairs)
+    p.block_events = int(block_events)
     return p
 
 

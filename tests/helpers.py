@@ -76,3 +76,29 @@ def ragged_sizes_set(sizes, seed, with_tracks=True, spread=200.0):
             layers.append([tuple(map(float, p)) for p in pts])
         events.append(layers)
     return synth.from_layers(events)
+
+
+def pair_boundary_events(n_events, per_layer, seed, rel=1e-6, z=(400.0, 410.0, 420.0)):
+    """Events whose tracks are displaced along u = (z1, -z0, 0)/|(z0, z1)|,
+    the direction that changes only the layer-0/1 part a of the residual, by
+    |a| within a relative ``rel`` of sqrt(ndf*T) (ndf 2): triplets sit right at
+    the boundary where f32(a*a) crosses Qmax."""
+    rng = np.random.default_rng(seed)
+    z = np.asarray(z, np.float64)
+    u = np.array([z[1], -z[0], 0.0]) / np.hypot(z[0], z[1])
+    xs, ys, off = [], [], [0]
+    for e in range(n_events):
+        n = per_layer
+        cx, cy = [], []
+        for T, store in ((0.03, cx), (0.025, cy)):
+            m = rng.uniform(-0.4, 0.4, n)
+            r = np.sqrt(2 * T) * (1.0 + rng.uniform(-rel, rel, n)) * rng.choice([-1.0, 1.0], n)
+            c = m[:, None] * z[None, :] + r[:, None] * u[None, :]
+            store.append(c.astype(np.float32))
+        cx, cy = cx[0], cy[0]
+        for l in range(3):
+            perm = rng.permutation(n)
+            xs.append(cx[perm, l]); ys.append(cy[perm, l])
+            off.append(off[-1] + n)
+    return synth.EventSet(np.asarray(off, np.int32), np.concatenate(xs), np.concatenate(ys),
+                          np.zeros(n_events, np.int8))

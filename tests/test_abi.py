@@ -12,7 +12,7 @@ import pytest
 from paper_1810_11966_amd import build, trig
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "trig.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("trig.h", "trig_probe.h")]
 
 
 @pytest.fixture(scope="module")
@@ -23,7 +23,7 @@ def lib():
 
 
 def declared_functions():
-    src = open(HEADER).read()
+    src = "".join(open(h).read() for h in HEADERS)
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(trig_[a-z_]+)\s*\(", src)))
 

@@ -14,7 +14,7 @@ from tests import helpers
 pytestmark = pytest.mark.gpu
 
 TESTS = ("msd", "msd_fit", "window")
-FORMS = ("plain", "pruned", "persistent", "persistent_pruned")
+FORMS = ("plain", "persistent", "pruned", "persistent_pruned")
 
 
 def forms_for(test):
@@ -122,6 +122,33 @@ def test_near_threshold_stress(gpu, test):
     for form in forms_for(test):
         c = assert_parity(gpu, s, test, form, "near_threshold")
     assert c.sum() > 0
+
+
+def test_pair_prune_boundary(gpu):
+    """Triplets whose layer-0/1 residual part alone sits at the cut: the exact
+    pair pruning of the batched form must keep every pair that can pass."""
+    s = synth.concat([helpers.pair_boundary_events(300, 6, seed=1, rel=1e-6),
+                      helpers.pair_boundary_events(300, 6, seed=2, rel=3e-8)])
+    for form in FORMS:
+        c = assert_parity(gpu, s, "msd", form, "pair boundary")
+    assert c.sum() > 0
+    for form in ("plain", "persistent_pruned"):
+        assert_parity(gpu, s, "msd", form, "pair boundary ndf3", ndf=3, msd_max=(0.02, 0.016666668))
+
+
+def test_block_shapes_and_large_events(gpu):
+    """Batched form: events per block from 1 to 256 (sub-blocks when a block's
+    hits exceed LDS), and events too large for LDS mixed into blocks."""
+    base = synth.make_event_set(synth.SMALL_10K, n_events=3000)
+    big = helpers.ragged_sizes_set([(1, 1, 5000), (2, 3, 4500), (70, 60, 4000), (3, 4100, 2)], seed=4)
+    s = synth.concat([base.subset(0, 1000), big, base.subset(1000, 2000)])
+    for test in ("msd", "window"):
+        for form in ("pruned", "persistent_pruned"):
+            for eb in (0, 1, 7, 64, 256):
+                assert_parity(gpu, s, test, form, f"block_events={eb}", block_events=eb)
+    dense = synth.make_event_set(synth.DENSE_100K, n_events=300)
+    for eb in (1, 5, 40):
+        assert_parity(gpu, dense, "msd", "persistent_pruned", f"dense block_events={eb}", block_events=eb)
 
 
 def test_near_threshold_other_ndf_and_thresholds(gpu):
