@@ -11,8 +11,8 @@
 //   k_units        persistent form, step 1: per-event validation and the
 //                  number of work units (ceil(pair tiles / tile units))
 //   k_scan_*       exclusive scans of per-block partial sums
-//   k_persistent   persistent grid; waves take batches of work units from one
-//                  global counter and add their counts with integer atomics
+//   k_persistent   persistent grid; workgroups take batches of work units from
+//                  one global counter, waves add their counts with integer atomics
 //   k_finalize     accept flags from the accumulated counts
 //   k_block        batched form: blocks of events staged in LDS, exact pair
 //                  pruning (trig_block.hpp); optionally persistent
@@ -252,25 +252,34 @@ __global__ __launch_bounds__(WPB * kWave) void k_persistent(
     unsigned long long* counter, int32_t* counts) {
     constexpr int KCH = Chunk<T>::value;
     __shared__ __align__(16) float lds_all[WPB][KCH * T::HF];
+    __shared__ unsigned long long s_first;
     const int w = uniform_i(threadIdx.x / kWave);
     float* lds = lds_all[w];
     const int64_t total = ustart[n_events];
     for (;;) {
-        unsigned long long first = 0;
-        if (lane_id() == 0) first = atomicAdd(counter, (unsigned long long)kPersistBatch);
-        first = __shfl(first, 0, kWave);
-        if ((int64_t)first >= total) break;
-        const int64_t last = min((int64_t)first + kPersistBatch, total);
-        int e = wave_find_event(ustart, n_events, (int64_t)first);
-        for (int64_t u = (int64_t)first; u < last; ++u) {
-            while (ustart[e + 1] <= u) ++e;  // next non-empty event
-            EventRange ev;
-            load_event(off, e, c.n_hits, ev);  // valid: only such events own units
-            const uint32_t tiles = pair_tiles(ev);
-            const uint32_t tb = (uint32_t)((u - ustart[e]) * tile_units);
-            const uint32_t te = min(tiles, tb + (uint32_t)tile_units);
-            const uint32_t cnt = wave_count<T, KCH>(x, y, ev, tb, te, c, lds);
-            if (lane_id() == 0 && cnt) atomicAdd(&counts[e], (int32_t)cnt);
+        // The workgroup takes WPB batches at once (thread 0, through LDS);
+        // every branch below depends on workgroup-uniform values only.
+        if (threadIdx.x == 0) s_first = atomicAdd(counter, (unsigned long long)(WPB * kPersistBatch));
+        __syncthreads();
+        const unsigned long long wg_first = s_first;
+        __syncthreads();
+        const int64_t first = (int64_t)(((uint64_t)(uint32_t)uniform_i((int)(uint32_t)(wg_first >> 32)) << 32) |
+                                        (uint32_t)uniform_i((int)(uint32_t)wg_first));
+        if (first >= total) break;
+        const int64_t lo = first + (int64_t)w * kPersistBatch;
+        const int64_t hi = min(lo + kPersistBatch, total);
+        if (lo < hi) {
+            int e = wave_find_event(ustart, n_events, lo);
+            for (int64_t u = lo; u < hi; ++u) {
+                while (ustart[e + 1] <= u) ++e;  // next non-empty event
+                EventRange ev;
+                load_event(off, e, c.n_hits, ev);  // valid: only such events own units
+                const uint32_t tiles = pair_tiles(ev);
+                const uint32_t tb = (uint32_t)((u - ustart[e]) * tile_units);
+                const uint32_t te = min(tiles, tb + (uint32_t)tile_units);
+                const uint32_t cnt = wave_count<T, KCH>(x, y, ev, tb, te, c, lds);
+                if (lane_id() == 0 && cnt) atomicAdd(&counts[e], (int32_t)cnt);
+            }
         }
     }
 }
@@ -530,8 +539,9 @@ int launch_block(const trig_events_csr* ev, const trig_hits* h, const trig_param
         grid = (unsigned)std::min<int64_t>(n_blocks, (int64_t)device_cus() * kBlockResident);
     }
     if (mark_start(s)) return fail(TRIG_EHIP, "hipEventRecord(start)");
+    const int vec = ((reinterpret_cast<uintptr_t>(h->x) | reinterpret_cast<uintptr_t>(h->y)) & 15) == 0;
     hipLaunchKernelGGL((k_block<P, kBlockHits>), dim3(grid), dim3(kBlockThreads), 0, s, ev->layer_offsets, n,
-                       h->x, h->y, c, eb, n_blocks, counter, counts, accept, p->out_status);
+                       h->x, h->y, c, eb, n_blocks, counter, vec, counts, accept, p->out_status);
     if (int r = check_launch("k_block")) return r;
     if (mark_stop(s)) return fail(TRIG_EHIP, "hipEventRecord(stop)");
     return TRIG_OK;

@@ -35,10 +35,12 @@ constexpr int kBlockWaves = kBlockThreads / kWave;
 constexpr int kPBuf = 256;     // per-wave buffer of layer-0 values (float2)
 constexpr int kMaxEB = 256;    // events per block at most
 
-// Hits of the current sub-block in LDS, indexed relative to `base`.
+// Hits of the current sub-block in LDS (structure of arrays), indexed
+// relative to the staged range's 4-aligned start.
 struct LdsHits {
-    const float2* s;
-    __device__ __forceinline__ float2 at(int h) const { return s[h]; }
+    const float* xs;
+    const float* ys;
+    __device__ __forceinline__ float2 at(int h) const { return make_float2(xs[h], ys[h]); }
 };
 // Hits read straight from HBM (events too large for LDS, irregular blocks).
 struct GlobalHits {
@@ -206,17 +208,74 @@ __device__ void wave_event(const Consts& c, const H& hits, int h_base, int o0, i
 // The block kernel.  Non-persistent when block_counter == nullptr (block =
 // blockIdx.x); otherwise workgroups take blocks from *block_counter until
 // they run out (the counter must be zero at launch).
+// Copies hits [base, base + nh) of x and y into xs/ys (LDS) at local index
+// (h - a0), a0 = base rounded down to a multiple of 4, with 16-byte loads
+// issued together (every thread's loads are in flight before any LDS write).
+// The one float4 group that would cross n_hits is copied element by element
+// by thread 0.  Needs x and y 16-byte aligned (checked by the host; `vec`
+// false otherwise: plain 4-byte loads).
+template <int HB>
+__device__ __forceinline__ void stage_hits(const float* __restrict__ x, const float* __restrict__ y,
+                                           int base, int nh, int n_hits, bool vec, float* xs, float* ys) {
+    constexpr int Q = (HB + 6) / 4 / kBlockThreads + 1;  // float4 groups per thread, upper bound
+    const int a0 = base & ~3;
+    const int nq = (base + nh - a0 + 3) >> 2;             // float4 groups to copy
+    const int t = (int)threadIdx.x;
+    if (vec) {
+        const int nq_full = min(nq, (n_hits - a0) >> 2);   // groups entirely below n_hits
+        if (nq_full > 0) {
+            // Unconditional loads (a group past the end re-reads the last full
+            // one), so that all of them are in flight in registers at once.
+            float4 vx[Q], vy[Q];
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                const int q = min(t + k * kBlockThreads, nq_full - 1);
+                vx[k] = *reinterpret_cast<const float4*>(x + a0 + 4 * q);
+                vy[k] = *reinterpret_cast<const float4*>(y + a0 + 4 * q);
+            }
+            // Consume every loaded value in an empty asm statement: all loads
+            // are issued before it (one wait for the lot), the LDS stores
+            // after it, instead of each load sinking next to its store.
+#pragma unroll
+            for (int k = 0; k < Q; ++k)
+                asm volatile("" ::"v"(vx[k].x), "v"(vx[k].y), "v"(vx[k].z), "v"(vx[k].w), "v"(vy[k].x),
+                             "v"(vy[k].y), "v"(vy[k].z), "v"(vy[k].w));
+#pragma unroll
+            for (int k = 0; k < Q; ++k) {
+                const int q = t + k * kBlockThreads;
+                if (q < nq_full) {
+                    reinterpret_cast<float4*>(xs)[q] = vx[k];
+                    reinterpret_cast<float4*>(ys)[q] = vy[k];
+                }
+            }
+        }
+        if (t == 0 && nq_full < nq) {
+            for (int g = a0 + 4 * nq_full; g < base + nh; ++g) {
+                xs[g - a0] = x[g];
+                ys[g - a0] = y[g];
+            }
+        }
+    } else {
+        for (int h = t; h < nh; h += kBlockThreads) {
+            xs[base - a0 + h] = x[base + h];
+            ys[base - a0 + h] = y[base + h];
+        }
+    }
+}
+
 template <class P, int HB>
 __global__ __launch_bounds__(kBlockThreads) void k_block(const int32_t* __restrict__ off, int n_events,
                                                          const float* __restrict__ x,
                                                          const float* __restrict__ y, Consts c, int eb,
-                                                         int n_blocks, unsigned* block_counter,
+                                                         int n_blocks, unsigned* block_counter, int vec,
                                                          int32_t* __restrict__ counts,
                                                          uint8_t* __restrict__ accept, uint32_t* status) {
-    __shared__ float2 stage[HB];
+    // HB hits plus up to 3 before the first and 3 after the last (4-aligned copy)
+    __shared__ __align__(16) float stage_x[HB + 8];
+    __shared__ __align__(16) float stage_y[HB + 8];
     __shared__ float2 pbuf_all[kBlockWaves][kPBuf];
     __shared__ int32_t soff[3 * kMaxEB + 1];
-    __shared__ int s_block, s_next, s_bad;
+    __shared__ int s_block, s_bad;
     const int w = uniform_i(threadIdx.x / kWave);
     float2* pbuf = pbuf_all[w];
     const GlobalHits ghits{x, y};
@@ -230,7 +289,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_block(const int32_t* __restri
             s_bad = 0;
         }
         __syncthreads();
-        const int b = s_block;
+        const int b = uniform_i(s_block);
         if (b >= n_blocks) break;
         const int e0 = b * eb;
         const int ne = min(eb, n_events - e0);
@@ -247,7 +306,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_block(const int32_t* __restri
             }
         }
         __syncthreads();
-        if (s_bad) {
+        if (uniform_i(s_bad)) {
             // Irregular block: every well-formed event straight from HBM.
             for (int t = w; t < ne; t += kBlockWaves) {
                 const int a0 = soff[3 * t], a1 = soff[3 * t + 1], a2 = soff[3 * t + 2], a3 = soff[3 * t + 3];
@@ -265,7 +324,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_block(const int32_t* __restri
             const int base = soff[3 * cur];
             const int t = (int)threadIdx.x;
             const bool fits = (cur + t < ne) && (soff[3 * (cur + t + 1)] - base <= HB);
-            const int nfit = __syncthreads_count(fits);  // fits is a prefix in t
+            const int nfit = uniform_i(__syncthreads_count(fits));  // fits is a prefix in t
             if (nfit == 0) {
                 // One event larger than LDS: wave 0 reads it from HBM.
                 if (w == 0)
@@ -277,18 +336,15 @@ __global__ __launch_bounds__(kBlockThreads) void k_block(const int32_t* __restri
             }
             const int end = cur + nfit;
             const int nh = soff[3 * end] - base;
-            for (int h = t; h < nh; h += kBlockThreads) stage[h] = make_float2(x[base + h], y[base + h]);
-            if (t == 0) s_next = cur;
+            stage_hits<HB>(x, y, base, nh, c.n_hits, vec != 0, stage_x, stage_y);
             __syncthreads();
-            const LdsHits lh{stage};
-            for (;;) {
-                int ev = 0;
-                if (lane_id() == 0) ev = atomicAdd(&s_next, 1);
-                ev = uniform_i(ev);
-                if (ev >= end) break;
-                wave_event<P>(c, lh, base, soff[3 * ev], soff[3 * ev + 1], soff[3 * ev + 2], soff[3 * ev + 3],
+            // Events of the sub-block round-robin over the waves (a static
+            // assignment: no per-wave claim loop).
+            const LdsHits lh{stage_x, stage_y};
+            const int a0 = base & ~3;
+            for (int ev = cur + w; ev < end; ev += kBlockWaves)
+                wave_event<P>(c, lh, a0, soff[3 * ev], soff[3 * ev + 1], soff[3 * ev + 2], soff[3 * ev + 3],
                               e0 + ev, counts, accept, status, pbuf);
-            }
             __syncthreads();
             cur = end;
         }

@@ -151,6 +151,27 @@ def test_block_shapes_and_large_events(gpu):
         assert_parity(gpu, dense, "msd", "persistent_pruned", f"dense block_events={eb}", block_events=eb)
 
 
+def test_misaligned_hit_arrays(gpu):
+    """x and y starting 4 bytes past a 16-byte boundary: the batched form's
+    staging takes its element-wise path; counts are unchanged."""
+    from paper_1810_11966_amd import trig
+    torch = gpu
+    s = synth.make_event_set(synth.SMALL_10K, n_events=4000)
+    c, a, st, _ = oracle_result(s, R.OracleConfig())
+    off = torch.from_numpy(s.offsets).cuda()
+    xf = torch.zeros(s.n_hits + 1, dtype=torch.float32, device="cuda")
+    yf = torch.zeros(s.n_hits + 1, dtype=torch.float32, device="cuda")
+    xf[1:] = torch.from_numpy(s.x).cuda()
+    yf[1:] = torch.from_numpy(s.y).cuda()
+    x, y = xf[1:], yf[1:]
+    assert x.data_ptr() % 16 == 4
+    for form in FORMS:
+        print(f"[misaligned] {form}", flush=True)
+        r = trig.select(off, x, y, form=form, compact=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(r.counts.cpu().numpy(), c), form
+
+
 def test_near_threshold_other_ndf_and_thresholds(gpu):
     s = helpers.near_threshold_events(200, 8, seed=9, rel=1e-4)
     for kw in ({"ndf": 3}, {"ndf": 1}, {"ndf": 7, "msd_max": (0.0085714, 0.0071428)},
