@@ -157,7 +157,7 @@ typedef struct {
                                    per work unit (multiple of 64; 0 = library
                                    default) */
     int32_t block_events;       /* TRIG_EXEC_PRUNED: events per workgroup block
-                                   (1..256; 0 = chosen from the mean number of
+                                   (1..128; 0 = chosen from the mean number of
                                    hits per event) */
     int32_t reserved[6];        /* must be zero */
 } trig_params;
@@ -183,7 +183,7 @@ size_t trig_workspace_bytes(const trig_events_csr *ev, const trig_params *p);
  * required pointer, n_events < 0, n_hits < 0, an ABI mismatch, non-finite or
  * non-positive z, a negative or NaN threshold or window, ndf < 1,
  * min_triplets < 0, tile_pairs not a non-negative multiple of 64,
- * block_events outside 0..256, non-zero reserved fields; TRIG_EWORKSPACE; TRIG_EUNSUPPORTED.  TRIG_EHIP if a launch
+ * block_events outside 0..128, non-zero reserved fields; TRIG_EWORKSPACE; TRIG_EUNSUPPORTED.  TRIG_EHIP if a launch
  * fails.  n_events == 0 enqueues only the compaction count (0), if requested.
  * Data-dependent problems are reported per event (see TRIG_COUNT_*) without a
  * host synchronisation.  Concurrent calls on different streams need distinct

@@ -42,8 +42,9 @@ constexpr int kCompactItems = 4;    // events per thread in compaction
 constexpr int kPersistWaves = 4;    // waves per workgroup, persistent form
 constexpr int kPersistBatch = 4;    // work units taken per atomic
 constexpr int kDefaultTileUnits = 8;  // pair tiles (of 64 pairs) per work unit
-constexpr int kBlockHits = 4096;      // LDS hit capacity of a batched-form workgroup
-constexpr int kBlockResident = 3;     // batched workgroups per CU (LDS-limited)
+constexpr int kBlockHitsSmall = 2048;  // LDS hit capacities of a batched-form workgroup
+constexpr int kBlockHitsLarge = 4096;
+constexpr int kBlockResident = 6;      // batched workgroups per CU (LDS-limited)
 
 template <class T>
 struct Chunk;
@@ -407,7 +408,7 @@ int validate(const trig_events_csr* ev, const trig_hits* hits, const trig_params
     if (p->ndf < 1) return fail(TRIG_EINVAL, "ndf < 1");
     if (p->min_triplets < 0) return fail(TRIG_EINVAL, "min_triplets < 0");
     if (p->tile_pairs < 0 || p->tile_pairs % kWave) return fail(TRIG_EINVAL, "tile_pairs not a multiple of 64");
-    if (p->block_events < 0 || p->block_events > kMaxEB) return fail(TRIG_EINVAL, "block_events outside 0..256");
+    if (p->block_events < 0 || p->block_events > kMaxEB) return fail(TRIG_EINVAL, "block_events outside 0..128");
     for (int r : p->reserved)
         if (r) return fail(TRIG_EINVAL, "reserved fields must be zero");
     const uint32_t known = TRIG_EXEC_PERSISTENT | TRIG_EXEC_PRUNED | TRIG_EXEC_BINNED |
@@ -514,22 +515,27 @@ int launch_persistent(const trig_events_csr* ev, const trig_hits* h, const Const
 
 __global__ void k_zero_u32(unsigned* p) { *p = 0u; }
 
-// Events per block for the batched form: about 60 % of the LDS hit capacity
-// at the batch's mean multiplicity, leaving room for fluctuations (blocks
-// that overflow are split into sub-blocks by the kernel).
-int choose_block_events(const trig_params* p, int n_events, int n_hits) {
-    if (p->block_events > 0) return p->block_events;
-    const double mean = n_events > 0 ? (double)n_hits / n_events : 1.0;
-    const double eb = 0.6 * kBlockHits / std::max(mean, 1.0);
-    return (int)std::max(1.0, std::min((double)kMaxEB, std::floor(eb)));
+// LDS hit capacity and events per block for the batched form: the small
+// capacity unless an average block would hold fewer than 8 events; events
+// per block about 60 % of capacity at the batch's mean multiplicity, leaving
+// room for fluctuations (blocks that overflow are split into sub-blocks).
+struct BlockShape {
+    int hb, eb;
+};
+BlockShape choose_block_shape(const trig_params* p, int n_events, int n_hits) {
+    const double mean = std::max(n_events > 0 ? (double)n_hits / n_events : 1.0, 1.0);
+    const int hb = 0.6 * kBlockHitsSmall / mean >= 8.0 ? kBlockHitsSmall : kBlockHitsLarge;
+    int eb = p->block_events;
+    if (eb <= 0) eb = (int)std::max(1.0, std::min((double)kMaxEB, std::floor(0.6 * hb / mean)));
+    return {hb, eb};
 }
 
 template <class P>
 int launch_block(const trig_events_csr* ev, const trig_hits* h, const trig_params* p, const Consts& c,
                  const Layout& L, char* ws, int32_t* counts, uint8_t* accept, hipStream_t s) {
     const int n = ev->n_events;
-    const int eb = choose_block_events(p, n, h->n_hits);
-    const int n_blocks = (int)cdiv(n, eb);
+    const BlockShape bs = choose_block_shape(p, n, h->n_hits);
+    const int n_blocks = (int)cdiv(n, bs.eb);
     unsigned* counter = nullptr;
     unsigned grid = (unsigned)n_blocks;
     if (p->flags & TRIG_EXEC_PERSISTENT) {
@@ -538,10 +544,16 @@ int launch_block(const trig_events_csr* ev, const trig_hits* h, const trig_param
         if (int r = check_launch("k_zero_u32")) return r;
         grid = (unsigned)std::min<int64_t>(n_blocks, (int64_t)device_cus() * kBlockResident);
     }
-    if (mark_start(s)) return fail(TRIG_EHIP, "hipEventRecord(start)");
     const int vec = ((reinterpret_cast<uintptr_t>(h->x) | reinterpret_cast<uintptr_t>(h->y)) & 15) == 0;
-    hipLaunchKernelGGL((k_block<P, kBlockHits>), dim3(grid), dim3(kBlockThreads), 0, s, ev->layer_offsets, n,
-                       h->x, h->y, c, eb, n_blocks, counter, vec, counts, accept, p->out_status);
+    if (mark_start(s)) return fail(TRIG_EHIP, "hipEventRecord(start)");
+    if (bs.hb == kBlockHitsSmall)
+        hipLaunchKernelGGL((k_block<P, kBlockHitsSmall>), dim3(grid), dim3(kBlockThreads), 0, s,
+                           ev->layer_offsets, n, h->x, h->y, c, bs.eb, n_blocks, counter, vec, counts, accept,
+                           p->out_status);
+    else
+        hipLaunchKernelGGL((k_block<P, kBlockHitsLarge>), dim3(grid), dim3(kBlockThreads), 0, s,
+                           ev->layer_offsets, n, h->x, h->y, c, bs.eb, n_blocks, counter, vec, counts, accept,
+                           p->out_status);
     if (int r = check_launch("k_block")) return r;
     if (mark_stop(s)) return fail(TRIG_EHIP, "hipEventRecord(stop)");
     return TRIG_OK;

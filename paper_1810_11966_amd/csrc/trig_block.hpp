@@ -32,8 +32,33 @@ namespace trig {
 
 constexpr int kBlockThreads = 256;
 constexpr int kBlockWaves = kBlockThreads / kWave;
-constexpr int kPBuf = 256;     // per-wave buffer of layer-0 values (float2)
-constexpr int kMaxEB = 256;    // events per block at most
+constexpr int kPBuf = 128;     // per-wave buffer of layer-0 values (float2)
+constexpr int kMaxEB = 128;    // events per block at most
+
+// Lane-layout constants by layer-1 size n (1..64), looked up instead of
+// divided: rep = copies of layer 1 per wave (64 / n for n <= 32, else 1),
+// chunk = layer-0 hits per buffer fill (a multiple of rep), inv = ceil(2^20/n)
+// so that (a * inv) >> 20 == a / n exactly for 0 <= a < 2^20 / 64.
+struct LaneTables {
+    uint8_t rep[65];
+    uint8_t chunk[65];
+    uint32_t inv[65];
+};
+constexpr LaneTables make_lane_tables() {
+    LaneTables t{};
+    for (int n = 1; n <= 64; ++n) {
+        const int r = n <= kWave / 2 ? kWave / n : 1;
+        t.rep[n] = (uint8_t)r;
+        t.chunk[n] = (uint8_t)((kPBuf / r) * r);
+        t.inv[n] = (uint32_t)(((1u << 20) + n - 1) / n);
+    }
+    return t;
+}
+__constant__ LaneTables kLane = make_lane_tables();
+
+__device__ __forceinline__ int div_small(int a, int n) {  // a / n for 0 <= a < 16384, 1 <= n <= 64
+    return (int)(((uint32_t)a * kLane.inv[n]) >> 20);
+}
 
 // Hits of the current sub-block in LDS (structure of arrays), indexed
 // relative to the staged range's 4-aligned start.
@@ -130,25 +155,23 @@ template <class P, class H>
 __device__ uint32_t wave_event_pruned(const Consts& c, const H& hits, int o0, int n0, int o1, int n1,
                                       int o2, int n2, float2* __restrict__ pbuf) {
     const int lane = (int)lane_id();
-    const int R = n1 <= kWave / 2 ? kWave / n1 : 1;  // copies of layer 1 per wave
+    const int nt = min(n1, kWave);                // layer-1 size of the table row
+    const int R = kLane.rep[nt];                  // copies of layer 1 per wave
+    const int chunk = kLane.chunk[nt];            // layer-0 hits per buffer fill
     uint32_t cnt = 0;
     for (int jc = 0; jc < n1; jc += kWave) {
-        int g, j;
+        int g = 0, j = jc + lane;
         if (R > 1) {
-            g = (int)(((float)lane + 0.5f) * (1.0f / (float)n1));  // floor(lane / n1), exact
+            g = div_small(lane, n1);              // floor(lane / n1)
             j = lane - g * n1;
-        } else {
-            g = 0;
-            j = jc + lane;
         }
         const bool jv = (g < R) && (j < n1);
         if (!jv) g = 0;
         const float2 q = jv ? P::layer1(c, hits.at(o1 + j)) : nan2();
-        const int chunk = (kPBuf / R) * R;  // layer-0 hits per buffer fill
         for (int ic = 0; ic < n0; ic += chunk) {
             const int ni = min(chunk, n0 - ic);
-            const int T = (ni + R - 1) / R;
-            const int npad = T * R;  // <= chunk <= kPBuf
+            const int T = div_small(ni + R - 1, R);  // ceil(ni / R)
+            const int npad = T * R;                  // <= chunk <= kPBuf
             for (int t = lane; t < npad; t += kWave)
                 pbuf[t] = t < ni ? P::layer0(c, hits.at(o0 + ic + t)) : nan2();
             wave_lds_sync();
@@ -164,15 +187,13 @@ __device__ uint32_t wave_event_pruned(const Consts& c, const H& hits, int o0, in
             };
             const float2* pp = pbuf + g;
             int t = 0;
-            for (; t + 4 <= T; t += 4) {
-                const float2 p0 = pp[R * t], p1 = pp[R * (t + 1)], p2 = pp[R * (t + 2)], p3 = pp[R * (t + 3)];
-                const uint64_t m0 = P::pair_mask(c, p0, q), m1 = P::pair_mask(c, p1, q);
-                const uint64_t m2 = P::pair_mask(c, p2, q), m3 = P::pair_mask(c, p3, q);
-                if ((m0 | m1 | m2 | m3) != 0ull) {
-                    finish(m0, t);
-                    finish(m1, t + 1);
-                    finish(m2, t + 2);
-                    finish(m3, t + 3);
+            for (; t + 8 <= T; t += 8) {
+                uint64_t m[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) m[u] = P::pair_mask(c, pp[R * (t + u)], q);
+                if ((m[0] | m[1] | m[2] | m[3] | m[4] | m[5] | m[6] | m[7]) != 0ull) {
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) finish(m[u], t + u);
                 }
             }
             for (; t < T; ++t) {
@@ -193,7 +214,8 @@ __device__ void wave_event(const Consts& c, const H& hits, int h_base, int o0, i
                            int e, int32_t* counts, uint8_t* accept, uint32_t* status, float2* pbuf) {
     const int n0 = o1 - o0, n1 = o2 - o1, n2 = o3 - o2;
     int32_t cnt = 0;
-    if (n2 > 0 && (int64_t)n0 * n1 > (int64_t)INT32_MAX / n2) {
+    const int64_t n01 = (int64_t)n0 * n1;  // < 2^62; if <= INT32_MAX then n01 * n2 < 2^62
+    if (n2 > 0 && (n01 > (int64_t)INT32_MAX || n01 * n2 > (int64_t)INT32_MAX)) {
         cnt = -2;
     } else if (n0 > 0 && n1 > 0 && n2 > 0) {
         cnt = (int32_t)wave_event_pruned<P>(c, hits, o0 - h_base, n0, o1 - h_base, n1, o2 - h_base, n2, pbuf);
@@ -273,7 +295,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_block(const int32_t* __restri
     // HB hits plus up to 3 before the first and 3 after the last (4-aligned copy)
     __shared__ __align__(16) float stage_x[HB + 8];
     __shared__ __align__(16) float stage_y[HB + 8];
-    __shared__ float2 pbuf_all[kBlockWaves][kPBuf];
+    __shared__ __align__(16) float2 pbuf_all[kBlockWaves][kPBuf];
     __shared__ int32_t soff[3 * kMaxEB + 1];
     __shared__ int s_block, s_bad;
     const int w = uniform_i(threadIdx.x / kWave);

@@ -144,7 +144,7 @@ def test_block_shapes_and_large_events(gpu):
     s = synth.concat([base.subset(0, 1000), big, base.subset(1000, 2000)])
     for test in ("msd", "window"):
         for form in ("pruned", "persistent_pruned"):
-            for eb in (0, 1, 7, 64, 256):
+            for eb in (0, 1, 7, 64, 128):
                 assert_parity(gpu, s, test, form, f"block_events={eb}", block_events=eb)
     dense = synth.make_event_set(synth.DENSE_100K, n_events=300)
     for eb in (1, 5, 40):
