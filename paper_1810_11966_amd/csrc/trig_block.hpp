@@ -35,29 +35,15 @@ constexpr int kBlockWaves = kBlockThreads / kWave;
 constexpr int kPBuf = 128;     // per-wave buffer of layer-0 values (float2)
 constexpr int kMaxEB = 128;    // events per block at most
 
-// Lane-layout constants by layer-1 size n (1..64), looked up instead of
-// divided: rep = copies of layer 1 per wave (64 / n for n <= 32, else 1),
-// chunk = layer-0 hits per buffer fill (a multiple of rep), inv = ceil(2^20/n)
-// so that (a * inv) >> 20 == a / n exactly for 0 <= a < 2^20 / 64.
-struct LaneTables {
-    uint8_t rep[65];
-    uint8_t chunk[65];
-    uint32_t inv[65];
-};
-constexpr LaneTables make_lane_tables() {
-    LaneTables t{};
-    for (int n = 1; n <= 64; ++n) {
-        const int r = n <= kWave / 2 ? kWave / n : 1;
-        t.rep[n] = (uint8_t)r;
-        t.chunk[n] = (uint8_t)((kPBuf / r) * r);
-        t.inv[n] = (uint32_t)(((1u << 20) + n - 1) / n);
-    }
-    return t;
-}
-__constant__ LaneTables kLane = make_lane_tables();
-
-__device__ __forceinline__ int div_small(int a, int n) {  // a / n for 0 <= a < 16384, 1 <= n <= 64
-    return (int)(((uint32_t)a * kLane.inv[n]) >> 20);
+// Small exact quotients without integer division: for 0 <= a < 4096 and
+// 1 <= n <= 256, a / n = floor(a * rcp(n) + 2^-10), rcp the hardware
+// reciprocal.  The computed product is within (a/n) 2^-22 <= 2^-10 of a/n
+// (relative error of rcp and of the product below 2^-22 together), so an
+// exact quotient q is reached again after adding 2^-10; otherwise a/n lies
+// at least 1/n >= 2^-8 below q + 1, and error plus 2^-10 stays below that
+// (and far from q + 1 in binary32 spacing, 2^-11 at most here).
+__device__ __forceinline__ int div_small(int a, int n) {
+    return (int)((float)a * __builtin_amdgcn_rcpf((float)n) + 0.0009765625f);
 }
 
 // Hits of the current sub-block in LDS (structure of arrays), indexed
@@ -155,14 +141,17 @@ template <class P, class H>
 __device__ uint32_t wave_event_pruned(const Consts& c, const H& hits, int o0, int n0, int o1, int n1,
                                       int o2, int n2, float2* __restrict__ pbuf) {
     const int lane = (int)lane_id();
-    const int nt = min(n1, kWave);                // layer-1 size of the table row
-    const int R = kLane.rep[nt];                  // copies of layer 1 per wave
-    const int chunk = kLane.chunk[nt];            // layer-0 hits per buffer fill
+    // R copies of layer 1 per wave (R = min(64 / n1, kPBuf / 4) for n1 <= 32,
+    // else 1); a buffer fill holds `chunk` layer-0 hits, a positive multiple
+    // of 4R <= kPBuf, so that every copy scans a multiple of 4 entries (NaN
+    // padding fails every test).
+    const int R = uniform_i(n1 <= kWave / 2 ? min(div_small(kWave, n1), kPBuf / 4) : 1);
+    const int chunk = uniform_i(div_small(kPBuf, 4 * R) * 4 * R);
     uint32_t cnt = 0;
     for (int jc = 0; jc < n1; jc += kWave) {
         int g = 0, j = jc + lane;
         if (R > 1) {
-            g = div_small(lane, n1);              // floor(lane / n1)
+            g = div_small(lane, n1);  // floor(lane / n1)
             j = lane - g * n1;
         }
         const bool jv = (g < R) && (j < n1);
@@ -170,8 +159,8 @@ __device__ uint32_t wave_event_pruned(const Consts& c, const H& hits, int o0, in
         const float2 q = jv ? P::layer1(c, hits.at(o1 + j)) : nan2();
         for (int ic = 0; ic < n0; ic += chunk) {
             const int ni = min(chunk, n0 - ic);
-            const int T = div_small(ni + R - 1, R);  // ceil(ni / R)
-            const int npad = T * R;                  // <= chunk <= kPBuf
+            const int T = uniform_i((div_small(ni + 4 * R - 1, 4 * R)) * 4);  // per copy, multiple of 4
+            const int npad = T * R;                                           // <= chunk <= kPBuf
             for (int t = lane; t < npad; t += kWave)
                 pbuf[t] = t < ni ? P::layer0(c, hits.at(o0 + ic + t)) : nan2();
             wave_lds_sync();
@@ -186,19 +175,17 @@ __device__ uint32_t wave_event_pruned(const Consts& c, const H& hits, int o0, in
                 }
             };
             const float2* pp = pbuf + g;
-            int t = 0;
-            for (; t + 8 <= T; t += 8) {
-                uint64_t m[8];
-#pragma unroll
-                for (int u = 0; u < 8; ++u) m[u] = P::pair_mask(c, pp[R * (t + u)], q);
-                if ((m[0] | m[1] | m[2] | m[3] | m[4] | m[5] | m[6] | m[7]) != 0ull) {
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) finish(m[u], t + u);
+            for (int t = 0; t < T; t += 4) {
+                const uint64_t m0 = P::pair_mask(c, pp[R * t], q);
+                const uint64_t m1 = P::pair_mask(c, pp[R * (t + 1)], q);
+                const uint64_t m2 = P::pair_mask(c, pp[R * (t + 2)], q);
+                const uint64_t m3 = P::pair_mask(c, pp[R * (t + 3)], q);
+                if ((m0 | m1 | m2 | m3) != 0ull) {
+                    finish(m0, t);
+                    finish(m1, t + 1);
+                    finish(m2, t + 2);
+                    finish(m3, t + 3);
                 }
-            }
-            for (; t < T; ++t) {
-                const uint64_t m = P::pair_mask(c, pp[R * t], q);
-                if (m) finish(m, t);
             }
             wave_lds_sync();
         }

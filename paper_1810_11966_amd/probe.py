@@ -41,3 +41,25 @@ def measure_copy(torch, nbytes: int = 1 << 30, reps: int = 5, n_blocks: int = 25
         if r:
             best = max(best, 32.0 * n_vec4 / (a.elapsed_ms(b) * 1e-3))
     return best
+
+
+def main(argv=None):
+    import argparse
+    import sys
+    import torch
+    ap = argparse.ArgumentParser(description="device ceilings: fp32 VALU rate, copy bandwidth")
+    ap.add_argument("--valu", action="store_true")
+    ap.add_argument("--copy", type=int, default=0, metavar="BYTES", help="copy probe over BYTES of input")
+    ap.add_argument("--reps", type=int, default=3)
+    a = ap.parse_args(argv)
+    trig.load()
+    if a.valu:
+        print(f"valu {measure_valu(torch, reps=a.reps) / 1e12:.2f} T fp32 ops/s", flush=True)
+    if a.copy:
+        print(f"copy {a.copy} B: {measure_copy(torch, nbytes=a.copy, reps=a.reps) / 1e9:.0f} GB/s (read+write)",
+              flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    raise SystemExit(main())
