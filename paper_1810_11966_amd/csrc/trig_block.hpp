@@ -136,17 +136,20 @@ struct WindowPrune {
 };
 
 // Passing triplets of one event (all layers non-empty), by one wave.
-// o0, o1, o2 index `hits`; pbuf is this wave's kPBuf-entry LDS buffer.
+// o0, o1, o2 index `hits`; px/py are this wave's kPBuf-entry LDS buffers
+// (16-byte aligned) for the layer-0 partials.
+//
+// Layout: lane L holds layer-1 hit j and copy number g; with R copies of
+// layer 1 (R = min(64 / n1, kPBuf / 4) for n1 <= 32, else 1) copy g scans the
+// contiguous layer-0 slice [g T, g T + T) of the current buffer fill, T a
+// multiple of 4, so one 16-byte LDS read per coordinate serves four pairs.
+// Buffer entries past the event's layer-0 hits hold NaN and fail every test.
 template <class P, class H>
 __device__ uint32_t wave_event_pruned(const Consts& c, const H& hits, int o0, int n0, int o1, int n1,
-                                      int o2, int n2, float2* __restrict__ pbuf) {
+                                      int o2, int n2, float* __restrict__ px, float* __restrict__ py) {
     const int lane = (int)lane_id();
-    // R copies of layer 1 per wave (R = min(64 / n1, kPBuf / 4) for n1 <= 32,
-    // else 1); a buffer fill holds `chunk` layer-0 hits, a positive multiple
-    // of 4R <= kPBuf, so that every copy scans a multiple of 4 entries (NaN
-    // padding fails every test).
     const int R = uniform_i(n1 <= kWave / 2 ? min(div_small(kWave, n1), kPBuf / 4) : 1);
-    const int chunk = uniform_i(div_small(kPBuf, 4 * R) * 4 * R);
+    const int chunk = uniform_i(div_small(kPBuf, 4 * R) * 4 * R);  // a positive multiple of 4R
     uint32_t cnt = 0;
     for (int jc = 0; jc < n1; jc += kWave) {
         int g = 0, j = jc + lane;
@@ -159,27 +162,32 @@ __device__ uint32_t wave_event_pruned(const Consts& c, const H& hits, int o0, in
         const float2 q = jv ? P::layer1(c, hits.at(o1 + j)) : nan2();
         for (int ic = 0; ic < n0; ic += chunk) {
             const int ni = min(chunk, n0 - ic);
-            const int T = uniform_i((div_small(ni + 4 * R - 1, 4 * R)) * 4);  // per copy, multiple of 4
-            const int npad = T * R;                                           // <= chunk <= kPBuf
-            for (int t = lane; t < npad; t += kWave)
-                pbuf[t] = t < ni ? P::layer0(c, hits.at(o0 + ic + t)) : nan2();
+            const int T = uniform_i(div_small(ni + 4 * R - 1, 4 * R) * 4);  // per copy, multiple of 4
+            const int npad = T * R;                                          // <= chunk <= kPBuf
+            for (int t = lane; t < npad; t += kWave) {
+                const float2 v = t < ni ? P::layer0(c, hits.at(o0 + ic + t)) : nan2();
+                px[t] = v.x;
+                py[t] = v.y;
+            }
             wave_lds_sync();
-            // Survivors of 64 pairs (lane -> pair (ic + g + R t, j)).
+            // Survivors among the lanes' pairs (ic + g T + t, j).
             auto finish = [&](uint64_t m, int t) {
                 while (m) {
                     const int L = __builtin_ctzll(m);
                     m &= m - 1;
-                    const int iL = __builtin_amdgcn_readlane(g, L) + R * t;
+                    const int iL = __builtin_amdgcn_readlane(g, L) * T + t;
                     const int jL = __builtin_amdgcn_readlane(j, L);
                     cnt += P::complete(c, hits, o0 + ic + iL, o1 + jL, o2, n2);
                 }
             };
-            const float2* pp = pbuf + g;
+            const float4* ppx = reinterpret_cast<const float4*>(px + g * T);
+            const float4* ppy = reinterpret_cast<const float4*>(py + g * T);
             for (int t = 0; t < T; t += 4) {
-                const uint64_t m0 = P::pair_mask(c, pp[R * t], q);
-                const uint64_t m1 = P::pair_mask(c, pp[R * (t + 1)], q);
-                const uint64_t m2 = P::pair_mask(c, pp[R * (t + 2)], q);
-                const uint64_t m3 = P::pair_mask(c, pp[R * (t + 3)], q);
+                const float4 vx = ppx[t >> 2], vy = ppy[t >> 2];
+                const uint64_t m0 = P::pair_mask(c, make_float2(vx.x, vy.x), q);
+                const uint64_t m1 = P::pair_mask(c, make_float2(vx.y, vy.y), q);
+                const uint64_t m2 = P::pair_mask(c, make_float2(vx.z, vy.z), q);
+                const uint64_t m3 = P::pair_mask(c, make_float2(vx.w, vy.w), q);
                 if ((m0 | m1 | m2 | m3) != 0ull) {
                     finish(m0, t);
                     finish(m1, t + 1);
@@ -198,14 +206,14 @@ __device__ uint32_t wave_event_pruned(const Consts& c, const H& hits, int o0, in
 // hit arrays (0 for GlobalHits).
 template <class P, class H>
 __device__ void wave_event(const Consts& c, const H& hits, int h_base, int o0, int o1, int o2, int o3,
-                           int e, int32_t* counts, uint8_t* accept, uint32_t* status, float2* pbuf) {
+                           int e, int32_t* counts, uint8_t* accept, uint32_t* status, float* px, float* py) {
     const int n0 = o1 - o0, n1 = o2 - o1, n2 = o3 - o2;
     int32_t cnt = 0;
     const int64_t n01 = (int64_t)n0 * n1;  // < 2^62; if <= INT32_MAX then n01 * n2 < 2^62
     if (n2 > 0 && (n01 > (int64_t)INT32_MAX || n01 * n2 > (int64_t)INT32_MAX)) {
         cnt = -2;
     } else if (n0 > 0 && n1 > 0 && n2 > 0) {
-        cnt = (int32_t)wave_event_pruned<P>(c, hits, o0 - h_base, n0, o1 - h_base, n1, o2 - h_base, n2, pbuf);
+        cnt = (int32_t)wave_event_pruned<P>(c, hits, o0 - h_base, n0, o1 - h_base, n1, o2 - h_base, n2, px, py);
     }
     if (lane_id() == 0) {
         counts[e] = cnt;
@@ -282,11 +290,13 @@ __global__ __launch_bounds__(kBlockThreads) void k_block(const int32_t* __restri
     // HB hits plus up to 3 before the first and 3 after the last (4-aligned copy)
     __shared__ __align__(16) float stage_x[HB + 8];
     __shared__ __align__(16) float stage_y[HB + 8];
-    __shared__ __align__(16) float2 pbuf_all[kBlockWaves][kPBuf];
+    __shared__ __align__(16) float pbuf_x[kBlockWaves][kPBuf];
+    __shared__ __align__(16) float pbuf_y[kBlockWaves][kPBuf];
     __shared__ int32_t soff[3 * kMaxEB + 1];
     __shared__ int s_block, s_bad;
     const int w = uniform_i(threadIdx.x / kWave);
-    float2* pbuf = pbuf_all[w];
+    float* px = pbuf_x[w];
+    float* py = pbuf_y[w];
     const GlobalHits ghits{x, y};
     int iter = 0;
     for (;; ++iter) {
@@ -320,7 +330,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_block(const int32_t* __restri
             for (int t = w; t < ne; t += kBlockWaves) {
                 const int a0 = soff[3 * t], a1 = soff[3 * t + 1], a2 = soff[3 * t + 2], a3 = soff[3 * t + 3];
                 if (0 <= a0 && a0 <= a1 && a1 <= a2 && a2 <= a3 && a3 <= c.n_hits)
-                    wave_event<P>(c, ghits, 0, a0, a1, a2, a3, e0 + t, counts, accept, status, pbuf);
+                    wave_event<P>(c, ghits, 0, a0, a1, a2, a3, e0 + t, counts, accept, status, px, py);
             }
             __syncthreads();
             if (!block_counter) break;
@@ -338,7 +348,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_block(const int32_t* __restri
                 // One event larger than LDS: wave 0 reads it from HBM.
                 if (w == 0)
                     wave_event<P>(c, ghits, 0, soff[3 * cur], soff[3 * cur + 1], soff[3 * cur + 2],
-                                  soff[3 * cur + 3], e0 + cur, counts, accept, status, pbuf);
+                                  soff[3 * cur + 3], e0 + cur, counts, accept, status, px, py);
                 __syncthreads();
                 cur += 1;
                 continue;
@@ -353,7 +363,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_block(const int32_t* __restri
             const int a0 = base & ~3;
             for (int ev = cur + w; ev < end; ev += kBlockWaves)
                 wave_event<P>(c, lh, a0, soff[3 * ev], soff[3 * ev + 1], soff[3 * ev + 2], soff[3 * ev + 3],
-                              e0 + ev, counts, accept, status, pbuf);
+                              e0 + ev, counts, accept, status, px, py);
             __syncthreads();
             cur = end;
         }
