@@ -159,7 +159,11 @@ typedef struct {
     int32_t block_events;       /* TRIG_EXEC_PRUNED: events per workgroup block
                                    (1..128; 0 = chosen from the mean number of
                                    hits per event) */
-    int32_t reserved[6];        /* must be zero */
+    int32_t block_hits;         /* TRIG_EXEC_PRUNED: LDS hit capacity of a
+                                   workgroup: 1024, 2048 or 4096 (0 = chosen) */
+    int32_t block_waves;        /* TRIG_EXEC_PRUNED: waves per workgroup: 1, 2
+                                   or 4 (0 = chosen) */
+    int32_t reserved[4];        /* must be zero */
 } trig_params;
 
 /* Fill *p (host) with the defaults above.  Returns TRIG_OK or TRIG_EINVAL for
@@ -183,7 +187,8 @@ size_t trig_workspace_bytes(const trig_events_csr *ev, const trig_params *p);
  * required pointer, n_events < 0, n_hits < 0, an ABI mismatch, non-finite or
  * non-positive z, a negative or NaN threshold or window, ndf < 1,
  * min_triplets < 0, tile_pairs not a non-negative multiple of 64,
- * block_events outside 0..128, non-zero reserved fields; TRIG_EWORKSPACE; TRIG_EUNSUPPORTED.  TRIG_EHIP if a launch
+ * block_events outside 0..128, block_hits or block_waves not one of the listed
+ * values, non-zero reserved fields; TRIG_EWORKSPACE; TRIG_EUNSUPPORTED.  TRIG_EHIP if a launch
  * fails.  n_events == 0 enqueues only the compaction count (0), if requested.
  * Data-dependent problems are reported per event (see TRIG_COUNT_*) without a
  * host synchronisation.  Concurrent calls on different streams need distinct

@@ -42,9 +42,7 @@ constexpr int kCompactItems = 4;    // events per thread in compaction
 constexpr int kPersistWaves = 4;    // waves per workgroup, persistent form
 constexpr int kPersistBatch = 4;    // work units taken per atomic
 constexpr int kDefaultTileUnits = 8;  // pair tiles (of 64 pairs) per work unit
-constexpr int kBlockHitsSmall = 2048;  // LDS hit capacities of a batched-form workgroup
-constexpr int kBlockHitsLarge = 4096;
-constexpr int kBlockResident = 6;      // batched workgroups per CU (LDS-limited)
+constexpr int kBlockResident = 8;      // persistent batched workgroups per CU
 
 template <class T>
 struct Chunk;
@@ -409,6 +407,10 @@ int validate(const trig_events_csr* ev, const trig_hits* hits, const trig_params
     if (p->min_triplets < 0) return fail(TRIG_EINVAL, "min_triplets < 0");
     if (p->tile_pairs < 0 || p->tile_pairs % kWave) return fail(TRIG_EINVAL, "tile_pairs not a multiple of 64");
     if (p->block_events < 0 || p->block_events > kMaxEB) return fail(TRIG_EINVAL, "block_events outside 0..128");
+    if (p->block_hits != 0 && p->block_hits != 1024 && p->block_hits != 2048 && p->block_hits != 4096)
+        return fail(TRIG_EINVAL, "block_hits must be 0, 1024, 2048 or 4096");
+    if (p->block_waves != 0 && p->block_waves != 1 && p->block_waves != 2 && p->block_waves != 4)
+        return fail(TRIG_EINVAL, "block_waves must be 0, 1, 2 or 4");
     for (int r : p->reserved)
         if (r) return fail(TRIG_EINVAL, "reserved fields must be zero");
     const uint32_t known = TRIG_EXEC_PERSISTENT | TRIG_EXEC_PRUNED | TRIG_EXEC_BINNED |
@@ -515,19 +517,37 @@ int launch_persistent(const trig_events_csr* ev, const trig_hits* h, const Const
 
 __global__ void k_zero_u32(unsigned* p) { *p = 0u; }
 
-// LDS hit capacity and events per block for the batched form: the small
-// capacity unless an average block would hold fewer than 8 events; events
-// per block about 60 % of capacity at the batch's mean multiplicity, leaving
-// room for fluctuations (blocks that overflow are split into sub-blocks).
+// Shape of the batched form: LDS hit capacity (hb), waves per workgroup (nw)
+// and events per block (eb).  Given values are used as they are; the
+// defaults take the largest capacity whose block holds at least 8 events of
+// the batch's mean multiplicity at 60 % fill (fluctuations fit; blocks that
+// overflow are split into sub-blocks by the kernel), one wave per 1024 hits.
 struct BlockShape {
-    int hb, eb;
+    int hb, nw, eb;
 };
 BlockShape choose_block_shape(const trig_params* p, int n_events, int n_hits) {
     const double mean = std::max(n_events > 0 ? (double)n_hits / n_events : 1.0, 1.0);
-    const int hb = 0.6 * kBlockHitsSmall / mean >= 8.0 ? kBlockHitsSmall : kBlockHitsLarge;
+    int hb = p->block_hits;
+    if (hb <= 0) hb = 0.6 * 1024 / mean >= 8.0 ? 1024 : 0.6 * 2048 / mean >= 8.0 ? 2048 : 4096;
+    int nw = p->block_waves;
+    if (nw <= 0) nw = hb / 1024;
     int eb = p->block_events;
     if (eb <= 0) eb = (int)std::max(1.0, std::min((double)kMaxEB, std::floor(0.6 * hb / mean)));
-    return {hb, eb};
+    return {hb, nw, eb};
+}
+
+using BlockKernel = void (*)(const int32_t*, int, const float*, const float*, Consts, int, int, unsigned*, int,
+                             int32_t*, uint8_t*, uint32_t*);
+
+template <class P>
+BlockKernel block_kernel(int hb, int nw) {
+#define TRIG_BLOCK_CASE(H, W) \
+    if (hb == H && nw == W) return k_block<P, H, W>;
+    TRIG_BLOCK_CASE(1024, 1) TRIG_BLOCK_CASE(1024, 2) TRIG_BLOCK_CASE(1024, 4)
+    TRIG_BLOCK_CASE(2048, 1) TRIG_BLOCK_CASE(2048, 2) TRIG_BLOCK_CASE(2048, 4)
+    TRIG_BLOCK_CASE(4096, 1) TRIG_BLOCK_CASE(4096, 2) TRIG_BLOCK_CASE(4096, 4)
+#undef TRIG_BLOCK_CASE
+    return nullptr;
 }
 
 template <class P>
@@ -535,6 +555,8 @@ int launch_block(const trig_events_csr* ev, const trig_hits* h, const trig_param
                  const Layout& L, char* ws, int32_t* counts, uint8_t* accept, hipStream_t s) {
     const int n = ev->n_events;
     const BlockShape bs = choose_block_shape(p, n, h->n_hits);
+    const BlockKernel kern = block_kernel<P>(bs.hb, bs.nw);
+    if (!kern) return fail(TRIG_EINVAL, "block_hits must be 1024, 2048 or 4096 and block_waves 1, 2 or 4");
     const int n_blocks = (int)cdiv(n, bs.eb);
     unsigned* counter = nullptr;
     unsigned grid = (unsigned)n_blocks;
@@ -542,18 +564,12 @@ int launch_block(const trig_events_csr* ev, const trig_hits* h, const trig_param
         counter = reinterpret_cast<unsigned*>(ws + L.counter_off);
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, counter);
         if (int r = check_launch("k_zero_u32")) return r;
-        grid = (unsigned)std::min<int64_t>(n_blocks, (int64_t)device_cus() * kBlockResident);
+        grid = (unsigned)std::min<int64_t>(n_blocks, (int64_t)device_cus() * kBlockResident * (4 / bs.nw));
     }
     const int vec = ((reinterpret_cast<uintptr_t>(h->x) | reinterpret_cast<uintptr_t>(h->y)) & 15) == 0;
     if (mark_start(s)) return fail(TRIG_EHIP, "hipEventRecord(start)");
-    if (bs.hb == kBlockHitsSmall)
-        hipLaunchKernelGGL((k_block<P, kBlockHitsSmall>), dim3(grid), dim3(kBlockThreads), 0, s,
-                           ev->layer_offsets, n, h->x, h->y, c, bs.eb, n_blocks, counter, vec, counts, accept,
-                           p->out_status);
-    else
-        hipLaunchKernelGGL((k_block<P, kBlockHitsLarge>), dim3(grid), dim3(kBlockThreads), 0, s,
-                           ev->layer_offsets, n, h->x, h->y, c, bs.eb, n_blocks, counter, vec, counts, accept,
-                           p->out_status);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(bs.nw * kWave), 0, s, ev->layer_offsets, n, h->x, h->y, c, bs.eb,
+                       n_blocks, counter, vec, counts, accept, p->out_status);
     if (int r = check_launch("k_block")) return r;
     if (mark_stop(s)) return fail(TRIG_EHIP, "hipEventRecord(stop)");
     return TRIG_OK;

@@ -30,8 +30,6 @@
 
 namespace trig {
 
-constexpr int kBlockThreads = 256;
-constexpr int kBlockWaves = kBlockThreads / kWave;
 constexpr int kPBuf = 128;     // per-wave buffer of layer-0 values (float2)
 constexpr int kMaxEB = 128;    // events per block at most
 
@@ -231,10 +229,10 @@ __device__ void wave_event(const Consts& c, const H& hits, int h_base, int o0, i
 // The one float4 group that would cross n_hits is copied element by element
 // by thread 0.  Needs x and y 16-byte aligned (checked by the host; `vec`
 // false otherwise: plain 4-byte loads).
-template <int HB>
+template <int HB, int NT>
 __device__ __forceinline__ void stage_hits(const float* __restrict__ x, const float* __restrict__ y,
                                            int base, int nh, int n_hits, bool vec, float* xs, float* ys) {
-    constexpr int Q = (HB + 6) / 4 / kBlockThreads + 1;  // float4 groups per thread, upper bound
+    constexpr int Q = (HB + 6) / 4 / NT + 1;  // float4 groups per thread, upper bound
     const int a0 = base & ~3;
     const int nq = (base + nh - a0 + 3) >> 2;             // float4 groups to copy
     const int t = (int)threadIdx.x;
@@ -246,7 +244,7 @@ __device__ __forceinline__ void stage_hits(const float* __restrict__ x, const fl
             float4 vx[Q], vy[Q];
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
-                const int q = min(t + k * kBlockThreads, nq_full - 1);
+                const int q = min(t + k * NT, nq_full - 1);
                 vx[k] = *reinterpret_cast<const float4*>(x + a0 + 4 * q);
                 vy[k] = *reinterpret_cast<const float4*>(y + a0 + 4 * q);
             }
@@ -259,7 +257,7 @@ __device__ __forceinline__ void stage_hits(const float* __restrict__ x, const fl
                              "v"(vy[k].y), "v"(vy[k].z), "v"(vy[k].w));
 #pragma unroll
             for (int k = 0; k < Q; ++k) {
-                const int q = t + k * kBlockThreads;
+                const int q = t + k * NT;
                 if (q < nq_full) {
                     reinterpret_cast<float4*>(xs)[q] = vx[k];
                     reinterpret_cast<float4*>(ys)[q] = vy[k];
@@ -273,15 +271,15 @@ __device__ __forceinline__ void stage_hits(const float* __restrict__ x, const fl
             }
         }
     } else {
-        for (int h = t; h < nh; h += kBlockThreads) {
+        for (int h = t; h < nh; h += NT) {
             xs[base - a0 + h] = x[base + h];
             ys[base - a0 + h] = y[base + h];
         }
     }
 }
 
-template <class P, int HB>
-__global__ __launch_bounds__(kBlockThreads) void k_block(const int32_t* __restrict__ off, int n_events,
+template <class P, int HB, int NW>
+__global__ __launch_bounds__(NW * kWave) void k_block(const int32_t* __restrict__ off, int n_events,
                                                          const float* __restrict__ x,
                                                          const float* __restrict__ y, Consts c, int eb,
                                                          int n_blocks, unsigned* block_counter, int vec,
@@ -290,8 +288,9 @@ __global__ __launch_bounds__(kBlockThreads) void k_block(const int32_t* __restri
     // HB hits plus up to 3 before the first and 3 after the last (4-aligned copy)
     __shared__ __align__(16) float stage_x[HB + 8];
     __shared__ __align__(16) float stage_y[HB + 8];
-    __shared__ __align__(16) float pbuf_x[kBlockWaves][kPBuf];
-    __shared__ __align__(16) float pbuf_y[kBlockWaves][kPBuf];
+    constexpr int NT = NW * kWave;
+    __shared__ __align__(16) float pbuf_x[NW][kPBuf];
+    __shared__ __align__(16) float pbuf_y[NW][kPBuf];
     __shared__ int32_t soff[3 * kMaxEB + 1];
     __shared__ int s_block, s_bad;
     const int w = uniform_i(threadIdx.x / kWave);
@@ -312,10 +311,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_block(const int32_t* __restri
         if (b >= n_blocks) break;
         const int e0 = b * eb;
         const int ne = min(eb, n_events - e0);
-        for (int t = threadIdx.x; t <= 3 * ne; t += kBlockThreads) soff[t] = off[3 * (int64_t)e0 + t];
+        for (int t = threadIdx.x; t <= 3 * ne; t += NT) soff[t] = off[3 * (int64_t)e0 + t];
         __syncthreads();
         // Per-event CSR checks; malformed events get -1 here.
-        for (int t = threadIdx.x; t < ne; t += kBlockThreads) {
+        for (int t = threadIdx.x; t < ne; t += NT) {
             const int a0 = soff[3 * t], a1 = soff[3 * t + 1], a2 = soff[3 * t + 2], a3 = soff[3 * t + 3];
             if (!(0 <= a0 && a0 <= a1 && a1 <= a2 && a2 <= a3 && a3 <= c.n_hits)) {
                 counts[e0 + t] = -1;
@@ -327,7 +326,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_block(const int32_t* __restri
         __syncthreads();
         if (uniform_i(s_bad)) {
             // Irregular block: every well-formed event straight from HBM.
-            for (int t = w; t < ne; t += kBlockWaves) {
+            for (int t = w; t < ne; t += NW) {
                 const int a0 = soff[3 * t], a1 = soff[3 * t + 1], a2 = soff[3 * t + 2], a3 = soff[3 * t + 3];
                 if (0 <= a0 && a0 <= a1 && a1 <= a2 && a2 <= a3 && a3 <= c.n_hits)
                     wave_event<P>(c, ghits, 0, a0, a1, a2, a3, e0 + t, counts, accept, status, px, py);
@@ -342,8 +341,15 @@ __global__ __launch_bounds__(kBlockThreads) void k_block(const int32_t* __restri
         while (cur < ne) {
             const int base = soff[3 * cur];
             const int t = (int)threadIdx.x;
-            const bool fits = (cur + t < ne) && (soff[3 * (cur + t + 1)] - base <= HB);
-            const int nfit = uniform_i(__syncthreads_count(fits));  // fits is a prefix in t
+            // Events from cur on whose hits still fit: a prefix, counted NT at a time.
+            int nfit = 0;
+            for (int t0 = 0;; t0 += NT) {
+                const int tt = t0 + t;
+                const bool fits = (cur + tt < ne) && (soff[3 * (cur + tt + 1)] - base <= HB);
+                const int c1 = uniform_i(__syncthreads_count(fits));
+                nfit += c1;
+                if (c1 < NT) break;
+            }
             if (nfit == 0) {
                 // One event larger than LDS: wave 0 reads it from HBM.
                 if (w == 0)
@@ -355,13 +361,13 @@ __global__ __launch_bounds__(kBlockThreads) void k_block(const int32_t* __restri
             }
             const int end = cur + nfit;
             const int nh = soff[3 * end] - base;
-            stage_hits<HB>(x, y, base, nh, c.n_hits, vec != 0, stage_x, stage_y);
+            stage_hits<HB, NT>(x, y, base, nh, c.n_hits, vec != 0, stage_x, stage_y);
             __syncthreads();
             // Events of the sub-block round-robin over the waves (a static
             // assignment: no per-wave claim loop).
             const LdsHits lh{stage_x, stage_y};
             const int a0 = base & ~3;
-            for (int ev = cur + w; ev < end; ev += kBlockWaves)
+            for (int ev = cur + w; ev < end; ev += NW)
                 wave_event<P>(c, lh, a0, soff[3 * ev], soff[3 * ev + 1], soff[3 * ev + 2], soff[3 * ev + 3],
                               e0 + ev, counts, accept, status, px, py);
             __syncthreads();

@@ -63,7 +63,8 @@ class TrigParams(ctypes.Structure):
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
                 ("out_accepted_ids", ctypes.c_void_p), ("out_n_accepted", ctypes.c_void_p),
                 ("out_status", ctypes.c_void_p), ("tile_pairs", ctypes.c_int32),
-                ("block_events", ctypes.c_int32), ("reserved", ctypes.c_int32 * 6)]
+                ("block_events", ctypes.c_int32), ("block_hits", ctypes.c_int32),
+                ("block_waves", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
 
 
 class TrigError(RuntimeError):
@@ -117,7 +118,8 @@ def trig_params_init() -> TrigParams:
 
 def make_params(test: str = "msd", z=None, msd_max=None, ndf: Optional[int] = None,
                 slope_window=None, min_triplets: Optional[int] = None, flags: int = 0,
-                tile_pairs: int = 0, block_events: int = 0) -> TrigParams:
+                tile_pairs: int = 0, block_events: int = 0, block_hits: int = 0,
+                block_waves: int = 0) -> TrigParams:
     """Defaults from trig_params_init(), overridden by the given values."""
     p = trig_params_init()
     p.test = TESTS[test] if isinstance(test, str) else int(test)
@@ -135,6 +137,8 @@ def make_params(test: str = "msd", z=None, msd_max=None, ndf: Optional[int] = No
     p.flags = int(flags)
     p.tile_pairs = int(tile_pairs)
     p.block_events = int(block_events)
+    p.block_hits = int(block_hits)
+    p.block_waves = int(block_waves)
     return p
 
 
