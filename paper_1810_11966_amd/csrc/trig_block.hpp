@@ -76,6 +76,13 @@ struct MsdPrune {
         const float ay = p.y + q.y;
         return lanes(__builtin_fabsf(ax) <= c.beta_x) & lanes(__builtin_fabsf(ay) <= c.beta_y);
     }
+    // Prefilter score: pair_mask's lane set is within {score <= bound()}.
+    __device__ static __forceinline__ float score(const Consts& c, float2 p, float2 q) {
+        const float ax = p.x + q.x;
+        const float ay = p.y + q.y;
+        return __builtin_fmaxf(__builtin_fabsf(ax), __builtin_fabsf(ay) * c.pre_k_msd);
+    }
+    __device__ static __forceinline__ float bound(const Consts& c) { return c.beta_x; }
     // Passing triplets of the surviving pair (hi, hj) over layer-2 hits
     // [o2, o2 + n2): lanes over k, the binary32 test of include/trig.h.
     template <class H>
@@ -114,6 +121,10 @@ struct WindowPrune {
     __device__ static __forceinline__ uint64_t pair_mask(const Consts& c, float2 p, float2 q) {
         return lanes(__builtin_fabsf(q.x - p.x) < c.win_x) & lanes(__builtin_fabsf(q.y - p.y) < c.win_y);
     }
+    __device__ static __forceinline__ float score(const Consts& c, float2 p, float2 q) {
+        return __builtin_fmaxf(__builtin_fabsf(q.x - p.x), __builtin_fabsf(q.y - p.y) * c.pre_k_win);
+    }
+    __device__ static __forceinline__ float bound(const Consts& c) { return c.win_x; }
     template <class H>
     __device__ static uint32_t complete(const Consts& c, const H& hits, int hi, int /*hj*/, int o2, int n2) {
         const float2 ci = hits.at(hi);
@@ -180,17 +191,22 @@ __device__ uint32_t wave_event_pruned(const Consts& c, const H& hits, int o0, in
             };
             const float4* ppx = reinterpret_cast<const float4*>(px + g * T);
             const float4* ppy = reinterpret_cast<const float4*>(py + g * T);
+            const float bnd = P::bound(c);
             for (int t = 0; t < T; t += 4) {
                 const float4 vx = ppx[t >> 2], vy = ppy[t >> 2];
-                const uint64_t m0 = P::pair_mask(c, make_float2(vx.x, vy.x), q);
-                const uint64_t m1 = P::pair_mask(c, make_float2(vx.y, vy.y), q);
-                const uint64_t m2 = P::pair_mask(c, make_float2(vx.z, vy.z), q);
-                const uint64_t m3 = P::pair_mask(c, make_float2(vx.w, vy.w), q);
-                if ((m0 | m1 | m2 | m3) != 0ull) {
-                    finish(m0, t);
-                    finish(m1, t + 1);
-                    finish(m2, t + 2);
-                    finish(m3, t + 3);
+                // Prefilter on the vector unit: does the smallest of the four
+                // pairs' scores reach the bound?  (fmin drops NaN scores; all
+                // NaN gives NaN, which fails.)
+                const float s0 = P::score(c, make_float2(vx.x, vy.x), q);
+                const float s1 = P::score(c, make_float2(vx.y, vy.y), q);
+                const float s2 = P::score(c, make_float2(vx.z, vy.z), q);
+                const float s3 = P::score(c, make_float2(vx.w, vy.w), q);
+                const float smin = __builtin_fminf(__builtin_fminf(s0, s1), __builtin_fminf(s2, s3));
+                if (wave_any(smin <= bnd)) {
+                    finish(P::pair_mask(c, make_float2(vx.x, vy.x), q), t);
+                    finish(P::pair_mask(c, make_float2(vx.y, vy.y), q), t + 1);
+                    finish(P::pair_mask(c, make_float2(vx.z, vy.z), q), t + 2);
+                    finish(P::pair_mask(c, make_float2(vx.w, vy.w), q), t + 3);
                 }
             }
             wave_lds_sync();

@@ -27,6 +27,11 @@ struct Consts {
     float qmax_x, qmax_y;
     // MSD pair bound: largest binary32 b >= 0 with f32(b * b) <= qmax, per plane
     float beta_x, beta_y;
+    // Pair prefilter of the batched form: one bound and a y-plane scale, so
+    // that (|u| <= bx and |v| <= by) implies max(|u|, f32(|v| * k)) <= bx.
+    // MSD: bx = beta_x, k = largest binary32 with f32(beta_y * k) <= beta_x.
+    // Window: the same with the windows in place of beta.
+    float pre_k_msd, pre_k_win;
     // TRIG_TEST_SLOPE_WINDOW
     float win_x, win_y;
     int32_t min_triplets;
