@@ -215,6 +215,69 @@ __device__ uint32_t wave_event_pruned(const Consts& c, const H& hits, int o0, in
     return cnt;
 }
 
+// Passing triplets of an event with 1 <= n1 <= 64 and n0 <= the buffer fill
+// for its lane layout (one layer-1 pass, one buffer fill): the same
+// computation as wave_event_pruned with its loops taken once.  R and T come
+// from the per-event descriptor (lane_layout).
+template <class P, class H>
+__device__ uint32_t wave_event_fast(const Consts& c, const H& hits, int o0, int n0, int o1, int n1, int o2,
+                                    int n2, int R, int T, float* __restrict__ px, float* __restrict__ py) {
+    const int lane = (int)lane_id();
+    int g = 0, j = lane;
+    if (R > 1) {
+        g = div_small(lane, n1);
+        j = lane - g * n1;
+    }
+    const bool jv = (g < R) && (j < n1);
+    if (!jv) g = 0;
+    const float2 q = jv ? P::layer1(c, hits.at(o1 + j)) : nan2();
+    const int npad = T * R;
+    for (int t = lane; t < npad; t += kWave) {
+        const float2 v = t < n0 ? P::layer0(c, hits.at(o0 + t)) : nan2();
+        px[t] = v.x;
+        py[t] = v.y;
+    }
+    wave_lds_sync();
+    uint32_t cnt = 0;
+    auto finish = [&](uint64_t m, int t) {
+        while (m) {
+            const int L = __builtin_ctzll(m);
+            m &= m - 1;
+            const int iL = __builtin_amdgcn_readlane(g, L) * T + t;
+            const int jL = __builtin_amdgcn_readlane(j, L);
+            cnt += P::complete(c, hits, o0 + iL, o1 + jL, o2, n2);
+        }
+    };
+    const float4* ppx = reinterpret_cast<const float4*>(px + g * T);
+    const float4* ppy = reinterpret_cast<const float4*>(py + g * T);
+    const float bnd = P::bound(c);
+    for (int t = 0; t < T; t += 4) {
+        const float4 vx = ppx[t >> 2], vy = ppy[t >> 2];
+        const float s0 = P::score(c, make_float2(vx.x, vy.x), q);
+        const float s1 = P::score(c, make_float2(vx.y, vy.y), q);
+        const float s2 = P::score(c, make_float2(vx.z, vy.z), q);
+        const float s3 = P::score(c, make_float2(vx.w, vy.w), q);
+        const float smin = __builtin_fminf(__builtin_fminf(s0, s1), __builtin_fminf(s2, s3));
+        if (wave_any(smin <= bnd)) {
+            finish(P::pair_mask(c, make_float2(vx.x, vy.x), q), t);
+            finish(P::pair_mask(c, make_float2(vx.y, vy.y), q), t + 1);
+            finish(P::pair_mask(c, make_float2(vx.z, vy.z), q), t + 2);
+            finish(P::pair_mask(c, make_float2(vx.w, vy.w), q), t + 3);
+        }
+    }
+    wave_lds_sync();
+    return cnt;
+}
+
+// Lane layout of wave_event_pruned for one buffer fill: R copies of layer 1
+// and T (a multiple of 4) layer-0 entries per copy; T = 0 when the event
+// needs more than one layer-1 pass or buffer fill.
+__device__ __forceinline__ void lane_layout(int n0, int n1, int& R, int& T) {
+    R = n1 <= kWave / 2 ? min(div_small(kWave, n1), kPBuf / 4) : 1;
+    const int chunk = div_small(kPBuf, 4 * R) * 4 * R;
+    T = (n1 <= kWave && n0 <= chunk) ? div_small(n0 + 4 * R - 1, 4 * R) * 4 : 0;
+}
+
 // Count of event e (absolute index) whose CSR range was checked by the
 // caller; writes count and flag.  h_base: index of hits.at(0) in the global
 // hit arrays (0 for GlobalHits).
@@ -308,6 +371,8 @@ __global__ __launch_bounds__(NW * kWave) void k_block(const int32_t* __restrict_
     __shared__ __align__(16) float pbuf_x[NW][kPBuf];
     __shared__ __align__(16) float pbuf_y[NW][kPBuf];
     __shared__ int32_t soff[3 * kMaxEB + 1];
+    __shared__ int4 desc0[kMaxEB], desc1[kMaxEB];
+    __shared__ int32_t sres[kMaxEB];
     __shared__ int s_block, s_bad;
     const int w = uniform_i(threadIdx.x / kWave);
     float* px = pbuf_x[w];
@@ -377,15 +442,49 @@ __global__ __launch_bounds__(NW * kWave) void k_block(const int32_t* __restrict_
             }
             const int end = cur + nfit;
             const int nh = soff[3 * end] - base;
+            const int nsub = end - cur;
             stage_hits<HB, NT>(x, y, base, nh, c.n_hits, vec != 0, stage_x, stage_y);
-            __syncthreads();
-            // Events of the sub-block round-robin over the waves (a static
-            // assignment: no per-wave claim loop).
-            const LdsHits lh{stage_x, stage_y};
+            // Per-event descriptors, one lane per event: local offsets,
+            // sizes, lane layout; events decided without pairs get their
+            // result here (0 for an empty layer, -2 for a count beyond int32).
             const int a0 = base & ~3;
-            for (int ev = cur + w; ev < end; ev += NW)
-                wave_event<P>(c, lh, a0, soff[3 * ev], soff[3 * ev + 1], soff[3 * ev + 2], soff[3 * ev + 3],
-                              e0 + ev, counts, accept, status, px, py);
+            for (int te = t; te < nsub; te += NT) {
+                const int ev = cur + te;
+                const int b0 = soff[3 * ev], b1 = soff[3 * ev + 1], b2 = soff[3 * ev + 2], b3 = soff[3 * ev + 3];
+                const int n0 = b1 - b0, n1 = b2 - b1, n2 = b3 - b2;
+                const int64_t n01 = (int64_t)n0 * n1;
+                int R = 0, T = 0, res = 0, work = 0;
+                if (n2 > 0 && (n01 > (int64_t)INT32_MAX || n01 * n2 > (int64_t)INT32_MAX)) {
+                    res = -2;
+                } else if (n0 > 0 && n1 > 0 && n2 > 0) {
+                    work = 1;
+                    lane_layout(n0, n1, R, T);
+                }
+                desc0[te] = make_int4(b0 - a0, n0, b1 - a0, n1);
+                desc1[te] = make_int4(b2 - a0, n2, work ? R : 0, T);
+                sres[te] = res;
+            }
+            __syncthreads();
+            // Events round-robin over the waves (a static assignment: no
+            // per-wave claim loop).
+            const LdsHits lh{stage_x, stage_y};
+            for (int te = w; te < nsub; te += NW) {
+                const int4 d0 = desc0[te], d1 = desc1[te];
+                const int o0 = uniform_i(d0.x), n0 = uniform_i(d0.y), o1 = uniform_i(d0.z), n1 = uniform_i(d0.w);
+                const int o2 = uniform_i(d1.x), n2 = uniform_i(d1.y), R = uniform_i(d1.z), T = uniform_i(d1.w);
+                if (R == 0) continue;  // decided in the descriptor pass
+                const uint32_t cnt = T > 0 ? wave_event_fast<P>(c, lh, o0, n0, o1, n1, o2, n2, R, T, px, py)
+                                           : wave_event_pruned<P>(c, lh, o0, n0, o1, n1, o2, n2, px, py);
+                if (lane_id() == 0) sres[te] = (int32_t)cnt;
+            }
+            __syncthreads();
+            // Results of the sub-block, one lane per event (coalesced).
+            for (int te = t; te < nsub; te += NT) {
+                const int32_t r = sres[te];
+                counts[e0 + cur + te] = r;
+                accept[e0 + cur + te] = (uint8_t)(r >= 0 && r >= c.min_triplets);
+                if (r < 0 && status) atomicOr(status, TRIG_STATUS_OVERFLOW);
+            }
             __syncthreads();
             cur = end;
         }
