@@ -170,6 +170,11 @@ typedef struct {
  * a NULL pointer. */
 int trig_params_init(trig_params *p);
 
+/* Checks *p (host) the way trig_select does, ignoring the pointers that
+ * TRIG_OUT_COMPACT needs; enqueues nothing.  Returns TRIG_OK, TRIG_EINVAL or
+ * TRIG_EUNSUPPORTED. */
+int trig_params_check(const trig_params *p);
+
 /* Bytes of device workspace trig_select needs for this batch and these
  * parameters (0 for the plain form without compaction).  Host-only call: it
  * reads ev->n_events and p->flags, never device memory.  Returns 0 for invalid

@@ -22,9 +22,10 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libtrig.so")
 ISA = os.path.join(ROOT, "_build", "trig-gfx950.s")
-SOURCES = [os.path.join(CSRC, "trig.hip"), os.path.join(CSRC, "probe.hip")]
-HEADERS = [os.path.join(CSRC, "trig_device.hpp"), os.path.join(INCLUDE, "trig.h"),
-           os.path.join(INCLUDE, "trig_probe.h")]
+SOURCES = [os.path.join(CSRC, "trig.hip"), os.path.join(CSRC, "probe.hip"), os.path.join(CSRC, "serve.hip")]
+HEADERS = [os.path.join(CSRC, "trig_device.hpp"), os.path.join(CSRC, "trig_block.hpp"),
+           os.path.join(CSRC, "serve_core.hpp"), os.path.join(INCLUDE, "trig.h"),
+           os.path.join(INCLUDE, "trig_probe.h"), os.path.join(INCLUDE, "trig_serve.h")]
 ARCH = "gfx950"
 
 COMMON = ["-std=c++17", "-O3", f"--offload-arch={ARCH}", "-ffp-contract=off",
@@ -43,7 +44,7 @@ def hipcc() -> str:
 def build(isa: bool = False, verbose: bool = False) -> str:
     """Compile every source into libtrig.so (always recompiles)."""
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [hipcc(), *COMMON, "-fPIC", "-shared", *SOURCES, "-o", tmp]
+    cmd = [hipcc(), *COMMON, "-fPIC", "-shared", *SOURCES, "-o", tmp, "-lpthread"]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)

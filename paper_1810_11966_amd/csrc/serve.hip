@@ -1,0 +1,352 @@
+// Serving runtime: continuous batching of timeslices on one GPU
+// (include/trig_serve.h).  Admission logic lives in serve_core.hpp.
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <vector>
+
+#include "serve_core.hpp"
+#include "trig.h"
+#include "trig_serve.h"
+
+namespace {
+
+using trig::serve::Admission;
+using trig::serve::Arena;
+
+constexpr size_t kAlign = 256;
+
+size_t r256(size_t b) { return (b + kAlign - 1) & ~(kAlign - 1); }
+
+// Byte layout of one slice, identical in pinned staging and in HBM:
+// offsets | x | y | status | counts | accept | ids | n_accepted [| workspace]
+struct Layout {
+    size_t off, x, y, status, counts, accept, ids, n_acc, ws, host_bytes, dev_bytes;
+    Layout(int64_t n_events, int64_t n_hits, size_t ws_bytes) {
+        size_t at = 0;
+        off = at; at += r256(4 * (size_t)(3 * n_events + 1));
+        x = at; at += r256(4 * (size_t)n_hits);
+        y = at; at += r256(4 * (size_t)n_hits);
+        status = at; at += r256(4);
+        counts = at; at += r256(4 * (size_t)n_events);
+        accept = at; at += r256((size_t)n_events);
+        ids = at; at += r256(4 * (size_t)(n_events > 0 ? n_events : 1));
+        n_acc = at; at += r256(4);
+        host_bytes = at;
+        ws = at; at += r256(ws_bytes);
+        dev_bytes = at;
+    }
+};
+
+enum class State { Queued, InFlight, Done, Polled };
+
+struct Slice {
+    uint64_t ticket = 0;
+    int32_t n_events = 0, n_hits = 0;
+    size_t pin_off = 0, dev_off = 0, ws_bytes = 0;
+    int stream = -1;
+    State state = State::Queued;
+    int32_t status = TRIG_OK;
+    double t_submit = 0, t_admit = 0, t_done = 0;
+};
+
+}  // namespace
+
+struct trig_server {
+    trig_server_config cfg;
+    char* dev_base = nullptr;
+    char* pin_base = nullptr;
+    Arena pin_arena;
+    Admission adm;
+    std::vector<hipStream_t> streams;
+    std::vector<hipEvent_t> events;
+    std::vector<uint64_t> stream_ticket;  // 0 = free
+    std::map<uint64_t, Slice> slices;
+    std::deque<uint64_t> done;
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::thread dispatcher;
+    bool stop = false;
+    uint64_t next_ticket = 1;
+    trig_server_stats stats{};
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+
+    trig_server(const trig_server_config& c)
+        : cfg(c), pin_arena(c.pinned_budget_bytes, kAlign), adm(c.hbm_budget_bytes, c.n_streams) {}
+
+    double now() const {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+
+    size_t workspace_for(int32_t n_events) const {
+        trig_params p = cfg.params;
+        p.flags |= TRIG_OUT_COMPACT;
+        trig_events_csr ev{n_events, nullptr};
+        return trig_workspace_bytes(&ev, &p);
+    }
+
+    // Enqueue copies, selection and result copy of an admitted slice on its
+    // stream (called with mu held).
+    void launch(Slice& s, int si) {
+        const Layout L(s.n_events, s.n_hits, s.ws_bytes);
+        char* d = dev_base + s.dev_off;
+        char* h = pin_base + s.pin_off;
+        hipStream_t st = streams[si];
+        s.stream = si;
+        s.state = State::InFlight;
+        s.t_admit = now();
+        stream_ticket[si] = s.ticket;
+        int rc = TRIG_OK;
+        if (hipMemcpyAsync(d, h, L.counts, hipMemcpyHostToDevice, st) != hipSuccess) rc = TRIG_EHIP;
+        if (rc == TRIG_OK) {
+            trig_params p = cfg.params;
+            p.flags |= TRIG_OUT_COMPACT;
+            p.workspace = s.ws_bytes ? d + L.ws : nullptr;
+            p.workspace_bytes = s.ws_bytes;
+            p.out_accepted_ids = reinterpret_cast<int32_t*>(d + L.ids);
+            p.out_n_accepted = reinterpret_cast<int32_t*>(d + L.n_acc);
+            p.out_status = reinterpret_cast<uint32_t*>(d + L.status);
+            trig_events_csr ev{s.n_events, reinterpret_cast<const int32_t*>(d + L.off)};
+            trig_hits hits{s.n_hits, reinterpret_cast<const float*>(d + L.x), reinterpret_cast<const float*>(d + L.y)};
+            rc = trig_select(&ev, &hits, &p, reinterpret_cast<int32_t*>(d + L.counts),
+                             reinterpret_cast<uint8_t*>(d + L.accept), st);
+        }
+        if (rc == TRIG_OK &&
+            hipMemcpyAsync(h + L.status, d + L.status, L.host_bytes - L.status, hipMemcpyDeviceToHost, st) != hipSuccess)
+            rc = TRIG_EHIP;
+        if (rc == TRIG_OK && hipEventRecord(events[si], st) != hipSuccess) rc = TRIG_EHIP;
+        s.status = rc;
+        ++stats.in_flight;
+        if (stats.in_flight > stats.max_in_flight) stats.max_in_flight = stats.in_flight;
+        if (adm.arena().in_use() > stats.hbm_peak) stats.hbm_peak = adm.arena().in_use();
+    }
+
+    // Marks a slice finished (mu held): frees its device memory and stream.
+    void finish(Slice& s) {
+        // Also after a failed launch: nothing may still use the slice's memory.
+        if (hipStreamSynchronize(streams[s.stream]) != hipSuccess && s.status == TRIG_OK) s.status = TRIG_EHIP;
+        s.t_done = now();
+        s.state = State::Done;
+        adm.complete(s.dev_off);
+        stream_ticket[s.stream] = 0;
+        --stats.in_flight;
+        ++stats.completed;
+        stats.events_completed += (uint64_t)s.n_events;
+        done.push_back(s.ticket);
+    }
+
+    void run() {
+        (void)hipSetDevice(cfg.device);
+        std::unique_lock<std::mutex> lk(mu);
+        for (;;) {
+            // Admit queued slices while a stream is free and memory fits.
+            if (!stop) {
+                for (int si = 0; si < (int)streams.size(); ++si) {
+                    if (stream_ticket[si]) continue;
+                    uint64_t t;
+                    size_t off;
+                    if (!adm.admit_next(t, off)) break;
+                    Slice& s = slices[t];
+                    s.dev_off = off;
+                    --stats.pending;
+                    launch(s, si);
+                }
+            }
+            // Retire finished slices (failed launches finish at once).
+            bool any = false, busy = false;
+            for (int si = 0; si < (int)streams.size(); ++si) {
+                const uint64_t t = stream_ticket[si];
+                if (!t) continue;
+                Slice& s = slices[t];
+                if (s.status != TRIG_OK || hipEventQuery(events[si]) == hipSuccess) {
+                    finish(s);
+                    any = true;
+                } else {
+                    busy = true;
+                }
+            }
+            if (any) {
+                cv_done.notify_all();
+                continue;  // freed memory and streams: try to admit again
+            }
+            if (stop && !busy) break;
+            if (busy) {
+                lk.unlock();
+                std::this_thread::sleep_for(std::chrono::microseconds(20));
+                lk.lock();
+            } else {
+                cv_work.wait(lk);
+            }
+        }
+    }
+};
+
+extern "C" {
+
+int trig_server_create(const trig_server_config* cfg, trig_server** out) {
+    if (!cfg || !out) return TRIG_EINVAL;
+    *out = nullptr;
+    if (cfg->hbm_budget_bytes < kAlign || cfg->pinned_budget_bytes < kAlign || cfg->n_streams < 1 ||
+        cfg->n_streams > 64 || cfg->max_pending < 1 || cfg->reserved != 0)
+        return TRIG_EINVAL;
+    {
+        // The selection parameters must be acceptable to trig_select.
+        trig_params p = cfg->params;
+        p.flags |= TRIG_OUT_COMPACT;
+        if (int rc = trig_params_check(&p)) return rc;
+    }
+    if (hipSetDevice(cfg->device) != hipSuccess) return TRIG_EHIP;
+    auto* s = new trig_server(*cfg);
+    if (hipMalloc(&s->dev_base, cfg->hbm_budget_bytes) != hipSuccess ||
+        hipHostMalloc(&s->pin_base, cfg->pinned_budget_bytes, hipHostMallocDefault) != hipSuccess) {
+        if (s->dev_base) (void)hipFree(s->dev_base);
+        delete s;
+        return TRIG_EHIP;
+    }
+    s->streams.resize(cfg->n_streams);
+    s->events.resize(cfg->n_streams);
+    s->stream_ticket.assign(cfg->n_streams, 0);
+    for (int i = 0; i < cfg->n_streams; ++i) {
+        if (hipStreamCreateWithFlags(&s->streams[i], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&s->events[i], hipEventDisableTiming) != hipSuccess) {
+            for (int k = 0; k <= i; ++k) {
+                if (s->streams[k]) (void)hipStreamDestroy(s->streams[k]);
+                if (s->events[k]) (void)hipEventDestroy(s->events[k]);
+            }
+            (void)hipFree(s->dev_base);
+            (void)hipHostFree(s->pin_base);
+            delete s;
+            return TRIG_EHIP;
+        }
+    }
+    s->dispatcher = std::thread([s] { s->run(); });
+    *out = s;
+    return TRIG_OK;
+}
+
+int trig_server_submit(trig_server* s, const int32_t* offsets, const float* x, const float* y, int32_t n_events,
+                       int32_t n_hits, uint64_t* ticket) {
+    if (!s || !ticket || n_events < 0 || n_hits < 0 || !offsets || (n_hits > 0 && (!x || !y))) return TRIG_EINVAL;
+    const size_t ws = s->workspace_for(n_events);
+    const Layout L(n_events, n_hits, ws);
+    size_t pin_off;
+    uint64_t t;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        if (s->stop || !s->adm.admissible(L.dev_bytes)) return TRIG_EINVAL;
+        if (s->stats.pending >= s->cfg.max_pending) {
+            ++s->stats.rejected_busy;
+            return TRIG_EBUSY;
+        }
+        pin_off = s->pin_arena.alloc(L.host_bytes);
+        if (pin_off == Arena::kFail) {
+            ++s->stats.rejected_busy;
+            return TRIG_EBUSY;
+        }
+        t = s->next_ticket++;
+        Slice& sl = s->slices[t];
+        sl.ticket = t;
+        sl.n_events = n_events;
+        sl.n_hits = n_hits;
+        sl.pin_off = pin_off;
+        sl.ws_bytes = ws;
+        sl.state = State::Queued;
+        sl.t_submit = s->now();
+        ++s->stats.pending;  // counted now; the staging below completes before it can be admitted
+    }
+    char* h = s->pin_base + pin_off;
+    std::memcpy(h + L.off, offsets, 4 * (size_t)(3 * n_events + 1));
+    if (n_hits) {
+        std::memcpy(h + L.x, x, 4 * (size_t)n_hits);
+        std::memcpy(h + L.y, y, 4 * (size_t)n_hits);
+    }
+    std::memset(h + L.status, 0, 4);
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->adm.enqueue(t, L.dev_bytes);
+        ++s->stats.submitted;
+    }
+    s->cv_work.notify_one();
+    *ticket = t;
+    return TRIG_OK;
+}
+
+int trig_server_poll(trig_server* s, trig_slice_result* out, int32_t timeout_ms) {
+    if (!s || !out) return TRIG_EINVAL;
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto ready = [&] { return !s->done.empty(); };
+    if (timeout_ms < 0)
+        s->cv_done.wait(lk, ready);
+    else if (!s->cv_done.wait_for(lk, std::chrono::milliseconds(timeout_ms), ready))
+        return TRIG_ETIMEOUT;
+    const uint64_t t = s->done.front();
+    s->done.pop_front();
+    Slice& sl = s->slices[t];
+    sl.state = State::Polled;
+    const Layout L(sl.n_events, sl.n_hits, sl.ws_bytes);
+    const char* h = s->pin_base + sl.pin_off;
+    std::memset(out, 0, sizeof(*out));
+    out->ticket = t;
+    out->status = sl.status;
+    out->n_events = sl.n_events;
+    out->t_submit = sl.t_submit;
+    out->t_admit = sl.t_admit;
+    out->t_done = sl.t_done;
+    if (sl.status == TRIG_OK) {
+        out->counts = reinterpret_cast<const int32_t*>(h + L.counts);
+        out->accept = reinterpret_cast<const uint8_t*>(h + L.accept);
+        out->accepted_ids = reinterpret_cast<const int32_t*>(h + L.ids);
+        std::memcpy(&out->n_accepted, h + L.n_acc, 4);
+        std::memcpy(&out->event_status, h + L.status, 4);
+    }
+    return TRIG_OK;
+}
+
+int trig_server_release(trig_server* s, uint64_t ticket) {
+    if (!s) return TRIG_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->slices.find(ticket);
+    if (it == s->slices.end() || it->second.state != State::Polled) return TRIG_EINVAL;
+    s->pin_arena.release(it->second.pin_off);
+    s->slices.erase(it);
+    return TRIG_OK;
+}
+
+int trig_server_stats_get(trig_server* s, trig_server_stats* out) {
+    if (!s || !out) return TRIG_EINVAL;
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->stats;
+    out->hbm_in_use = s->adm.arena().in_use();
+    return TRIG_OK;
+}
+
+double trig_server_now(trig_server* s) { return s ? s->now() : 0.0; }
+
+int trig_server_destroy(trig_server* s) {
+    if (!s) return TRIG_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    if (s->dispatcher.joinable()) s->dispatcher.join();
+    (void)hipSetDevice(s->cfg.device);
+    for (size_t i = 0; i < s->streams.size(); ++i) {
+        (void)hipStreamSynchronize(s->streams[i]);
+        (void)hipStreamDestroy(s->streams[i]);
+        (void)hipEventDestroy(s->events[i]);
+    }
+    (void)hipFree(s->dev_base);
+    (void)hipHostFree(s->pin_base);
+    delete s;
+    return TRIG_OK;
+}
+
+}  // extern "C"

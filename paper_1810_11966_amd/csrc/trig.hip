@@ -400,13 +400,20 @@ Consts make_consts(const trig_params* p, int n_hits) {
     return c;
 }
 
+int validate_params(const trig_params* p, bool need_outputs);
+
 int validate(const trig_events_csr* ev, const trig_hits* hits, const trig_params* p) {
     if (!ev || !hits || !p) return fail(TRIG_EINVAL, "NULL descriptor");
-    if (p->abi_version != TRIG_ABI_VERSION) return fail(TRIG_EINVAL, "abi_version mismatch");
     if (ev->n_events < 0) return fail(TRIG_EINVAL, "n_events < 0");
     if (hits->n_hits < 0) return fail(TRIG_EINVAL, "n_hits < 0");
     if (ev->n_events > 0 && !ev->layer_offsets) return fail(TRIG_EINVAL, "layer_offsets is NULL");
     if (hits->n_hits > 0 && (!hits->x || !hits->y)) return fail(TRIG_EINVAL, "x or y is NULL");
+    return validate_params(p, true);
+}
+
+int validate_params(const trig_params* p, bool need_outputs) {
+    if (!p) return fail(TRIG_EINVAL, "NULL params");
+    if (p->abi_version != TRIG_ABI_VERSION) return fail(TRIG_EINVAL, "abi_version mismatch");
     if (p->test != TRIG_TEST_MSD && p->test != TRIG_TEST_MSD_FIT && p->test != TRIG_TEST_SLOPE_WINDOW)
         return fail(TRIG_EINVAL, "unknown test");
     for (int l = 0; l < 3; ++l)
@@ -429,7 +436,7 @@ int validate(const trig_events_csr* ev, const trig_hits* hits, const trig_params
     const uint32_t known = TRIG_EXEC_PERSISTENT | TRIG_EXEC_PRUNED | TRIG_EXEC_BINNED |
                            TRIG_EXEC_AUTOTUNE | TRIG_OUT_COMPACT;
     if (p->flags & ~known) return fail(TRIG_EINVAL, "unknown flag bits");
-    if ((p->flags & TRIG_OUT_COMPACT) && (!p->out_accepted_ids || !p->out_n_accepted))
+    if (need_outputs && (p->flags & TRIG_OUT_COMPACT) && (!p->out_accepted_ids || !p->out_n_accepted))
         return fail(TRIG_EINVAL, "TRIG_OUT_COMPACT needs out_accepted_ids and out_n_accepted");
     if ((p->flags & TRIG_EXEC_PRUNED) && p->test == TRIG_TEST_MSD_FIT)
         return fail(TRIG_EUNSUPPORTED, "pruning is not provided for TRIG_TEST_MSD_FIT");
@@ -619,6 +626,12 @@ int trig_params_init(trig_params* p) {
     p->min_triplets = 2;
     p->flags = TRIG_EXEC_PLAIN;
     return TRIG_OK;
+}
+
+int trig_params_check(const trig_params* p) {
+    const int r = validate_params(p, false);
+    if (r == TRIG_OK) g_detail.clear();
+    return r;
 }
 
 size_t trig_workspace_bytes(const trig_events_csr* ev, const trig_params* p) {

@@ -12,7 +12,7 @@ import pytest
 from paper_1810_11966_amd import build, trig
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("trig.h", "trig_probe.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("trig.h", "trig_probe.h", "trig_serve.h")]
 
 
 @pytest.fixture(scope="module")
@@ -119,6 +119,34 @@ def test_rejects_null_and_negative_sizes(lib):
     p.workspace = 0x10010  # misaligned
     p.workspace_bytes = 1 << 30
     assert _call(p) == trig.TRIG_EWORKSPACE
+
+
+def test_params_check(lib):
+    from paper_1810_11966_amd import serve
+    serve._lib()
+    p = trig.make_params()
+    assert lib.trig_params_check(p) == trig.TRIG_OK
+    p.flags = trig.TRIG_OUT_COMPACT  # output pointers are not required here
+    assert lib.trig_params_check(p) == trig.TRIG_OK
+    p.ndf = 0
+    assert lib.trig_params_check(p) == trig.TRIG_EINVAL
+
+
+def test_server_rejects_bad_config_without_gpu(lib):
+    from paper_1810_11966_amd import serve
+    import ctypes
+    serve._lib()
+    cfg = serve.ServerConfig()
+    cfg.params = trig.make_params()
+    h = ctypes.c_void_p()
+    cfg.hbm_budget_bytes, cfg.pinned_budget_bytes, cfg.n_streams, cfg.max_pending = 0, 1 << 20, 2, 4
+    assert lib.trig_server_create(ctypes.byref(cfg), ctypes.byref(h)) == trig.TRIG_EINVAL
+    cfg.hbm_budget_bytes, cfg.n_streams = 1 << 20, 0
+    assert lib.trig_server_create(ctypes.byref(cfg), ctypes.byref(h)) == trig.TRIG_EINVAL
+    cfg.n_streams = 2
+    cfg.params.ndf = 0
+    assert lib.trig_server_create(ctypes.byref(cfg), ctypes.byref(h)) == trig.TRIG_EINVAL
+    assert not h.value
 
 
 def test_strerror_and_event_hook(lib):
