@@ -89,7 +89,7 @@ class Server:
         cfg.n_streams = int(n_streams)
         cfg.max_pending = int(max_pending)
         cfg.device = int(device)
-        cfg.params = params if params is not None else trig.make_params()
+        cfg.params = params if params is not None else trig.make_params(flags=trig.TRIG_EXEC_PRUNED)
         h = ctypes.c_void_p()
         rc = lib.trig_server_create(ctypes.byref(cfg), ctypes.byref(h))
         if rc:
@@ -153,15 +153,19 @@ class Server:
         self.close()
 
 
-def run_stream(server: Server, slices, arrivals_s, pace: bool = True, poll_ms: int = 1):
+def run_stream(server: Server, slices, arrivals_s, pace: bool = True, poll_ms: int = 1,
+               deadline_s: float = 300.0):
     """Submits ``slices`` (EventSet-like objects with offsets, x, y) at
     ``arrivals_s`` (seconds from now; if pace is False, as fast as possible)
     and returns {ticket: Finished} plus the index -> ticket map and the wall
-    time.  Busy servers are retried after polling."""
+    time.  Busy servers are retried after polling.  Raises TimeoutError if
+    the stream has not finished after ``deadline_s``."""
     done, tickets = {}, {}
     start = time.perf_counter()
     i = 0
     while i < len(slices) or len(done) < len(slices):
+        if time.perf_counter() - start > deadline_s:
+            raise TimeoutError(f"stream unfinished: {i} submitted, {len(done)} done")
         if i < len(slices) and (not pace or time.perf_counter() - start >= arrivals_s[i]):
             s = slices[i]
             t = server.submit(s.offsets, s.x, s.y)

@@ -48,8 +48,8 @@ def test_alone_equals_mix_equals_oracle(srv_mod):
     with srv_mod.Server(1 << 30, 1 << 30, n_streams=4) as srv:
         for s in slices:
             t = srv.submit(s.offsets, s.x, s.y)
-            f = srv.poll(-1)
-            assert f.ticket == t and f.status == 0
+            f = srv.poll(60000)
+            assert f is not None and f.ticket == t and f.status == 0
             alone.append(f)
     print("[serve] mix", flush=True)
     with srv_mod.Server(1 << 30, 1 << 30, n_streams=4) as srv:
