@@ -124,8 +124,18 @@ enum {
     TRIG_EXEC_BINNED = 4u,      /* slope-cell binning of layer-1 hits so that
                                    only candidate pairs are formed; MSD and
                                    window tests */
-    TRIG_EXEC_AUTOTUNE = 8u,    /* let the library pick the form and launch
-                                   shape (tuned table for gfx950) */
+    TRIG_EXEC_AUTOTUNE = 8u,    /* MSD and window tests: run the batched form
+                                   with the launch shape (block_hits,
+                                   block_waves, fill of block_events, block
+                                   stealing on or off) that trig_autotune
+                                   recorded for this device, test and
+                                   multiplicity class (floor(log2(mean hits
+                                   per event))); without a record, the
+                                   built-in rule.  Non-zero block_* fields
+                                   win over the record.  MSD_FIT: the
+                                   caller's brute-force flags.  Needs the
+                                   workspace of trig_workspace_bytes() for
+                                   these flags */
     TRIG_OUT_COMPACT = 16u      /* also write the ascending ids of accepted
                                    events; needs workspace */
 };
@@ -200,6 +210,40 @@ size_t trig_workspace_bytes(const trig_events_csr *ev, const trig_params *p);
  * workspaces. */
 int trig_select(const trig_events_csr *ev, const trig_hits *hits, const trig_params *p,
                 int32_t *out_counts, uint8_t *out_accept, void *stream);
+
+/* Result of trig_autotune (host). */
+typedef struct {
+    int32_t n_candidates;     /* launch shapes timed (0 for MSD_FIT) */
+    int32_t mult_class;       /* multiplicity class of the batch */
+    int32_t block_hits;       /* chosen shape */
+    int32_t block_waves;
+    int32_t block_events;     /* events per block for this batch */
+    int32_t persistent;       /* 1 if block stealing won */
+    float ms_best;            /* mean kernel time of the chosen shape, ms */
+    float ms_rule;            /* same for the built-in rule's shape */
+} trig_autotune_result;
+
+/* Times the batched form's launch shapes on this batch and records the fastest
+ * for the batch's multiplicity class (per device and test), for later calls
+ * with TRIG_EXEC_AUTOTUNE.  Candidates: block_hits 1024/2048/4096 x
+ * block_waves 1/2/4 x block fill 0.4/0.6/0.8 of the LDS capacity (in mean
+ * event sizes) x block stealing off/on, each timed `reps` times (1..100) after
+ * one warm-up; every candidate computes the same counts.  Arguments are those
+ * of trig_select, with TRIG_EXEC_AUTOTUNE set in p->flags; block_* fields of
+ * p are ignored while timing.  On return (the call synchronises `stream`)
+ * out_counts, out_accept (and the compact outputs, if requested) hold the
+ * result of an autotuned trig_select with the new record, and *out (may be
+ * NULL) describes it.  Errors: those of trig_select; TRIG_EINVAL if
+ * TRIG_EXEC_AUTOTUNE is not set or reps is out of range; TRIG_EHIP if an
+ * event or synchronisation fails.  Not for concurrent use with other calls on
+ * the same workspace. */
+int trig_autotune(const trig_events_csr *ev, const trig_hits *hits, const trig_params *p,
+                  int32_t *out_counts, uint8_t *out_accept, int32_t reps, trig_autotune_result *out,
+                  void *stream);
+
+/* Forgets every recorded launch shape (host); autotuned calls use the
+ * built-in rule again. */
+void trig_autotune_reset(void);
 
 /* Profiling hook (host, per calling thread): the following trig_select calls
  * of this thread record `start` immediately before and `stop` immediately

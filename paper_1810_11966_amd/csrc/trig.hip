@@ -24,8 +24,11 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
+#include <vector>
 
 #include "trig.h"
 #include "trig_block.hpp"
@@ -440,8 +443,8 @@ int validate_params(const trig_params* p, bool need_outputs) {
         return fail(TRIG_EINVAL, "TRIG_OUT_COMPACT needs out_accepted_ids and out_n_accepted");
     if ((p->flags & TRIG_EXEC_PRUNED) && p->test == TRIG_TEST_MSD_FIT)
         return fail(TRIG_EUNSUPPORTED, "pruning is not provided for TRIG_TEST_MSD_FIT");
-    if (p->flags & (TRIG_EXEC_BINNED | TRIG_EXEC_AUTOTUNE))
-        return fail(TRIG_EUNSUPPORTED, "binned/autotuned forms are not built in this library version");
+    if (p->flags & TRIG_EXEC_BINNED)
+        return fail(TRIG_EUNSUPPORTED, "the binned form is not built in this library version");
     return TRIG_OK;
 }
 
@@ -472,6 +475,16 @@ Layout layout(int n_events, uint32_t flags) {
     }
     L.total = at;
     return L;
+}
+
+// Flags whose workspace layout covers a call: an autotuned call may run the
+// batched form with or without block stealing (the MSD_FIT test keeps the
+// caller's brute-force flags), so it reserves the block counter.
+uint32_t layout_flags(const trig_params* p) {
+    if (!(p->flags & TRIG_EXEC_AUTOTUNE)) return p->flags;
+    const uint32_t f = p->flags & ~(uint32_t)TRIG_EXEC_AUTOTUNE;
+    if (p->test == TRIG_TEST_MSD_FIT) return f;
+    return f | TRIG_EXEC_PRUNED | TRIG_EXEC_PERSISTENT;
 }
 
 int check_launch(const char* what) {
@@ -606,6 +619,56 @@ int run_form(const trig_events_csr* ev, const trig_hits* h, const trig_params* p
     return launch_plain<T>(ev, h, c, counts, accept, p->out_status, s);
 }
 
+// ------------------------------------------------------------ autotuner ---
+
+// Multiplicity class of a batch: floor(log2(mean hits per event)), 0..31.
+int multiplicity_class(int n_events, int n_hits) {
+    const double mean = n_events > 0 ? (double)n_hits / n_events : 1.0;
+    int cls = 0;
+    while (cls < 31 && mean >= (double)(2u << cls)) ++cls;
+    return cls;
+}
+
+struct TunedShape {
+    int hb, nw;
+    double fill;  // events per block = fill * hb / mean hits per event
+    bool persistent;
+};
+
+int events_for_fill(double fill, int hb, int n_events, int n_hits) {
+    const double mean = std::max(n_events > 0 ? (double)n_hits / n_events : 1.0, 1.0);
+    return (int)std::max(1.0, std::min((double)kMaxEB, std::floor(fill * hb / mean)));
+}
+
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int>, TunedShape> g_tuned;  // (device, test, class)
+
+int current_device() {
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess) d = 0;
+    return d;
+}
+
+// Effective parameters of a TRIG_EXEC_AUTOTUNE call: the batched form for the
+// tests that have it, with the recorded shape of the batch's class (fields the
+// caller set explicitly win), else the built-in rule.
+trig_params resolve_autotune(const trig_params* p, int n_events, int n_hits) {
+    trig_params q = *p;
+    q.flags &= ~(uint32_t)TRIG_EXEC_AUTOTUNE;
+    if (p->test == TRIG_TEST_MSD_FIT) return q;  // brute force only
+    q.flags |= TRIG_EXEC_PRUNED;
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tuned.find({current_device(), p->test, multiplicity_class(n_events, n_hits)});
+    if (it != g_tuned.end()) {
+        const TunedShape& t = it->second;
+        if (!q.block_hits) q.block_hits = t.hb;
+        if (!q.block_waves) q.block_waves = t.nw;
+        if (!q.block_events) q.block_events = events_for_fill(t.fill, q.block_hits, n_events, n_hits);
+        if (t.persistent) q.flags |= TRIG_EXEC_PERSISTENT;
+    }
+    return q;
+}
+
 }  // namespace
 
 extern "C" {
@@ -636,15 +699,25 @@ int trig_params_check(const trig_params* p) {
 
 size_t trig_workspace_bytes(const trig_events_csr* ev, const trig_params* p) {
     if (!ev || !p || ev->n_events < 0) return 0;
-    return layout(ev->n_events, p->flags).total;
+    return layout(ev->n_events, layout_flags(p)).total;
 }
 
-int trig_select(const trig_events_csr* ev, const trig_hits* hits, const trig_params* p,
+int trig_select(const trig_events_csr* ev, const trig_hits* hits, const trig_params* p_in,
                 int32_t* out_counts, uint8_t* out_accept, void* stream) {
-    if (int r = validate(ev, hits, p)) return r;
+    if (int r = validate(ev, hits, p_in)) return r;
+    // An autotuned call runs with the effective parameters of its batch's
+    // multiplicity class; its workspace was sized by layout_flags().
+    trig_params p_eff;
+    const trig_params* p = p_in;
+    if (p_in->flags & TRIG_EXEC_AUTOTUNE) {
+        p_eff = resolve_autotune(p_in, ev->n_events, hits->n_hits);
+        p_eff.workspace = p_in->workspace;
+        p_eff.workspace_bytes = p_in->workspace_bytes;
+        p = &p_eff;
+    }
     const int n = ev->n_events;
     if (n > 0 && (!out_counts || !out_accept)) return fail(TRIG_EINVAL, "out_counts or out_accept is NULL");
-    const Layout L = layout(n, p->flags);
+    const Layout L = layout(n, layout_flags(p_in));
     if (L.total && (!p->workspace || p->workspace_bytes < L.total))
         return fail(TRIG_EWORKSPACE, "workspace smaller than trig_workspace_bytes()");
     if (L.total && (reinterpret_cast<uintptr_t>(p->workspace) & 255))
@@ -682,6 +755,102 @@ int trig_select(const trig_events_csr* ev, const trig_hits* hits, const trig_par
                            L.compact_blocks, p->out_accepted_ids, p->out_n_accepted);
         if (int r = check_launch("k_compact_write")) return r;
     }
+    g_detail.clear();
+    return TRIG_OK;
+}
+
+void trig_autotune_reset(void) {
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    g_tuned.clear();
+}
+
+int trig_autotune(const trig_events_csr* ev, const trig_hits* hits, const trig_params* p,
+                  int32_t* out_counts, uint8_t* out_accept, int32_t reps, trig_autotune_result* out,
+                  void* stream) {
+    if (!p) return fail(TRIG_EINVAL, "NULL params");
+    if (!(p->flags & TRIG_EXEC_AUTOTUNE)) return fail(TRIG_EINVAL, "TRIG_EXEC_AUTOTUNE is not set");
+    if (reps < 1 || reps > 100) return fail(TRIG_EINVAL, "reps must be in 1..100");
+    if (int r = validate(ev, hits, p)) return r;
+    trig_autotune_result res{};
+    const int n = ev->n_events, n_hits = hits->n_hits;
+    res.mult_class = multiplicity_class(n, n_hits);
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+
+    if (p->test != TRIG_TEST_MSD_FIT && n > 0) {
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+            if (e0) (void)hipEventDestroy(e0);
+            return fail(TRIG_EHIP, "hipEventCreate failed");
+        }
+        // Times one candidate: the whole selection without compaction.
+        auto time_shape = [&](const TunedShape& t, float& ms) -> int {
+            trig_params q = *p;
+            q.flags = TRIG_EXEC_PRUNED | (t.persistent ? TRIG_EXEC_PERSISTENT : 0u);
+            q.block_hits = t.hb;
+            q.block_waves = t.nw;
+            q.block_events = events_for_fill(t.fill, t.hb, n, n_hits);
+            q.out_accepted_ids = nullptr;
+            q.out_n_accepted = nullptr;
+            double total = 0.0;
+            for (int it = 0; it <= reps; ++it) {
+                if (hipEventRecord(e0, s) != hipSuccess) return fail(TRIG_EHIP, "hipEventRecord failed");
+                if (int r = trig_select(ev, hits, &q, out_counts, out_accept, stream)) return r;
+                if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+                    return fail(TRIG_EHIP, "event synchronisation failed");
+                float one = 0.0f;
+                if (hipEventElapsedTime(&one, e0, e1) != hipSuccess) return fail(TRIG_EHIP, "hipEventElapsedTime failed");
+                if (it > 0) total += one;  // the first run warms up
+            }
+            ms = (float)(total / reps);
+            return TRIG_OK;
+        };
+        // The built-in rule's shape first (its fill is 0.6).
+        trig_params rp = *p;
+        rp.block_hits = rp.block_waves = rp.block_events = 0;
+        const BlockShape r0 = choose_block_shape(&rp, n, n_hits);
+        TunedShape best{r0.hb, r0.nw, 0.6, false};
+        int rc = time_shape(best, res.ms_rule);
+        res.ms_best = res.ms_rule;
+        if (rc == TRIG_OK) res.n_candidates = 1;
+        const int hbs[3] = {1024, 2048, 4096}, nws[3] = {1, 2, 4};
+        const double fills[3] = {0.4, 0.6, 0.8};
+        for (int a = 0; a < 3 && rc == TRIG_OK; ++a)
+            for (int b = 0; b < 3 && rc == TRIG_OK; ++b)
+                for (int f = 0; f < 3 && rc == TRIG_OK; ++f)
+                    for (int ps = 0; ps < 2 && rc == TRIG_OK; ++ps) {
+                        const TunedShape t{hbs[a], nws[b], fills[f], ps == 1};
+                        float ms = 0.0f;
+                        rc = time_shape(t, ms);
+                        if (rc == TRIG_OK) {
+                            ++res.n_candidates;
+                            if (ms < res.ms_best) {
+                                res.ms_best = ms;
+                                best = t;
+                            }
+                        }
+                    }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (rc) return rc;
+        {
+            std::lock_guard<std::mutex> lock(g_tune_mu);
+            g_tuned[{current_device(), p->test, res.mult_class}] = best;
+        }
+    }
+    // The caller's outputs: one autotuned call with the new record.
+    trig_params q = *p;
+    q.block_hits = q.block_waves = q.block_events = 0;
+    if (int r = trig_select(ev, hits, &q, out_counts, out_accept, stream)) return r;
+    if (p->test != TRIG_TEST_MSD_FIT && n > 0) {
+        const trig_params eff = resolve_autotune(&q, n, n_hits);
+        const BlockShape bs = choose_block_shape(&eff, n, n_hits);
+        res.block_hits = bs.hb;
+        res.block_waves = bs.nw;
+        res.block_events = bs.eb;
+        res.persistent = (eff.flags & TRIG_EXEC_PERSISTENT) ? 1 : 0;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess) return fail(TRIG_EHIP, "hipStreamSynchronize failed");
+    if (out) *out = res;
     g_detail.clear();
     return TRIG_OK;
 }

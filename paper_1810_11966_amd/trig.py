@@ -6,10 +6,14 @@ provides device memory and the stream.  The functions keep the C names:
     trig_params_init() -> TrigParams
     trig_workspace_bytes(n_events, params) -> int
     trig_select(events, hits, params, out_counts, out_accept, stream) -> int
+    trig_autotune(events, hits, params, out_counts, out_accept, reps, stream)
+        -> (int, TrigAutotuneResult)
+    trig_autotune_reset()
     trig_strerror(code) -> str
 
-plus ``select(offsets, x, y, ...)``, which allocates the outputs (and the
-workspace) with torch on the inputs' device and raises TrigError on failure.
+plus ``select(offsets, x, y, ...)`` and ``autotune(offsets, x, y, ...)``,
+which allocate the outputs (and the workspace) with torch on the inputs'
+device and raise TrigError on failure.
 The library must be built (python -m paper_1810_11966_amd.build); loading
 fails loudly otherwise, there is no fallback.
 """
@@ -44,7 +48,7 @@ FORMS = {
 
 # Every symbol include/trig.h declares.
 EXPORTED = ("trig_params_init", "trig_params_check", "trig_workspace_bytes", "trig_select",
-            "trig_set_kernel_events", "trig_strerror", "trig_last_error_detail", "trig_probe_valu",
+            "trig_autotune", "trig_autotune_reset", "trig_set_kernel_events", "trig_strerror", "trig_last_error_detail", "trig_probe_valu",
             "trig_probe_copy", "trig_server_create", "trig_server_submit", "trig_server_poll",
             "trig_server_release", "trig_server_stats_get", "trig_server_now", "trig_server_destroy")
 
@@ -67,6 +71,13 @@ class TrigParams(ctypes.Structure):
                 ("out_status", ctypes.c_void_p), ("tile_pairs", ctypes.c_int32),
                 ("block_events", ctypes.c_int32), ("block_hits", ctypes.c_int32),
                 ("block_waves", ctypes.c_int32), ("reserved", ctypes.c_int32 * 4)]
+
+
+class TrigAutotuneResult(ctypes.Structure):
+    _fields_ = [("n_candidates", ctypes.c_int32), ("mult_class", ctypes.c_int32),
+                ("block_hits", ctypes.c_int32), ("block_waves", ctypes.c_int32),
+                ("block_events", ctypes.c_int32), ("persistent", ctypes.c_int32),
+                ("ms_best", ctypes.c_float), ("ms_rule", ctypes.c_float)]
 
 
 class TrigError(RuntimeError):
@@ -94,6 +105,12 @@ def load(path: str = LIB_PATH):
     lib.trig_select.argtypes = [ctypes.POINTER(TrigEventsCsr), ctypes.POINTER(TrigHits),
                                 ctypes.POINTER(TrigParams), ctypes.c_void_p, ctypes.c_void_p,
                                 ctypes.c_void_p]
+    lib.trig_autotune.restype = ctypes.c_int
+    lib.trig_autotune.argtypes = [ctypes.POINTER(TrigEventsCsr), ctypes.POINTER(TrigHits),
+                                  ctypes.POINTER(TrigParams), ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.c_int32, ctypes.POINTER(TrigAutotuneResult), ctypes.c_void_p]
+    lib.trig_autotune_reset.restype = None
+    lib.trig_autotune_reset.argtypes = []
     lib.trig_set_kernel_events.restype = ctypes.c_int
     lib.trig_set_kernel_events.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     lib.trig_strerror.restype = ctypes.c_char_p
@@ -158,6 +175,20 @@ def trig_select(events: TrigEventsCsr, hits: TrigHits, params: TrigParams, out_c
                                   ctypes.c_void_p(stream or None)))
 
 
+def trig_autotune(events: TrigEventsCsr, hits: TrigHits, params: TrigParams, out_counts: int,
+                  out_accept: int, reps: int, stream: int):
+    """Raw call (see trig_select); returns (code, TrigAutotuneResult)."""
+    r = TrigAutotuneResult()
+    rc = int(load().trig_autotune(ctypes.byref(events), ctypes.byref(hits), ctypes.byref(params),
+                                  ctypes.c_void_p(out_counts or None), ctypes.c_void_p(out_accept or None),
+                                  int(reps), ctypes.byref(r), ctypes.c_void_p(stream or None)))
+    return rc, r
+
+
+def trig_autotune_reset() -> None:
+    load().trig_autotune_reset()
+
+
 def trig_set_kernel_events(start: int, stop: int) -> int:
     """hipEvent_t handles (ints) recorded around the dominant kernel of the
     following trig_select calls of this thread; 0, 0 switches off."""
@@ -179,6 +210,7 @@ class SelectResult:
     ids: "object" = None       # torch.int32 [E] (first n_accepted valid) when compact
     n_accepted: "object" = None  # torch.int32 [1] when compact
     status: "object" = None    # torch.int32 [1] (uint32 bits) when requested
+    workspace: "object" = None  # torch.uint8 workspace, kept alive with the result
 
 
 def _check_tensor(t, dtype, name):
@@ -187,11 +219,7 @@ def _check_tensor(t, dtype, name):
         raise ValueError(f"{name} must be a contiguous {dtype} tensor on a GPU")
 
 
-def select(offsets, x, y, *, test: str = "msd", form: str = "plain", compact: bool = False,
-           want_status: bool = False, stream=None, workspace=None, out=None, **param_kw) -> SelectResult:
-    """Run trig_select on torch device tensors (int32 offsets [3E+1], float32
-    x, y [H]).  ``form`` is a key of FORMS; extra keywords go to make_params.
-    ``out`` may hold preallocated (counts, accept) tensors."""
+def _prepare(offsets, x, y, test, form, compact, want_status, stream, workspace, out, param_kw):
     import torch
     _check_tensor(offsets, torch.int32, "offsets")
     _check_tensor(x, torch.float32, "x")
@@ -220,7 +248,7 @@ def select(offsets, x, y, *, test: str = "msd", form: str = "plain", compact: bo
         p.out_status = res.status.data_ptr()
     nbytes = trig_workspace_bytes(n_ev, p)
     if nbytes:
-        if workspace is None or workspace.numel() < nbytes:
+        if workspace is None or workspace.numel() < nbytes + 256:
             workspace = torch.empty(nbytes + 256, dtype=torch.uint8, device=dev)
         addr = workspace.data_ptr()
         aligned = (addr + 255) & ~255
@@ -229,7 +257,30 @@ def select(offsets, x, y, *, test: str = "msd", form: str = "plain", compact: bo
     s = torch.cuda.current_stream(dev).cuda_stream if stream is None else int(stream)
     ev = TrigEventsCsr(n_ev, offsets.data_ptr())
     hits = TrigHits(x.numel(), x.data_ptr(), y.data_ptr())
-    rc = trig_select(ev, hits, p, counts.data_ptr(), accept.data_ptr(), s)
+    res.workspace = workspace  # kept until the result is dropped (the call is asynchronous)
+    return p, res, ev, hits, s
+
+
+def select(offsets, x, y, *, test: str = "msd", form: str = "plain", compact: bool = False,
+           want_status: bool = False, stream=None, workspace=None, out=None, **param_kw) -> SelectResult:
+    """Run trig_select on torch device tensors (int32 offsets [3E+1], float32
+    x, y [H]).  ``form`` is a key of FORMS; extra keywords go to make_params.
+    ``out`` may hold preallocated (counts, accept) tensors."""
+    p, res, ev, hits, s = _prepare(offsets, x, y, test, form, compact, want_status, stream, workspace,
+                                   out, param_kw)
+    rc = trig_select(ev, hits, p, res.counts.data_ptr(), res.accept.data_ptr(), s)
     if rc:
         raise TrigError(rc, trig_last_error_detail())
     return res
+
+
+def autotune(offsets, x, y, *, test: str = "msd", reps: int = 3, compact: bool = False,
+             want_status: bool = False, stream=None, workspace=None, out=None, **param_kw):
+    """Run trig_autotune on torch device tensors (form "auto"); returns
+    (SelectResult, TrigAutotuneResult).  Synchronises the stream."""
+    p, res, ev, hits, s = _prepare(offsets, x, y, test, "auto", compact, want_status, stream, workspace,
+                                   out, param_kw)
+    rc, info = trig_autotune(ev, hits, p, res.counts.data_ptr(), res.accept.data_ptr(), reps, s)
+    if rc:
+        raise TrigError(rc, trig_last_error_detail())
+    return res, info

@@ -193,3 +193,21 @@ def test_msd_kernels_have_no_fma_or_packed_fp32(isa):
 def test_fp32_subnormals_enabled(isa):
     modes = re.findall(r"\.amdhsa_float_denorm_mode_32\s+(\d+)", isa)
     assert modes and all(m == "3" for m in modes)
+
+
+def test_autotune_argument_checks(lib):
+    p = trig.make_params(flags=trig.TRIG_EXEC_AUTOTUNE)
+    assert trig.trig_workspace_bytes(100, p) >= 256  # block counter for stealing
+    assert _call(p) == trig.TRIG_EWORKSPACE
+    fit = trig.make_params(test="msd_fit", flags=trig.TRIG_EXEC_AUTOTUNE)
+    assert trig.trig_workspace_bytes(100, fit) == 0  # brute force, no stealing
+    ev = trig.TrigEventsCsr(1, 0x1000)
+    hits = trig.TrigHits(0, None, None)
+    plain = trig.make_params()
+    rc, _ = trig.trig_autotune(ev, hits, plain, 0x2000, 0x3000, 1, 0)
+    assert rc == trig.TRIG_EINVAL  # flag not set
+    rc, _ = trig.trig_autotune(ev, hits, fit, 0x2000, 0x3000, 0, 0)
+    assert rc == trig.TRIG_EINVAL  # reps out of range
+    rc, _ = trig.trig_autotune(ev, hits, fit, 0x2000, 0x3000, 101, 0)
+    assert rc == trig.TRIG_EINVAL
+    trig.trig_autotune_reset()

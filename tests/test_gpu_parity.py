@@ -14,7 +14,7 @@ from tests import helpers
 pytestmark = pytest.mark.gpu
 
 TESTS = ("msd", "msd_fit", "window")
-FORMS = ("plain", "persistent", "pruned", "persistent_pruned")
+FORMS = ("plain", "persistent", "pruned", "persistent_pruned", "auto")
 
 
 def forms_for(test):
@@ -294,3 +294,36 @@ def test_medium_1m_full_size_sampled(gpu):
     sub = s.subset(0, 6000)
     c, _, _, _ = R.select_set(sub, R.OracleConfig(test="window"), n_threads=THREADS)
     assert np.array_equal(w["counts"][:6000], c)
+
+
+# -------------------------------------------------------------- autotuner ---
+
+@pytest.mark.parametrize("test", TESTS)
+def test_autotune_records_and_matches_oracle(gpu, test):
+    from paper_1810_11966_amd import trig
+    trig.trig_autotune_reset()
+    s = synth.concat([synth.make_event_set(synth.SMALL_10K),
+                      synth.make_event_set(synth.DENSE_100K, n_events=300)])
+    c, a, st, _ = oracle_result(s, oracle_cfg(test))
+    off, x, y = to_dev(gpu, s)
+    print(f"[autotune] {test} events={s.n_events} hits={s.n_hits}", flush=True)
+    r, info = trig.autotune(off, x, y, test=test, reps=1, compact=True, want_status=True)
+    gpu.cuda.synchronize()
+    assert np.array_equal(r.counts.cpu().numpy(), c)
+    assert np.array_equal(r.accept.cpu().numpy(), a)
+    n = int(r.n_accepted.cpu().numpy()[0])
+    assert np.array_equal(r.ids.cpu().numpy()[:n], R.accepted_ids(a))
+    if test == "msd_fit":
+        assert info.n_candidates == 0
+    else:
+        assert info.n_candidates == 1 + 3 * 3 * 3 * 2
+        assert 0 < info.ms_best <= info.ms_rule
+        assert info.block_hits in (1024, 2048, 4096) and info.block_waves in (1, 2, 4)
+        assert 1 <= info.block_events <= 128
+    # later autotuned calls use the record; explicit block fields still win
+    assert_parity(gpu, s, test, "auto", "autotuned")
+    if test != "msd_fit":
+        assert_parity(gpu, s, test, "auto", "autotuned+explicit", block_hits=1024, block_waves=1,
+                      block_events=3)
+    trig.trig_autotune_reset()
+    assert_parity(gpu, s, test, "auto", "rule after reset")
