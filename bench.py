@@ -3,9 +3,11 @@
 
 One step = one trig_select call over the whole resident batch (validation,
 triplet counting, accept flags and the ordered accepted-id list) in the
-production form (persistent work stealing with exact pair pruning).  The plain
-one-wave-per-event brute-force form is timed beside it on the same input, and
-both must produce identical counts.  Inputs are generated on the host
+production form (workgroups staging event blocks in LDS, with exact pair
+pruning).  The plain one-wave-per-event brute-force form is timed beside it on
+the same input, and both must produce identical counts.  A serving leg then
+streams timeslices cut from the same events through the serving runtime at a
+fixed offered load and reports p50/p99 slice latency.  Inputs are generated on the host
 (seeded, synthetic), copied to HBM before the timed region, and outputs stay
 in HBM.
 
@@ -56,7 +58,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="medium_1m", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--test", default="msd", choices=["msd", "msd_fit", "window"])
-    ap.add_argument("--form", default="persistent_pruned")
+    ap.add_argument("--form", default="pruned")
     ap.add_argument("--compare", default="plain,pruned,persistent",
                     help="other forms timed on the same input (comma separated)")
     ap.add_argument("--compare-steps", type=int, default=5, help="timed steps of each compared form")
@@ -64,6 +66,10 @@ def parse():
                     help="target wall time of the CPU-oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-form", action="store_true", help="time only --form (profiling runs)")
+    ap.add_argument("--serve-slices", type=int, default=100,
+                    help="timeslices of the serving leg (0 = skip it)")
+    ap.add_argument("--serve-load", type=float, default=1e7, help="offered load of the serving leg, events/s")
+    ap.add_argument("--serve-streams", type=int, default=4)
     return ap.parse_args()
 
 
@@ -148,6 +154,65 @@ def time_form(torch, trig, hip_events, dev_in, n_events, form, test, steps, warm
         "ids": ids[: int(n_acc.item())],
         "n_accepted": int(n_acc.item()),
     }
+
+
+class SliceView:
+    """Events [first, first+count) of a set: rebased offsets, x and y views."""
+
+    def __init__(self, s, first, count):
+        lo = int(s.offsets[3 * first])
+        self.offsets = (s.offsets[3 * first: 3 * (first + count) + 1] - lo).astype(np.int32)
+        hi = lo + int(self.offsets[-1])
+        self.x, self.y = s.x[lo:hi], s.y[lo:hi]
+        self.first, self.n_events = first, count
+
+
+def serving_leg(s, full_counts, test, n_slices, load, n_streams, seed=11):
+    """Timeslices of U[1e4, 1e6] events cut from the resident workload at
+    random positions arrive as a Poisson stream with the given offered load
+    (events/s); the server admits them by HBM footprint and overlaps their
+    copies and kernels.  Every slice's counts must equal the full-batch
+    result on the same events.  Latency = result on the host - scheduled
+    arrival (so a late submit counts against it)."""
+    from paper_1810_11966_amd import serve, trig
+    rng = np.random.default_rng(seed)
+    sizes = rng.integers(10_000, min(1_000_000, s.n_events) + 1, n_slices)
+    firsts = [int(rng.integers(0, s.n_events - n + 1)) for n in sizes]
+    slices = [SliceView(s, f, int(n)) for f, n in zip(firsts, sizes)]
+    rate = load / float(np.mean(sizes))
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, n_slices))
+    arrivals -= arrivals[0]
+    big = max(sl.x.size for sl in slices)
+    dev_slice = 16 * big + 32 * int(max(sizes)) + (8 << 20)   # generous device footprint
+    host_slice = 8 * big + 32 * int(max(sizes)) + (8 << 20)   # staging: inputs and results
+    params = trig.make_params(test=test, flags=trig.TRIG_EXEC_PRUNED)
+    with serve.Server(hbm_budget_bytes=(n_streams + 1) * dev_slice,
+                      pinned_budget_bytes=(n_streams + 4) * host_slice,
+                      n_streams=n_streams, max_pending=64, params=params) as srv:
+        # one small slice first: code objects and pinned pages are warm
+        srv.submit(slices[0].offsets, slices[0].x, slices[0].y)
+        srv.poll(60000)
+        origin = srv.now()
+        done, tickets, wall = serve.run_stream(srv, slices, arrivals, pace=True, poll_ms=1, deadline_s=240)
+        st = srv.stats()
+    lat, qwait, ev_done = [], [], 0
+    for i, sl in enumerate(slices):
+        f = done[tickets[i]]
+        if f.status != 0 or not np.array_equal(f.counts, full_counts[sl.first: sl.first + sl.n_events]):
+            print(f"bench.py: served slice {i} differs from the full-batch result", file=sys.stderr)
+            sys.exit(1)
+        lat.append(f.t_done - (origin + arrivals[i]))
+        qwait.append(f.t_admit - f.t_submit)
+        ev_done += sl.n_events
+    lat = np.array(lat) * 1e3
+    return {"slices": n_slices, "slice_events": "U[10000, 1000000]", "offered_events_per_s": load,
+            "arrival_rate_per_s": rate, "events_per_s": ev_done / wall, "wall_s": wall,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "max_ms": float(lat.max()), "mean_admission_wait_ms": 1e3 * float(np.mean(qwait)),
+            "streams": n_streams, "max_in_flight": int(st.max_in_flight),
+            "latency": "scheduled arrival to result on the host (includes the copy into pinned staging, "
+                       "H2D, kernels, D2H)",
+            "counts_identical_to_full_batch": True}
 
 
 def cpu_baseline(s, test, target_s):
@@ -238,6 +303,14 @@ def main():
     if plain_info:
         extra["batched_vs_plain"] = value / plain_info["events_per_s"]
 
+    serving = None
+    if args.serve_slices > 0 and not args.only_form:
+        log(f"[bench] serving leg: {args.serve_slices} slices at {args.serve_load:.3g} events/s offered")
+        serving = serving_leg(s, main_r["counts"].cpu().numpy(), args.test, args.serve_slices,
+                              args.serve_load, args.serve_streams)
+        log(f"[bench] serving: p50 {serving['p50_ms']:.2f} ms, p99 {serving['p99_ms']:.2f} ms, "
+            f"{serving['events_per_s']:.4g} events/s")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
@@ -269,7 +342,8 @@ def main():
         "n_accepted": main_r["n_accepted"],
         "plain": plain_info,
         "forms": forms,
-        "p99_slice_latency_ms": None,
+        "p99_slice_latency_ms": serving["p99_ms"] if serving else None,
+        "serving": serving,
         **extra,
     }
     print(json.dumps(out), flush=True)

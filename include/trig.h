@@ -121,9 +121,19 @@ enum {
                                    for every k in binary32; window: the layer-1
                                    window is part of the test); same counts.
                                    Not for TRIG_TEST_MSD_FIT */
-    TRIG_EXEC_BINNED = 4u,      /* slope-cell binning of layer-1 hits so that
-                                   only candidate pairs are formed; MSD and
-                                   window tests */
+    TRIG_EXEC_BINNED = 4u,      /* binned form for high-multiplicity events:
+                                   one wave per event sorts layers 1 and 2
+                                   into cells of a slope-proportional key in
+                                   LDS and tests only hits in the cells whose
+                                   key interval can pass (MSD: |a|, |b| <=
+                                   beta; window: the slope windows), with the
+                                   interval ends rounded outwards; same
+                                   counts.  Events with more than 512 hits in
+                                   layer 1 or 2 take the pruned path.  With
+                                   TRIG_EXEC_PERSISTENT workgroups take event
+                                   groups from a counter (needs workspace).
+                                   Not for TRIG_TEST_MSD_FIT, not with
+                                   TRIG_EXEC_PRUNED or TRIG_EXEC_AUTOTUNE */
     TRIG_EXEC_AUTOTUNE = 8u,    /* MSD and window tests: run the batched form
                                    with the launch shape (block_hits,
                                    block_waves, fill of block_events, block

@@ -16,6 +16,9 @@
 //   k_finalize     accept flags from the accumulated counts
 //   k_block        batched form: blocks of events staged in LDS, exact pair
 //                  pruning (trig_block.hpp); optionally persistent
+//   k_binned       binned form: one wave per event, slope-cell binning of
+//                  layers 1 and 2 in LDS (trig_binned.hpp); optionally
+//                  persistent
 //   k_compact_*    ordered list of accepted event ids
 #include <hip/hip_runtime.h>
 
@@ -31,6 +34,7 @@
 #include <vector>
 
 #include "trig.h"
+#include "trig_binned.hpp"
 #include "trig_block.hpp"
 #include "trig_device.hpp"
 
@@ -297,6 +301,55 @@ __global__ __launch_bounds__(kScanBlock) void k_finalize(int n_events, Consts c,
     }
 }
 
+// --------------------------------------------------------------- binned ---
+
+constexpr int kBinWaves = 4;     // waves (one event each) per workgroup
+constexpr int kBinResident = 3;  // persistent binned workgroups per CU (LDS bound)
+
+// One wave per event, events [4 b, 4 b + 4) for workgroup block b.
+// Non-persistent when block_counter == nullptr (b = blockIdx.x); otherwise
+// workgroups take blocks from *block_counter (zero at launch) until none is
+// left.  Events with more than kBinCap hits in layer 1 or 2 take the
+// pair-pruned path from HBM.
+template <class B>
+__global__ __launch_bounds__(kBinWaves * kWave) void k_binned(
+    const int32_t* __restrict__ off, int n_events, const float* __restrict__ x, const float* __restrict__ y,
+    Consts c, unsigned* block_counter, int32_t* __restrict__ counts, uint8_t* __restrict__ accept,
+    uint32_t* status) {
+    __shared__ __align__(16) BinLds lds_all[kBinWaves];
+    __shared__ unsigned s_block;
+    const int w = uniform_i((int)(threadIdx.x / kWave));
+    BinLds& L = lds_all[w];
+    const unsigned n_blocks = (unsigned)(((int64_t)n_events + kBinWaves - 1) / kBinWaves);
+    unsigned blk = blockIdx.x;
+    for (;;) {
+        if (block_counter) {
+            // every branch below depends on workgroup-uniform values only
+            if (threadIdx.x == 0) s_block = atomicAdd(block_counter, 1u);
+            __syncthreads();
+            blk = (unsigned)uniform_i((int)s_block);
+            __syncthreads();
+        }
+        if (blk >= n_blocks) break;
+        const int e = (int)blk * kBinWaves + w;
+        if (e < n_events) {
+            EventRange ev;
+            int32_t cnt = load_event(off, e, c.n_hits, ev);
+            if (cnt == 0 && ev.n0 > 0 && ev.n1 > 0 && ev.n2 > 0) {
+                if (ev.n1 <= kBinCap && ev.n2 <= kBinCap) {
+                    cnt = (int32_t)wave_event_binned<B>(c, x, y, ev.o0, ev.n0, ev.o1, ev.n1, ev.o2, ev.n2, L);
+                } else {
+                    cnt = (int32_t)wave_event_pruned<typename B::Prune>(c, GlobalHits{x, y}, ev.o0, ev.n0, ev.o1,
+                                                                        ev.n1, ev.o2, ev.n2, L.a1, L.b1);
+                    wave_lds_sync();
+                }
+            }
+            if (lane_id() == 0) write_result(e, cnt, c, counts, accept, status);
+        }
+        if (!block_counter) break;
+    }
+}
+
 // ------------------------------------------------------------------ host ---
 
 thread_local std::string g_detail;
@@ -398,6 +451,7 @@ Consts make_consts(const trig_params* p, int n_hits) {
     c.pre_k_win = prefilter_scale(p->slope_window[1], p->slope_window[0]);
     c.win_x = p->slope_window[0];
     c.win_y = p->slope_window[1];
+    c.bin_r = p->test == TRIG_TEST_SLOPE_WINDOW ? c.win_x : std::nextafter(c.beta_x, INFINITY);
     c.min_triplets = p->min_triplets;
     c.n_hits = n_hits;
     return c;
@@ -443,8 +497,10 @@ int validate_params(const trig_params* p, bool need_outputs) {
         return fail(TRIG_EINVAL, "TRIG_OUT_COMPACT needs out_accepted_ids and out_n_accepted");
     if ((p->flags & TRIG_EXEC_PRUNED) && p->test == TRIG_TEST_MSD_FIT)
         return fail(TRIG_EUNSUPPORTED, "pruning is not provided for TRIG_TEST_MSD_FIT");
-    if (p->flags & TRIG_EXEC_BINNED)
-        return fail(TRIG_EUNSUPPORTED, "the binned form is not built in this library version");
+    if ((p->flags & TRIG_EXEC_BINNED) && p->test == TRIG_TEST_MSD_FIT)
+        return fail(TRIG_EUNSUPPORTED, "binning is not provided for TRIG_TEST_MSD_FIT");
+    if ((p->flags & TRIG_EXEC_BINNED) && (p->flags & (TRIG_EXEC_PRUNED | TRIG_EXEC_AUTOTUNE)))
+        return fail(TRIG_EUNSUPPORTED, "TRIG_EXEC_BINNED does not combine with TRIG_EXEC_PRUNED or TRIG_EXEC_AUTOTUNE");
     return TRIG_OK;
 }
 
@@ -461,7 +517,7 @@ Layout layout(int n_events, uint32_t flags) {
         L.compact_off = at;
         at += align256(sizeof(int32_t) * (size_t)(L.compact_blocks + 1));
     }
-    if ((flags & TRIG_EXEC_PERSISTENT) && (flags & TRIG_EXEC_PRUNED)) {
+    if ((flags & TRIG_EXEC_PERSISTENT) && (flags & (TRIG_EXEC_PRUNED | TRIG_EXEC_BINNED))) {
         L.counter_off = at;  // block counter only
         at += 256;
     } else if (flags & TRIG_EXEC_PERSISTENT) {
@@ -608,9 +664,31 @@ int launch_block(const trig_events_csr* ev, const trig_hits* h, const trig_param
     return TRIG_OK;
 }
 
-template <class T, class P>
+template <class B>
+int launch_binned(const trig_events_csr* ev, const trig_hits* h, const trig_params* p, const Consts& c,
+                  const Layout& L, char* ws, int32_t* counts, uint8_t* accept, hipStream_t s) {
+    const int n = ev->n_events;
+    const int64_t n_blocks = cdiv(n, kBinWaves);
+    unsigned* counter = nullptr;
+    unsigned grid = (unsigned)n_blocks;
+    if (p->flags & TRIG_EXEC_PERSISTENT) {
+        counter = reinterpret_cast<unsigned*>(ws + L.counter_off);
+        hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, counter);
+        if (int r = check_launch("k_zero_u32")) return r;
+        grid = (unsigned)std::min<int64_t>(n_blocks, (int64_t)device_cus() * kBinResident);
+    }
+    if (mark_start(s)) return fail(TRIG_EHIP, "hipEventRecord(start)");
+    hipLaunchKernelGGL(k_binned<B>, dim3(grid), dim3(kBinWaves * kWave), 0, s, ev->layer_offsets, n, h->x, h->y, c,
+                       counter, counts, accept, p->out_status);
+    if (int r = check_launch("k_binned")) return r;
+    if (mark_stop(s)) return fail(TRIG_EHIP, "hipEventRecord(stop)");
+    return TRIG_OK;
+}
+
+template <class T, class P, class B>
 int run_form(const trig_events_csr* ev, const trig_hits* h, const trig_params* p, const Consts& c,
              const Layout& L, char* ws, int32_t* counts, uint8_t* accept, hipStream_t s) {
+    if (p->flags & TRIG_EXEC_BINNED) return launch_binned<B>(ev, h, p, c, L, ws, counts, accept, s);
     if (p->flags & TRIG_EXEC_PRUNED) return launch_block<P>(ev, h, p, c, L, ws, counts, accept, s);
     if (p->flags & TRIG_EXEC_PERSISTENT) {
         const int tile_units = p->tile_pairs ? p->tile_pairs / kWave : kDefaultTileUnits;
@@ -730,13 +808,13 @@ int trig_select(const trig_events_csr* ev, const trig_hits* hits, const trig_par
         int r = TRIG_OK;
         switch (p->test) {
             case TRIG_TEST_MSD:
-                r = run_form<MsdTest, MsdPrune>(ev, hits, p, c, L, ws, out_counts, out_accept, s);
+                r = run_form<MsdTest, MsdPrune, MsdBin>(ev, hits, p, c, L, ws, out_counts, out_accept, s);
                 break;
             case TRIG_TEST_MSD_FIT:  // validated: never with TRIG_EXEC_PRUNED
-                r = run_form<MsdFitTest, MsdPrune>(ev, hits, p, c, L, ws, out_counts, out_accept, s);
+                r = run_form<MsdFitTest, MsdPrune, MsdBin>(ev, hits, p, c, L, ws, out_counts, out_accept, s);
                 break;
             default:
-                r = run_form<WindowTest, WindowPrune>(ev, hits, p, c, L, ws, out_counts, out_accept, s);
+                r = run_form<WindowTest, WindowPrune, WindowBin>(ev, hits, p, c, L, ws, out_counts, out_accept, s);
                 break;
         }
         if (r) return r;

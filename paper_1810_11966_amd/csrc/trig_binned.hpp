@@ -1,0 +1,276 @@
+// Slope-cell binned selection (the binned form) for high-multiplicity events.
+//
+// The count is the brute-force one (paper Sec. 3.2 steps 1-3) in the binary32
+// contract of include/trig.h.  Instead of scanning every (i, j) pair, each
+// layer-1 hit is put into a cell by a key that is proportional to its slope
+// x/z, and each layer-0 hit looks only at the cells that can hold a partner:
+//
+//   MSD test: a triplet passes only if |a| <= beta in both planes (see the
+//     batched form), a = f32(u + v) with u = f32(U0 x_i), v = f32(U1 x_j).  As
+//     binary32 rounding is monotone and beta_up = next float above beta,
+//     |f32(u + v)| <= beta implies -beta_up < u + v < beta_up in real numbers,
+//     so v lies in (-u - beta_up, -u + beta_up).  The layer-1 key is v.  In
+//     the same way b = f32(p + w_k) with p = f32(V0 x_i + V1 x_j) and
+//     w_k = f32(V2 x_k) needs w_k in (-p - beta_up, -p + beta_up); the
+//     layer-2 key is w_k.
+//   window test: |f32(s_j - s_i)| < W implies |s_j - s_i| < W (W is a binary32
+//     value), so s_j lies in (s_i - W, s_i + W); the same for s_k.  Here the
+//     layer-2 condition depends on i alone, so an i's count is the product of
+//     its numbers of layer-1 and layer-2 partners.
+//
+// The interval ends are rounded outwards (one binary32 step past the rounded
+// end point), and the cell of a key is a non-decreasing function of the key,
+// so the cells from cell(lower end) to cell(upper end) contain every key in
+// the interval whatever the cell width.  Every candidate then gets the full
+// binary32 test, so the count is exact; a hit whose key is not finite can
+// never pass (its a or b is infinite or NaN) and is left out.
+//
+// One wave per event.  Cells are built in LDS with a counting sort (histogram
+// of the cell indices, exclusive scan, scatter); events with more than
+// kBinCap hits in layer 1 or 2 take the batched form's pair-pruned path from
+// HBM instead.
+#pragma once
+
+#include "trig_block.hpp"
+#include "trig_device.hpp"
+
+namespace trig {
+
+constexpr int kBinCap = 512;            // layer-1 / layer-2 hits per event in LDS
+constexpr int kBinRounds = kBinCap / kWave;
+
+// Next binary32 value above f (f not NaN; +inf stays).
+__device__ __forceinline__ float next_up(float f) {
+    if (f == __builtin_inff()) return f;
+    if (f == 0.0f) return __uint_as_float(1u);  // smallest subnormal
+    const uint32_t b = __float_as_uint(f);
+    return __uint_as_float(f > 0.0f ? b + 1u : b - 1u);
+}
+__device__ __forceinline__ float next_down(float f) { return -next_up(-f); }
+
+__device__ __forceinline__ float wave_min_f(float v) {
+    for (int d = 1; d < kWave; d <<= 1) v = __builtin_fminf(v, __shfl_xor(v, d));
+    return v;
+}
+__device__ __forceinline__ float wave_max_f(float v) {
+    for (int d = 1; d < kWave; d <<= 1) v = __builtin_fmaxf(v, __shfl_xor(v, d));
+    return v;
+}
+__device__ __forceinline__ uint32_t wave_sum_u(uint32_t v) {
+    for (int d = 1; d < kWave; d <<= 1) v += (uint32_t)__shfl_xor((int)v, d);
+    return v;
+}
+
+// LDS of one wave: cell ends and the two payload floats per hit, in cell
+// order, for layers 1 and 2.  Float arrays first (16-byte aligned: the
+// fallback path reuses a1/b1 as its layer-0 buffers).
+struct BinLds {
+    float a1[kBinCap], b1[kBinCap];
+    float a2[kBinCap], b2[kBinCap];
+    int end1[kBinCap], end2[kBinCap];
+};
+
+// Cells over [kmin, kmax] of one layer.  cell(v) is non-decreasing in v
+// (binary32 subtraction, multiplication and floor are monotone, the clamps
+// too, and fmaxf maps a NaN to cell 0, as for every v when inv_w is 0).
+struct Bins {
+    float kmin, kmax, inv_w;
+    int n_cells;
+    __device__ __forceinline__ int cell(float v) const {
+        const float t = __builtin_floorf((v - kmin) * inv_w);
+        return (int)__builtin_fminf(__builtin_fmaxf(t, 0.0f), (float)(n_cells - 1));
+    }
+    // Index range [first, last) of the hits in cells cell(lo) .. cell(hi).
+    __device__ __forceinline__ void range(const int* end, float lo, float hi, int& first, int& last) const {
+        const int cl = cell(lo), ch = cell(hi);
+        first = cl > 0 ? end[cl - 1] : 0;
+        last = end[ch];
+    }
+};
+
+// Counting sort of the hits [o, o + n) (n <= kBinCap) of one layer into
+// cells of the key K::key, storing K::payload in cell order.  Whole wave.
+template <class K>
+__device__ Bins build_bins(const Consts& c, const float* __restrict__ x, const float* __restrict__ y, int o,
+                           int n, int* end, float* pa, float* pb) {
+    const int lane = (int)lane_id();
+    float key[kBinRounds];
+    float2 pay[kBinRounds];
+    float lo = __builtin_inff(), hi = -__builtin_inff();
+#pragma unroll
+    for (int r = 0; r < kBinRounds; ++r) {
+        const int t = r * kWave + lane;
+        key[r] = __builtin_nanf("");
+        if (t < n) {
+            const float xv = x[o + t], yv = y[o + t];
+            key[r] = K::key(c, xv, yv);
+            pay[r] = K::payload(c, xv, yv);
+        }
+        if (__builtin_isfinite(key[r])) {
+            lo = __builtin_fminf(lo, key[r]);
+            hi = __builtin_fmaxf(hi, key[r]);
+        } else {
+            key[r] = __builtin_nanf("");  // left out below
+        }
+    }
+    Bins b;
+    b.kmin = wave_min_f(lo);
+    b.kmax = wave_max_f(hi);
+    int nc = 64;
+    while (nc < n) nc <<= 1;  // power of two >= n, at most kBinCap
+    b.n_cells = uniform_i(nc);
+    const float width = b.kmax - b.kmin;
+    // Any non-negative scale keeps cell() monotone; the hardware reciprocal
+    // is enough to spread the keys over the cells.
+    b.inv_w = (width > 0.0f && width < __builtin_inff()) ? __builtin_amdgcn_rcpf(width) * (float)b.n_cells : 0.0f;
+    for (int t = lane; t < b.n_cells; t += kWave) end[t] = 0;
+    wave_lds_sync();
+    int cell[kBinRounds];
+#pragma unroll
+    for (int r = 0; r < kBinRounds; ++r) {
+        cell[r] = -1;
+        if (!__builtin_isnan(key[r])) {
+            cell[r] = b.cell(key[r]);
+            atomicAdd(&end[cell[r]], 1);
+        }
+    }
+    wave_lds_sync();
+    // Exclusive scan of the cell sizes: lane L owns cells [L*per, L*per + per).
+    const int per = b.n_cells / kWave;  // n_cells is a multiple of 64
+    int local = 0;
+    for (int q = 0; q < per; ++q) local += end[lane * per + q];
+    int incl = local;
+    for (int d = 1; d < kWave; d <<= 1) {
+        const int v = __shfl_up(incl, d);
+        if (lane >= d) incl += v;
+    }
+    int run = incl - local;
+    for (int q = 0; q < per; ++q) {
+        const int sz = end[lane * per + q];
+        end[lane * per + q] = run;  // start of the cell
+        run += sz;
+    }
+    wave_lds_sync();
+    // Scatter; afterwards end[cell] is the end of the cell.
+#pragma unroll
+    for (int r = 0; r < kBinRounds; ++r) {
+        if (cell[r] >= 0) {
+            const int pos = atomicAdd(&end[cell[r]], 1);
+            pa[pos] = pay[r].x;
+            pb[pos] = pay[r].y;
+        }
+    }
+    wave_lds_sync();
+    return b;
+}
+
+// ---------------------------------------------------------------- MSD ---
+
+struct MsdBin {
+    using Prune = MsdPrune;
+    struct Key1 {  // layer 1: key U1 x, payload (x, y)
+        __device__ static __forceinline__ float key(const Consts& c, float x, float) { return c.U1 * x; }
+        __device__ static __forceinline__ float2 payload(const Consts&, float x, float y) {
+            return make_float2(x, y);
+        }
+    };
+    struct Key2 {  // layer 2: key V2 x, payload (V2 x, V2 y)
+        __device__ static __forceinline__ float key(const Consts& c, float x, float) { return c.V2 * x; }
+        __device__ static __forceinline__ float2 payload(const Consts& c, float x, float y) {
+            return make_float2(c.V2 * x, c.V2 * y);
+        }
+    };
+    // Passing triplets with layer-0 hit (xi, yi).
+    __device__ static uint32_t count_i(const Consts& c, float xi, float yi, const Bins& b1, const Bins& b2,
+                                       const BinLds& L) {
+        const float ux = c.U0 * xi;
+        const float r = c.bin_r;
+        if (!__builtin_isfinite(ux)) return 0;
+        const float lo = next_down(-ux - r), hi = next_up(-ux + r);
+        if (hi < b1.kmin || lo > b1.kmax) return 0;
+        int j0, j1;
+        b1.range(L.end1, lo, hi, j0, j1);
+        uint32_t cnt = 0;
+        for (int j = j0; j < j1; ++j) {
+            const float xj = L.a1[j], yj = L.b1[j];
+            const float ax = c.U0 * xi + c.U1 * xj;
+            const float ay = c.U0 * yi + c.U1 * yj;
+            if (!(__builtin_fabsf(ax) <= c.beta_x && __builtin_fabsf(ay) <= c.beta_y)) continue;
+            const float ax2 = ax * ax, ay2 = ay * ay;
+            const float bx0 = c.V0 * xi + c.V1 * xj;
+            const float by0 = c.V0 * yi + c.V1 * yj;
+            if (!__builtin_isfinite(bx0)) continue;
+            const float lo2 = next_down(-bx0 - r), hi2 = next_up(-bx0 + r);
+            if (hi2 < b2.kmin || lo2 > b2.kmax) continue;
+            int k0, k1;
+            b2.range(L.end2, lo2, hi2, k0, k1);
+            for (int k = k0; k < k1; ++k) {
+                const float bx = bx0 + L.a2[k];
+                const float qx = ax2 + bx * bx;
+                const float by = by0 + L.b2[k];
+                const float qy = ay2 + by * by;
+                cnt += (uint32_t)((qx <= c.qmax_x) & (qy <= c.qmax_y));
+            }
+        }
+        return cnt;
+    }
+};
+
+// ------------------------------------------------------------- window ---
+
+struct WindowBin {
+    using Prune = WindowPrune;
+    struct Key1 {  // layer 1: slopes (x / z1, y / z1), key the x slope
+        __device__ static __forceinline__ float key(const Consts& c, float x, float) { return x / c.z1; }
+        __device__ static __forceinline__ float2 payload(const Consts& c, float x, float y) {
+            return make_float2(x / c.z1, y / c.z1);
+        }
+    };
+    struct Key2 {
+        __device__ static __forceinline__ float key(const Consts& c, float x, float) { return x / c.z2; }
+        __device__ static __forceinline__ float2 payload(const Consts& c, float x, float y) {
+            return make_float2(x / c.z2, y / c.z2);
+        }
+    };
+    __device__ static uint32_t count_i(const Consts& c, float xi, float yi, const Bins& b1, const Bins& b2,
+                                       const BinLds& L) {
+        const float sxi = xi / c.z0, syi = yi / c.z0;
+        if (!__builtin_isfinite(sxi)) return 0;
+        const float lo = next_down(sxi - c.bin_r), hi = next_up(sxi + c.bin_r);
+        uint32_t nj = 0, nk = 0;
+        if (!(hi < b1.kmin || lo > b1.kmax)) {
+            int j0, j1;
+            b1.range(L.end1, lo, hi, j0, j1);
+            for (int j = j0; j < j1; ++j)
+                nj += (uint32_t)((__builtin_fabsf(L.a1[j] - sxi) < c.win_x) &
+                                 (__builtin_fabsf(L.b1[j] - syi) < c.win_y));
+        }
+        if (nj == 0 || hi < b2.kmin || lo > b2.kmax) return 0;
+        int k0, k1;
+        b2.range(L.end2, lo, hi, k0, k1);
+        for (int k = k0; k < k1; ++k)
+            nk += (uint32_t)((__builtin_fabsf(L.a2[k] - sxi) < c.win_x) &
+                             (__builtin_fabsf(L.b2[k] - syi) < c.win_y));
+        return nj * nk;
+    }
+};
+
+// Passing triplets of one event with 1 <= n0 and 1 <= n1, n2 <= kBinCap,
+// hits straight from HBM (x, y absolute arrays).  Whole wave; the same count
+// on every lane.
+template <class B>
+__device__ uint32_t wave_event_binned(const Consts& c, const float* __restrict__ x, const float* __restrict__ y,
+                                      int o0, int n0, int o1, int n1, int o2, int n2, BinLds& L) {
+    const Bins b1 = build_bins<typename B::Key1>(c, x, y, o1, n1, L.end1, L.a1, L.b1);
+    const Bins b2 = build_bins<typename B::Key2>(c, x, y, o2, n2, L.end2, L.a2, L.b2);
+    uint32_t cnt = 0;
+    for (int i0 = 0; i0 < n0; i0 += kWave) {
+        const int i = i0 + (int)lane_id();
+        if (i < n0) cnt += B::count_i(c, x[o0 + i], y[o0 + i], b1, b2, L);
+    }
+    cnt = wave_sum_u(cnt);
+    wave_lds_sync();  // the next event rebuilds the cells
+    return cnt;
+}
+
+}  // namespace trig

@@ -34,6 +34,9 @@ struct Consts {
     float pre_k_msd, pre_k_win;
     // TRIG_TEST_SLOPE_WINDOW
     float win_x, win_y;
+    // Binned form: half-width of the key interval around a hit's centre
+    // (MSD: the binary32 value above beta_x; window: win_x).
+    float bin_r;
     int32_t min_triplets;
     int32_t n_hits;
 };

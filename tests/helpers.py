@@ -102,3 +102,95 @@ def pair_boundary_events(n_events, per_layer, seed, rel=1e-6, z=(400.0, 410.0, 4
             off.append(off[-1] + n)
     return synth.EventSet(np.asarray(off, np.int32), np.concatenate(xs), np.concatenate(ys),
                           np.zeros(n_events, np.int8))
+
+
+def k_boundary_events(n_events, per_layer, seed, rel=1e-6, z=(400.0, 410.0, 420.0)):
+    """Events whose tracks are displaced along the unit vector orthogonal to
+    z and to (z1, -z0, 0): only the layer-2 part b of the residual changes, by
+    |b| within a relative ``rel`` of sqrt(ndf*T) (ndf 2), so triplets sit
+    where f32(b*b) crosses Qmax (the edge of the binned form's layer-2 key
+    interval)."""
+    rng = np.random.default_rng(seed)
+    z = np.asarray(z, np.float64)
+    zh = z / np.linalg.norm(z)
+    u = np.array([z[1], -z[0], 0.0]) / np.hypot(z[0], z[1])
+    v = np.cross(zh, u)
+    xs, ys, off = [], [], [0]
+    for e in range(n_events):
+        n = per_layer
+        cs = []
+        for T in (0.03, 0.025):
+            m = rng.uniform(-0.4, 0.4, n)
+            r = np.sqrt(2 * T) * (1.0 + rng.uniform(-rel, rel, n)) * rng.choice([-1.0, 1.0], n)
+            cs.append((m[:, None] * z[None, :] + r[:, None] * v[None, :]).astype(np.float32))
+        for l in range(3):
+            perm = rng.permutation(n)
+            xs.append(cs[0][perm, l]); ys.append(cs[1][perm, l])
+            off.append(off[-1] + n)
+    return synth.EventSet(np.asarray(off, np.int32), np.concatenate(xs), np.concatenate(ys),
+                          np.zeros(n_events, np.int8))
+
+
+def window_boundary_events(n_events, per_layer, seed, w=(0.005, 0.005), rel=1e-6, z=(400.0, 410.0, 420.0)):
+    """Slope-window edge cases: layer-1 and layer-2 slopes differ from the
+    layer-0 slope by the window within a relative ``rel`` (either sign)."""
+    rng = np.random.default_rng(seed)
+    xs, ys, off = [], [], [0]
+    for e in range(n_events):
+        n = per_layer
+        layers = []
+        base = rng.uniform(-0.4, 0.4, (n, 2))
+        for l in range(3):
+            s = base.copy()
+            if l > 0:
+                for p in range(2):
+                    s[:, p] += w[p] * (1.0 + rng.uniform(-rel, rel, n)) * rng.choice([-1.0, 1.0], n)
+            layers.append((s * z[l]).astype(np.float32))
+        for l in range(3):
+            perm = rng.permutation(n)
+            xs.append(layers[l][perm, 0]); ys.append(layers[l][perm, 1])
+            off.append(off[-1] + n)
+    return synth.EventSet(np.asarray(off, np.int32), np.concatenate(xs), np.concatenate(ys),
+                          np.zeros(n_events, np.int8))
+
+
+def special_values_events(seed):
+    """Hits with NaN, +-inf, huge, subnormal and zero coordinates, mixed with
+    vertex tracks; events whose keys are all equal; events past the binned
+    form's LDS capacity."""
+    rng = np.random.default_rng(seed)
+    z = (400.0, 410.0, 420.0)
+    events = []
+
+    def track(m):
+        return [(m[0] * zl, m[1] * zl) for zl in z]
+
+    def noisy(n):
+        return [tuple(map(float, p)) for p in rng.uniform(-200, 200, (n, 2)).astype(np.float32)]
+
+    nan, inf = float("nan"), float("inf")
+    specials = [(nan, 1.0), (1.0, nan), (inf, 0.0), (-inf, 5.0), (0.0, inf), (1e30, 1e30),
+                (-3e38, 2e38), (1e-40, -1e-40), (0.0, 0.0), (-0.0, 0.0)]
+    for k in range(len(specials)):
+        layers = [noisy(6) for _ in range(3)]
+        for l in range(3):
+            layers[l].append(specials[(k + l) % len(specials)])
+            layers[l].append(specials[(k + 3 * l + 1) % len(specials)])
+            layers[l].append(track((0.1 * k - 0.3, 0.05))[l])
+        events.append(layers)
+    # every hit special
+    events.append([[specials[(l + i) % len(specials)] for i in range(7)] for l in range(3)])
+    # all hits identical (zero key width): every triplet passes
+    events.append([[track((0.2, -0.1))[l]] * 9 for l in range(3)])
+    # subnormal vertex tracks: every triplet passes
+    events.append([[(1e-41 * (i + 1), -2e-41 * (i + 1)) for i in range(5)] for l in range(3)])
+    # a vertex track among hits at the origin
+    events.append([[(0.0, 0.0)] * 4 + [track((0.3, 0.3))[l]] for l in range(3)])
+    # more hits than the binned form keeps in LDS (layer 1, layer 2)
+    for sizes in ((20, 700, 20), (20, 20, 700), (5, 513, 512)):
+        layers = [noisy(n) for n in sizes]
+        for l in range(3):
+            layers[l][0] = track((0.05, -0.2))[l]
+        layers[1][-1] = (nan, nan)
+        events.append(layers)
+    return synth.from_layers(events)

@@ -99,6 +99,11 @@ def _call(p, n_events=4, n_hits=12, offsets=0x1000, x=0x2000, y=0x3000, counts=0
     (lambda p: setattr(p, "flags", trig.TRIG_EXEC_PERSISTENT), trig.TRIG_EWORKSPACE),
     (lambda p: (setattr(p, "test", trig.TRIG_TEST_MSD_FIT), setattr(p, "flags", trig.TRIG_EXEC_PRUNED)),
      trig.TRIG_EUNSUPPORTED),
+    (lambda p: (setattr(p, "test", trig.TRIG_TEST_MSD_FIT), setattr(p, "flags", trig.TRIG_EXEC_BINNED)),
+     trig.TRIG_EUNSUPPORTED),
+    (lambda p: setattr(p, "flags", trig.TRIG_EXEC_BINNED | trig.TRIG_EXEC_PRUNED), trig.TRIG_EUNSUPPORTED),
+    (lambda p: setattr(p, "flags", trig.TRIG_EXEC_BINNED | trig.TRIG_EXEC_AUTOTUNE), trig.TRIG_EUNSUPPORTED),
+    (lambda p: setattr(p, "flags", trig.TRIG_EXEC_BINNED | trig.TRIG_EXEC_PERSISTENT), trig.TRIG_EWORKSPACE),
 ])
 def test_rejects_bad_params_before_any_launch(lib, mutate, code):
     p = trig.make_params()
@@ -182,8 +187,8 @@ def kernel_bodies(isa_text):
 
 def test_msd_kernels_have_no_fma_or_packed_fp32(isa):
     bodies = kernel_bodies(isa)
-    msd = {k: v for k, v in bodies.items() if "MsdTest" in k or "MsdFitTest" in k}
-    assert len(msd) >= 4
+    msd = {k: v for k, v in bodies.items() if re.search(r"Msd(Test|FitTest|Prune|Bin)", k)}
+    assert len(msd) >= 8
     for name, body in msd.items():
         bad = re.findall(r"\b(v_fma\w*|v_fmac\w*|v_mac_f32\w*|v_mad_f32\w*|v_mad_legacy\w*|"
                          r"v_pk_(?:add|mul|fma)_f32\w*)", body)

@@ -14,11 +14,12 @@ from tests import helpers
 pytestmark = pytest.mark.gpu
 
 TESTS = ("msd", "msd_fit", "window")
-FORMS = ("plain", "persistent", "pruned", "persistent_pruned", "auto")
+FORMS = ("plain", "persistent", "pruned", "persistent_pruned", "binned", "persistent_binned", "auto")
+EXACT_ONLY = ("pruned", "binned")  # forms without the MSD_FIT test
 
 
 def forms_for(test):
-    return [f for f in FORMS if not (test == "msd_fit" and "pruned" in f)]
+    return [f for f in FORMS if not (test == "msd_fit" and any(t in f for t in EXACT_ONLY))]
 
 
 @pytest.fixture(scope="module")
@@ -99,7 +100,7 @@ def test_golden_cases(gpu, form):
         if "window" in cfg:
             kw["slope_window"] = cfg["window"]
         for t in ([test] if test == "window" else ["msd", "msd_fit"]):
-            if t == "msd_fit" and "pruned" in form:
+            if t == "msd_fit" and any(x in form for x in EXACT_ONLY):
                 continue
             print(f"[golden] {case['name']} {t} {form}", flush=True)
             got = run_gpu(gpu, s, t, form, **kw)
@@ -200,7 +201,7 @@ def test_ragged_layer_sizes(gpu):
         for form in forms_for(test):
             assert_parity(gpu, s, test, form, "ragged")
             for tp in (64, 128, 1024):
-                if "persistent" in form:
+                if form == "persistent":
                     assert_parity(gpu, s, test, form, f"ragged tile_pairs={tp}", tile_pairs=tp)
 
 
@@ -208,9 +209,10 @@ def test_dense_and_mixture_samples(gpu):
     dense = synth.make_event_set(synth.DENSE_100K, n_events=400)
     mix = synth.make_event_set(synth.MIXTURE_4M, n_events=4000)
     for s, label in ((dense, "dense_100k[:400]"), (mix, "mixture_4m[:4000]")):
-        for form in ("plain", "pruned", "persistent_pruned"):
+        for form in ("plain", "pruned", "persistent_pruned", "binned", "persistent_binned"):
             assert_parity(gpu, s, "msd", form, label)
-        assert_parity(gpu, s, "window", "persistent", label)
+        for form in ("persistent", "binned"):
+            assert_parity(gpu, s, "window", form, label)
 
 
 def test_injected_exact_tracks_accept(gpu):
@@ -221,6 +223,37 @@ def test_injected_exact_tracks_accept(gpu):
     for form in FORMS:
         c = assert_parity(gpu, s, "msd", form, "exact pairs")
     assert (c[s.n_tracks > 0] >= 2).all()
+
+
+# ---------------------------------------------------- binning edge cases ---
+
+def test_binned_key_interval_edges(gpu):
+    """Pairs at the edge of the layer-1 key interval (|a| at beta), triplets
+    at the edge of the layer-2 interval (|b| at beta), slopes at the window
+    edge: the binned form keeps every candidate that can pass."""
+    pair = synth.concat([helpers.pair_boundary_events(200, 6, seed=5, rel=1e-6),
+                         helpers.pair_boundary_events(200, 6, seed=6, rel=3e-8)])
+    kb = synth.concat([helpers.k_boundary_events(200, 6, seed=7, rel=1e-6),
+                       helpers.k_boundary_events(200, 6, seed=8, rel=3e-8)])
+    win = synth.concat([helpers.window_boundary_events(200, 6, seed=9, rel=1e-6),
+                        helpers.window_boundary_events(200, 6, seed=10, rel=3e-8)])
+    for form in ("plain", "binned", "persistent_binned", "pruned"):
+        c1 = assert_parity(gpu, pair, "msd", form, "layer-1 key edge")
+        c2 = assert_parity(gpu, kb, "msd", form, "layer-2 key edge")
+        c3 = assert_parity(gpu, win, "window", form, "window edge")
+    assert c1.sum() > 0 and c2.sum() > 0 and c3.sum() > 0
+    for form in ("plain", "binned"):
+        assert_parity(gpu, kb, "msd", form, "layer-2 key edge ndf3", ndf=3, msd_max=(0.02, 0.016666668))
+        assert_parity(gpu, win, "window", form, "window edge W=0.0049999", slope_window=(0.0049999, 0.0050001))
+
+
+def test_special_coordinate_values(gpu):
+    """NaN, +-inf, huge, subnormal and zero coordinates, zero-width key ranges
+    and events past the binned form's LDS capacity, in every form."""
+    s = helpers.special_values_events(seed=3)
+    for test in TESTS:
+        for form in forms_for(test):
+            assert_parity(gpu, s, test, form, "special values")
 
 
 # ------------------------------------------------------------ error paths ---

@@ -315,3 +315,25 @@ def test_malformed_ranges_and_overflow(oracle_lib):
 def test_empty_batch(oracle_lib):
     c, a, st, _ = R.select(np.zeros(1, np.int32), np.zeros(0, np.float32), np.zeros(0, np.float32))
     assert len(c) == 0 and st == 0
+
+
+# ------------------------------------------------------- special values ---
+
+@pytest.mark.parametrize("mode", MODES)
+def test_special_coordinate_values(oracle_lib, mode):
+    """NaN and infinite coordinates never pass (every comparison with NaN is
+    false and an infinite residual exceeds any threshold); the two oracles
+    agree on them, and the events with closed-form counts get them."""
+    s = helpers.special_values_events(seed=3)
+    cfg = R.OracleConfig(test=mode)
+    c, a, st, _ = R.select_set(s, cfg)
+    with np.errstate(all="ignore"):
+        n, na, nst = R.select_numpy(s.offsets, s.x, s.y, cfg)
+    assert np.array_equal(c, n) and np.array_equal(a, na) and st == nst == 0
+    # all hits identical on one vertex track: 9^3 triplets; five subnormal
+    # vertex tracks: every one of the 5^3 triplets lies within 1e-40 cm of a
+    # line through the vertex; four hits at the origin plus one track: 4^3 + 1
+    assert c[11] == 9 ** 3 and c[12] == 5 ** 3 and c[13] == 4 ** 3 + 1
+    # special values only: no layer-0 hit has two finite coordinates below
+    # 1e30 in magnitude, so no triplet can pass
+    assert c[10] == 0
