@@ -134,15 +134,18 @@ enum {
                                    groups from a counter (needs workspace).
                                    Not for TRIG_TEST_MSD_FIT, not with
                                    TRIG_EXEC_PRUNED or TRIG_EXEC_AUTOTUNE */
-    TRIG_EXEC_AUTOTUNE = 8u,    /* MSD and window tests: run the batched form
-                                   with the launch shape (block_hits,
-                                   block_waves, fill of block_events, block
-                                   stealing on or off) that trig_autotune
-                                   recorded for this device, test and
-                                   multiplicity class (floor(log2(mean hits
-                                   per event))); without a record, the
-                                   built-in rule.  Non-zero block_* fields
-                                   win over the record.  MSD_FIT: the
+    TRIG_EXEC_AUTOTUNE = 8u,    /* MSD and window tests: run the form that
+                                   trig_autotune recorded for this device,
+                                   test and multiplicity class
+                                   (floor(log2(mean hits per event))): the
+                                   batched form with its launch shape
+                                   (block_hits, block_waves, fill of
+                                   block_events, block stealing on or off),
+                                   or the binned form with or without
+                                   stealing; without a record, the batched
+                                   form with the built-in rule.  Non-zero
+                                   block_* fields win over the record and
+                                   select the batched form.  MSD_FIT: the
                                    caller's brute-force flags.  Needs the
                                    workspace of trig_workspace_bytes() for
                                    these flags */
@@ -225,20 +228,23 @@ int trig_select(const trig_events_csr *ev, const trig_hits *hits, const trig_par
 typedef struct {
     int32_t n_candidates;     /* launch shapes timed (0 for MSD_FIT) */
     int32_t mult_class;       /* multiplicity class of the batch */
-    int32_t block_hits;       /* chosen shape */
+    int32_t block_hits;       /* chosen batched-form shape (0 if binned) */
     int32_t block_waves;
     int32_t block_events;     /* events per block for this batch */
     int32_t persistent;       /* 1 if block stealing won */
+    int32_t binned;           /* 1 if the binned form won */
     float ms_best;            /* mean kernel time of the chosen shape, ms */
     float ms_rule;            /* same for the built-in rule's shape */
 } trig_autotune_result;
 
-/* Times the batched form's launch shapes on this batch and records the fastest
- * for the batch's multiplicity class (per device and test), for later calls
- * with TRIG_EXEC_AUTOTUNE.  Candidates: block_hits 1024/2048/4096 x
- * block_waves 1/2/4 x block fill 0.4/0.6/0.8 of the LDS capacity (in mean
- * event sizes) x block stealing off/on, each timed `reps` times (1..100) after
- * one warm-up; every candidate computes the same counts.  Arguments are those
+/* Times the batched form's launch shapes and the binned form on this batch
+ * and records the fastest for the batch's multiplicity class (per device and
+ * test), for later calls with TRIG_EXEC_AUTOTUNE.  Candidates: the built-in
+ * rule's shape; block_hits 1024/2048/4096 x block_waves 1/2/4 x block fill
+ * 0.4/0.6/0.8 of the LDS capacity (in mean event sizes) x block stealing
+ * off/on; the binned form with and without stealing.  Each is timed `reps`
+ * times (1..100) after one warm-up; every candidate computes the same
+ * counts.  Arguments are those
  * of trig_select, with TRIG_EXEC_AUTOTUNE set in p->flags; block_* fields of
  * p are ignored while timing.  On return (the call synchronises `stream`)
  * out_counts, out_accept (and the compact outputs, if requested) hold the

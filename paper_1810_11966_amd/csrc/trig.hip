@@ -711,6 +711,7 @@ struct TunedShape {
     int hb, nw;
     double fill;  // events per block = fill * hb / mean hits per event
     bool persistent;
+    bool binned;  // the binned form (hb, nw, fill unused)
 };
 
 int events_for_fill(double fill, int hb, int n_events, int n_hits) {
@@ -727,9 +728,10 @@ int current_device() {
     return d;
 }
 
-// Effective parameters of a TRIG_EXEC_AUTOTUNE call: the batched form for the
-// tests that have it, with the recorded shape of the batch's class (fields the
-// caller set explicitly win), else the built-in rule.
+// Effective parameters of a TRIG_EXEC_AUTOTUNE call for the tests that have
+// the batched and binned forms: the recorded form and shape of the batch's
+// class, else the batched form with the built-in rule.  Block fields the
+// caller set explicitly win over the record and select the batched form.
 trig_params resolve_autotune(const trig_params* p, int n_events, int n_hits) {
     trig_params q = *p;
     q.flags &= ~(uint32_t)TRIG_EXEC_AUTOTUNE;
@@ -739,6 +741,12 @@ trig_params resolve_autotune(const trig_params* p, int n_events, int n_hits) {
     auto it = g_tuned.find({current_device(), p->test, multiplicity_class(n_events, n_hits)});
     if (it != g_tuned.end()) {
         const TunedShape& t = it->second;
+        if (t.binned && !p->block_hits && !p->block_waves && !p->block_events) {
+            q.flags = (q.flags & ~(uint32_t)TRIG_EXEC_PRUNED) | TRIG_EXEC_BINNED |
+                      (t.persistent ? (uint32_t)TRIG_EXEC_PERSISTENT : 0u);
+            return q;
+        }
+        if (t.binned) return q;
         if (!q.block_hits) q.block_hits = t.hb;
         if (!q.block_waves) q.block_waves = t.nw;
         if (!q.block_events) q.block_events = events_for_fill(t.fill, q.block_hits, n_events, n_hits);
@@ -863,7 +871,7 @@ int trig_autotune(const trig_events_csr* ev, const trig_hits* hits, const trig_p
         // Times one candidate: the whole selection without compaction.
         auto time_shape = [&](const TunedShape& t, float& ms) -> int {
             trig_params q = *p;
-            q.flags = TRIG_EXEC_PRUNED | (t.persistent ? TRIG_EXEC_PERSISTENT : 0u);
+            q.flags = (t.binned ? TRIG_EXEC_BINNED : TRIG_EXEC_PRUNED) | (t.persistent ? TRIG_EXEC_PERSISTENT : 0u);
             q.block_hits = t.hb;
             q.block_waves = t.nw;
             q.block_events = events_for_fill(t.fill, t.hb, n, n_hits);
@@ -886,7 +894,7 @@ int trig_autotune(const trig_events_csr* ev, const trig_hits* hits, const trig_p
         trig_params rp = *p;
         rp.block_hits = rp.block_waves = rp.block_events = 0;
         const BlockShape r0 = choose_block_shape(&rp, n, n_hits);
-        TunedShape best{r0.hb, r0.nw, 0.6, false};
+        TunedShape best{r0.hb, r0.nw, 0.6, false, false};
         int rc = time_shape(best, res.ms_rule);
         res.ms_best = res.ms_rule;
         if (rc == TRIG_OK) res.n_candidates = 1;
@@ -896,7 +904,7 @@ int trig_autotune(const trig_events_csr* ev, const trig_hits* hits, const trig_p
             for (int b = 0; b < 3 && rc == TRIG_OK; ++b)
                 for (int f = 0; f < 3 && rc == TRIG_OK; ++f)
                     for (int ps = 0; ps < 2 && rc == TRIG_OK; ++ps) {
-                        const TunedShape t{hbs[a], nws[b], fills[f], ps == 1};
+                        const TunedShape t{hbs[a], nws[b], fills[f], ps == 1, false};
                         float ms = 0.0f;
                         rc = time_shape(t, ms);
                         if (rc == TRIG_OK) {
@@ -907,6 +915,18 @@ int trig_autotune(const trig_events_csr* ev, const trig_hits* hits, const trig_p
                             }
                         }
                     }
+        for (int ps = 0; ps < 2 && rc == TRIG_OK; ++ps) {
+            const TunedShape t{0, 0, 0.0, ps == 1, true};
+            float ms = 0.0f;
+            rc = time_shape(t, ms);
+            if (rc == TRIG_OK) {
+                ++res.n_candidates;
+                if (ms < res.ms_best) {
+                    res.ms_best = ms;
+                    best = t;
+                }
+            }
+        }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
         if (rc) return rc;
@@ -921,11 +941,14 @@ int trig_autotune(const trig_events_csr* ev, const trig_hits* hits, const trig_p
     if (int r = trig_select(ev, hits, &q, out_counts, out_accept, stream)) return r;
     if (p->test != TRIG_TEST_MSD_FIT && n > 0) {
         const trig_params eff = resolve_autotune(&q, n, n_hits);
-        const BlockShape bs = choose_block_shape(&eff, n, n_hits);
-        res.block_hits = bs.hb;
-        res.block_waves = bs.nw;
-        res.block_events = bs.eb;
         res.persistent = (eff.flags & TRIG_EXEC_PERSISTENT) ? 1 : 0;
+        res.binned = (eff.flags & TRIG_EXEC_BINNED) ? 1 : 0;
+        if (!res.binned) {
+            const BlockShape bs = choose_block_shape(&eff, n, n_hits);
+            res.block_hits = bs.hb;
+            res.block_waves = bs.nw;
+            res.block_events = bs.eb;
+        }
     }
     if (hipStreamSynchronize(s) != hipSuccess) return fail(TRIG_EHIP, "hipStreamSynchronize failed");
     if (out) *out = res;

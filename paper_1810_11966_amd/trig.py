@@ -77,7 +77,7 @@ class TrigAutotuneResult(ctypes.Structure):
     _fields_ = [("n_candidates", ctypes.c_int32), ("mult_class", ctypes.c_int32),
                 ("block_hits", ctypes.c_int32), ("block_waves", ctypes.c_int32),
                 ("block_events", ctypes.c_int32), ("persistent", ctypes.c_int32),
-                ("ms_best", ctypes.c_float), ("ms_rule", ctypes.c_float)]
+                ("binned", ctypes.c_int32), ("ms_best", ctypes.c_float), ("ms_rule", ctypes.c_float)]
 
 
 class TrigError(RuntimeError):
