@@ -8,7 +8,8 @@
  * can be hidden behind the computation of another (Sec. 4.3).  This runtime
  * does that for a stream of timeslices:
  *   - submit() copies a slice (host CSR offsets and x, y) into pinned staging
- *     owned by the server and queues it;
+ *     owned by the server (large slices with a few host threads) and queues
+ *     it;
  *   - a dispatcher thread admits queued slices first-come first-served as soon
  *     as a stream slot is free and the slice's device footprint (inputs,
  *     outputs, workspace) fits the server's HBM arena; each admitted slice is
@@ -94,6 +95,11 @@ int trig_server_poll(trig_server *srv, trig_slice_result *out, int32_t timeout_m
 /* Frees the host buffers of a polled result.  TRIG_EINVAL for an unknown or
  * not yet polled ticket. */
 int trig_server_release(trig_server *srv, uint64_t ticket);
+
+/* Stops (paused != 0) or resumes admission of queued slices; slices already
+ * on the device finish either way.  Lets a caller stage several slices and
+ * release them together, or drain the device.  TRIG_EINVAL for NULL. */
+int trig_server_pause(trig_server *srv, int32_t paused);
 
 /* Current counters. */
 int trig_server_stats_get(trig_server *srv, trig_server_stats *out);

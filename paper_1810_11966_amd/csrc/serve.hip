@@ -2,6 +2,7 @@
 // (include/trig_serve.h).  Admission logic lives in serve_core.hpp.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <atomic>
 #include <chrono>
 #include <condition_variable>
@@ -47,6 +48,38 @@ struct Layout {
 
 enum class State { Queued, InFlight, Done, Polled };
 
+// Host copies into pinned staging: large slices are split over a few threads
+// (one host thread copies far below the PCIe rate).
+struct CopySeg {
+    char* dst;
+    const char* src;
+    size_t bytes;
+};
+constexpr size_t kCopyParallelMin = 8u << 20;  // below this, one memcpy per segment
+constexpr unsigned kCopyThreadsMax = 8;
+
+void copy_segments(const CopySeg* seg, int n_seg) {
+    size_t total = 0;
+    for (int i = 0; i < n_seg; ++i) total += seg[i].bytes;
+    const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+    const unsigned nt = total < kCopyParallelMin ? 1u : std::min(kCopyThreadsMax, hw);
+    // Thread q copies bytes [q*total/nt, (q+1)*total/nt) of the concatenation.
+    auto part = [&](unsigned q) {
+        const size_t lo = total * q / nt, hi = total * (q + 1) / nt;
+        size_t base = 0;
+        for (int i = 0; i < n_seg; ++i) {
+            const size_t a = std::max(lo, base), b = std::min(hi, base + seg[i].bytes);
+            if (a < b) std::memcpy(seg[i].dst + (a - base), seg[i].src + (a - base), b - a);
+            base += seg[i].bytes;
+        }
+    };
+    std::vector<std::thread> th;
+    th.reserve(nt - 1);
+    for (unsigned q = 1; q < nt; ++q) th.emplace_back(part, q);
+    part(0);
+    for (auto& t : th) t.join();
+}
+
 struct Slice {
     uint64_t ticket = 0;
     int32_t n_events = 0, n_hits = 0;
@@ -74,6 +107,7 @@ struct trig_server {
     std::condition_variable cv_work, cv_done;
     std::thread dispatcher;
     bool stop = false;
+    bool paused = false;  // admit nothing while set
     uint64_t next_ticket = 1;
     trig_server_stats stats{};
     std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
@@ -147,7 +181,7 @@ struct trig_server {
         std::unique_lock<std::mutex> lk(mu);
         for (;;) {
             // Admit queued slices while a stream is free and memory fits.
-            if (!stop) {
+            if (!stop && !paused) {
                 for (int si = 0; si < (int)streams.size(); ++si) {
                     if (stream_ticket[si]) continue;
                     uint64_t t;
@@ -262,11 +296,10 @@ int trig_server_submit(trig_server* s, const int32_t* offsets, const float* x, c
         ++s->stats.pending;  // counted now; the staging below completes before it can be admitted
     }
     char* h = s->pin_base + pin_off;
-    std::memcpy(h + L.off, offsets, 4 * (size_t)(3 * n_events + 1));
-    if (n_hits) {
-        std::memcpy(h + L.x, x, 4 * (size_t)n_hits);
-        std::memcpy(h + L.y, y, 4 * (size_t)n_hits);
-    }
+    const CopySeg seg[3] = {{h + L.off, reinterpret_cast<const char*>(offsets), 4 * (size_t)(3 * n_events + 1)},
+                            {h + L.x, reinterpret_cast<const char*>(x), n_hits ? 4 * (size_t)n_hits : 0},
+                            {h + L.y, reinterpret_cast<const char*>(y), n_hits ? 4 * (size_t)n_hits : 0}};
+    copy_segments(seg, 3);
     std::memset(h + L.status, 0, 4);
     {
         std::lock_guard<std::mutex> lk(s->mu);
@@ -316,6 +349,16 @@ int trig_server_release(trig_server* s, uint64_t ticket) {
     if (it == s->slices.end() || it->second.state != State::Polled) return TRIG_EINVAL;
     s->pin_arena.release(it->second.pin_off);
     s->slices.erase(it);
+    return TRIG_OK;
+}
+
+int trig_server_pause(trig_server* s, int32_t paused) {
+    if (!s) return TRIG_EINVAL;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->paused = paused != 0;
+    }
+    s->cv_work.notify_all();
     return TRIG_OK;
 }
 

@@ -54,6 +54,8 @@ def _lib():
         lib.trig_server_poll.argtypes = [vp, ctypes.POINTER(SliceResult), ctypes.c_int32]
         lib.trig_server_release.restype = ctypes.c_int
         lib.trig_server_release.argtypes = [vp, ctypes.c_uint64]
+        lib.trig_server_pause.restype = ctypes.c_int
+        lib.trig_server_pause.argtypes = [vp, ctypes.c_int32]
         lib.trig_server_stats_get.restype = ctypes.c_int
         lib.trig_server_stats_get.argtypes = [vp, ctypes.POINTER(ServerStats)]
         lib.trig_server_now.restype = ctypes.c_double
@@ -132,6 +134,12 @@ class Server:
                      float(r.t_submit), float(r.t_admit), float(r.t_done))
         _lib().trig_server_release(self._h, r.ticket)
         return f
+
+    def pause(self, paused: bool = True) -> None:
+        """Stop (or resume) admitting queued slices."""
+        rc = _lib().trig_server_pause(self._h, 1 if paused else 0)
+        if rc:
+            raise trig.TrigError(rc, "trig_server_pause")
 
     def stats(self) -> ServerStats:
         st = ServerStats()

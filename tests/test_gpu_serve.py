@@ -53,7 +53,18 @@ def test_alone_equals_mix_equals_oracle(srv_mod):
             alone.append(f)
     print("[serve] mix", flush=True)
     with srv_mod.Server(1 << 30, 1 << 30, n_streams=4) as srv:
-        done, tickets, _ = srv_mod.run_stream(srv, slices, np.zeros(len(slices)), pace=False)
+        # stage every slice first, then release them together: up to four
+        # are on the device at once
+        srv.pause(True)
+        tickets = {i: srv.submit(s.offsets, s.x, s.y) for i, s in enumerate(slices)}
+        assert all(t is not None for t in tickets.values())
+        assert srv.stats().in_flight == 0
+        srv.pause(False)
+        done = {}
+        while len(done) < len(slices):
+            f = srv.poll(60000)
+            assert f is not None
+            done[f.ticket] = f
         st = srv.stats()
     assert st.completed == len(slices) and st.max_in_flight >= 2
     for i, s in enumerate(slices):
