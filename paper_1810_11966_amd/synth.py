@@ -22,7 +22,9 @@ depends only on (spec, seed), never on how many processes generate it.
 from __future__ import annotations
 
 import hashlib
+import os
 import math
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass, field, replace
 from typing import Optional
 
@@ -195,11 +197,19 @@ def _gen_chunk(spec: EventSetSpec, seed: int, chunk: int, n_ev: int):
 def make_event_set(spec: EventSetSpec, seed: int = 0, n_events: Optional[int] = None) -> EventSet:
     """Generate ``spec`` (optionally only its first ``n_events`` events)."""
     n = spec.n_events if n_events is None else int(n_events)
-    seg_lens, xs, ys, ntrs = [], [], [], []
-    for c in range((n + CHUNK - 1) // CHUNK):
-        n_ev = min(CHUNK, n - c * CHUNK)
-        sl, x, y, nt = _gen_chunk(spec, seed, c, n_ev)
-        seg_lens.append(sl); xs.append(x); ys.append(y); ntrs.append(nt)
+    n_chunks = (n + CHUNK - 1) // CHUNK
+    jobs = [(c, min(CHUNK, n - c * CHUNK)) for c in range(n_chunks)]
+    # Chunks draw from independent streams, so threads give the same bytes.
+    workers = max(1, min(8, len(os.sched_getaffinity(0)), n_chunks))
+    if workers > 1:
+        with ThreadPoolExecutor(workers) as pool:
+            parts = list(pool.map(lambda job: _gen_chunk(spec, seed, job[0], job[1]), jobs))
+    else:
+        parts = [_gen_chunk(spec, seed, c, n_ev) for c, n_ev in jobs]
+    seg_lens = [q[0] for q in parts]
+    xs = [q[1] for q in parts]
+    ys = [q[2] for q in parts]
+    ntrs = [q[3] for q in parts]
     if n == 0:
         return EventSet(np.zeros(1, np.int32), np.zeros(0, np.float32), np.zeros(0, np.float32),
                         np.zeros(0, np.int8), spec, seed)
