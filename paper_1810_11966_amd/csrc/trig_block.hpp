@@ -76,12 +76,6 @@ struct MsdPrune {
         const float ay = p.y + q.y;
         return lanes(__builtin_fabsf(ax) <= c.beta_x) & lanes(__builtin_fabsf(ay) <= c.beta_y);
     }
-    // The same test for this lane alone.
-    __device__ static __forceinline__ bool pair_ok(const Consts& c, float2 p, float2 q) {
-        const float ax = p.x + q.x;
-        const float ay = p.y + q.y;
-        return (__builtin_fabsf(ax) <= c.beta_x) & (__builtin_fabsf(ay) <= c.beta_y);
-    }
     // Prefilter score: pair_mask's lane set is within {score <= bound()}.
     __device__ static __forceinline__ float score(const Consts& c, float2 p, float2 q) {
         const float ax = p.x + q.x;
@@ -126,9 +120,6 @@ struct WindowPrune {
     }
     __device__ static __forceinline__ uint64_t pair_mask(const Consts& c, float2 p, float2 q) {
         return lanes(__builtin_fabsf(q.x - p.x) < c.win_x) & lanes(__builtin_fabsf(q.y - p.y) < c.win_y);
-    }
-    __device__ static __forceinline__ bool pair_ok(const Consts& c, float2 p, float2 q) {
-        return (__builtin_fabsf(q.x - p.x) < c.win_x) & (__builtin_fabsf(q.y - p.y) < c.win_y);
     }
     __device__ static __forceinline__ float score(const Consts& c, float2 p, float2 q) {
         return __builtin_fmaxf(__builtin_fabsf(q.x - p.x), __builtin_fabsf(q.y - p.y) * c.pre_k_win);
@@ -308,6 +299,9 @@ __device__ void wave_event(const Consts& c, const H& hits, int h_base, int o0, i
     }
 }
 
+// The block kernel.  Non-persistent when block_counter == nullptr (block =
+// blockIdx.x); otherwise workgroups take blocks from *block_counter until
+// they run out (the counter must be zero at launch).
 // Copies hits [base, base + nh) of x and y into xs/ys (LDS) at local index
 // (h - a0), a0 = base rounded down to a multiple of 4, with 16-byte loads
 // issued together (every thread's loads are in flight before any LDS write).
@@ -363,21 +357,6 @@ __device__ __forceinline__ void stage_hits(const float* __restrict__ x, const fl
     }
 }
 
-constexpr int kQCap = 512;  // candidate pairs of one sub-block queued in LDS
-
-// The block kernel.  Non-persistent when block_counter == nullptr (block =
-// blockIdx.x); otherwise workgroups take blocks from *block_counter until
-// they run out (the counter must be zero at launch).
-//
-// Per sub-block of events staged in LDS, the pair scan is flat over the
-// sub-block: lane slot s stands for one layer-1 hit j of one event (slots
-// are numbered event after event, so a wave's 64 lanes may span several
-// events) and scans that event's layer-0 partials four at a time, keeping the
-// smallest prefilter score.  Lanes whose smallest score reaches the bound
-// re-test their pairs exactly and queue the pairs that can pass; the queue is
-// then completed against layer 2 one pair per wave (lanes over k) and the
-// counts are added per event.  If more than kQCap pairs qualify, the
-// sub-block is counted again event by event (per-event pruned path).
 template <class P, int HB, int NW>
 __global__ __launch_bounds__(NW * kWave) void k_block(const int32_t* __restrict__ off, int n_events,
                                                          const float* __restrict__ x,
@@ -388,19 +367,14 @@ __global__ __launch_bounds__(NW * kWave) void k_block(const int32_t* __restrict_
     // HB hits plus up to 3 before the first and 3 after the last (4-aligned copy)
     __shared__ __align__(16) float stage_x[HB + 8];
     __shared__ __align__(16) float stage_y[HB + 8];
-    __shared__ __align__(16) float2 upart[HB + 8];  // layer-0 partial of every staged hit
     constexpr int NT = NW * kWave;
     __shared__ __align__(16) float pbuf_x[NW][kPBuf];
     __shared__ __align__(16) float pbuf_y[NW][kPBuf];
     __shared__ int32_t soff[3 * kMaxEB + 1];
-    __shared__ int4 desc0[kMaxEB];          // o0, n0, o1, n1 (local hit indices)
-    __shared__ int2 desc1[kMaxEB];          // o2, n2 (n2 = 0: no pairs to scan)
-    __shared__ int32_t wpre[kMaxEB + 1];    // first lane slot of each event
+    __shared__ int4 desc0[kMaxEB], desc1[kMaxEB];
     __shared__ int32_t sres[kMaxEB];
-    __shared__ uint32_t qbuf[kQCap];
-    __shared__ int s_block, s_bad, s_qn;
+    __shared__ int s_block, s_bad;
     const int w = uniform_i(threadIdx.x / kWave);
-    const int lane = (int)lane_id();
     float* px = pbuf_x[w];
     float* py = pbuf_y[w];
     const GlobalHits ghits{x, y};
@@ -470,122 +444,38 @@ __global__ __launch_bounds__(NW * kWave) void k_block(const int32_t* __restrict_
             const int nh = soff[3 * end] - base;
             const int nsub = end - cur;
             stage_hits<HB, NT>(x, y, base, nh, c.n_hits, vec != 0, stage_x, stage_y);
-            // Per-event descriptors, one lane per event: local offsets and
-            // sizes; events decided without pairs get their result here (0
-            // for an empty layer, -2 for a count beyond int32).
+            // Per-event descriptors, one lane per event: local offsets,
+            // sizes, lane layout; events decided without pairs get their
+            // result here (0 for an empty layer, -2 for a count beyond int32).
             const int a0 = base & ~3;
             for (int te = t; te < nsub; te += NT) {
                 const int ev = cur + te;
                 const int b0 = soff[3 * ev], b1 = soff[3 * ev + 1], b2 = soff[3 * ev + 2], b3 = soff[3 * ev + 3];
                 const int n0 = b1 - b0, n1 = b2 - b1, n2 = b3 - b2;
                 const int64_t n01 = (int64_t)n0 * n1;
-                int res = 0, work = 0;
-                if (n2 > 0 && (n01 > (int64_t)INT32_MAX || n01 * n2 > (int64_t)INT32_MAX))
+                int R = 0, T = 0, res = 0, work = 0;
+                if (n2 > 0 && (n01 > (int64_t)INT32_MAX || n01 * n2 > (int64_t)INT32_MAX)) {
                     res = -2;
-                else if (n0 > 0 && n1 > 0 && n2 > 0)
+                } else if (n0 > 0 && n1 > 0 && n2 > 0) {
                     work = 1;
+                    lane_layout(n0, n1, R, T);
+                }
                 desc0[te] = make_int4(b0 - a0, n0, b1 - a0, n1);
-                desc1[te] = make_int2(b2 - a0, work ? n2 : 0);
+                desc1[te] = make_int4(b2 - a0, n2, work ? R : 0, T);
                 sres[te] = res;
             }
-            if (t == 0) s_qn = 0;
             __syncthreads();
-            // Layer-0 partials of every staged hit (only layer-0 entries are
-            // used), and the lane-slot prefix over the events (wave 0, two
-            // events per lane: nsub <= 128).
-            const int lo = base - a0;
-            for (int h = t; h < nh; h += NT)
-                upart[lo + h] = P::layer0(c, make_float2(stage_x[lo + h], stage_y[lo + h]));
-            if (w == 0) {
-                const int ea = 2 * lane, eb2 = 2 * lane + 1;
-                const int ca = (ea < nsub && desc1[ea].y > 0) ? desc0[ea].w : 0;
-                const int cb = (eb2 < nsub && desc1[eb2].y > 0) ? desc0[eb2].w : 0;
-                int incl = ca + cb;
-                for (int d = 1; d < kWave; d <<= 1) {
-                    const int v = __shfl_up(incl, d);
-                    if (lane >= d) incl += v;
-                }
-                const int ex = incl - (ca + cb);
-                if (ea < nsub) wpre[ea] = ex;
-                if (eb2 < nsub) wpre[eb2] = ex + ca;
-                if (lane == kWave - 1) wpre[nsub] = incl;
-            }
-            __syncthreads();
-            // Flat pair scan.
-            const int wtot = uniform_i(wpre[nsub]);
-            const float bnd = P::bound(c);
-            for (int s0 = w * kWave; s0 < wtot; s0 += NT) {
-                const int sl = s0 + lane;
-                int te = 0, o0 = 0, n0 = 0, j = 0;
-                if (sl < wtot) {
-                    int lo_e = 0, hi_e = nsub;  // wpre[lo_e] <= sl < wpre[hi_e]
-                    while (hi_e - lo_e > 1) {
-                        const int mid = (lo_e + hi_e) >> 1;
-                        if (wpre[mid] <= sl)
-                            lo_e = mid;
-                        else
-                            hi_e = mid;
-                    }
-                    te = lo_e;
-                    const int4 d0 = desc0[te];
-                    o0 = d0.x;
-                    n0 = d0.y;
-                    j = d0.z + (sl - wpre[te]);
-                }
-                const float2 v = P::layer1(c, make_float2(stage_x[j], stage_y[j]));
-                // Entries past the lane's last layer-0 hit only enter the
-                // prefilter (at most three, all within the staged range).
-                float smin = __builtin_nanf("");
-                for (int i = 0; i < n0; i += 4) {
-                    const float2 u0 = upart[o0 + i], u1 = upart[o0 + i + 1];
-                    const float2 u2 = upart[o0 + i + 2], u3 = upart[o0 + i + 3];
-                    const float m01 = __builtin_fminf(P::score(c, u0, v), P::score(c, u1, v));
-                    const float m23 = __builtin_fminf(P::score(c, u2, v), P::score(c, u3, v));
-                    smin = __builtin_fminf(smin, __builtin_fminf(m01, m23));
-                }
-                if (smin <= bnd) {
-                    // Rare: the exact pair test of this lane's pairs.
-                    for (int i = 0; i < n0; ++i) {
-                        if (P::pair_ok(c, upart[o0 + i], v)) {
-                            const int slot = atomicAdd(&s_qn, 1);
-                            if (slot < kQCap)
-                                qbuf[slot] = ((uint32_t)te << 24) | ((uint32_t)i << 12) |
-                                             (uint32_t)(j - desc0[te].z);
-                        }
-                    }
-                }
-            }
-            __syncthreads();
+            // Events round-robin over the waves (a static assignment: no
+            // per-wave claim loop).
             const LdsHits lh{stage_x, stage_y};
-            const int nq = uniform_i(s_qn);
-            if (nq <= kQCap) {
-                // Complete the queued pairs: one pair per wave, lanes over k.
-                for (int q = w; q < nq; q += NW) {
-                    const uint32_t e = (uint32_t)uniform_i((int)qbuf[q]);
-                    const int te = (int)(e >> 24);
-                    const int4 d0 = desc0[te];
-                    const int2 d1 = desc1[te];
-                    const int hi = uniform_i(d0.x) + (int)((e >> 12) & 0xFFFu);
-                    const int hj = uniform_i(d0.z) + (int)(e & 0xFFFu);
-                    const uint32_t cnt = P::complete(c, lh, hi, hj, uniform_i(d1.x), uniform_i(d1.y));
-                    if (lane == 0 && cnt) atomicAdd(&sres[te], (int32_t)cnt);
-                }
-            } else {
-                // Too many candidate pairs: count the work events one by one.
-                for (int te = w; te < nsub; te += NW) {
-                    const int4 d0 = desc0[te];
-                    const int2 d1 = desc1[te];
-                    const int o0 = uniform_i(d0.x), n0 = uniform_i(d0.y), o1 = uniform_i(d0.z), n1 = uniform_i(d0.w);
-                    const int o2 = uniform_i(d1.x), n2 = uniform_i(d1.y);
-                    if (n2 == 0) continue;  // decided in the descriptor pass
-                    int R, T;
-                    lane_layout(n0, n1, R, T);
-                    R = uniform_i(R);
-                    T = uniform_i(T);
-                    const uint32_t cnt = T > 0 ? wave_event_fast<P>(c, lh, o0, n0, o1, n1, o2, n2, R, T, px, py)
-                                               : wave_event_pruned<P>(c, lh, o0, n0, o1, n1, o2, n2, px, py);
-                    if (lane == 0) sres[te] = (int32_t)cnt;
-                }
+            for (int te = w; te < nsub; te += NW) {
+                const int4 d0 = desc0[te], d1 = desc1[te];
+                const int o0 = uniform_i(d0.x), n0 = uniform_i(d0.y), o1 = uniform_i(d0.z), n1 = uniform_i(d0.w);
+                const int o2 = uniform_i(d1.x), n2 = uniform_i(d1.y), R = uniform_i(d1.z), T = uniform_i(d1.w);
+                if (R == 0) continue;  // decided in the descriptor pass
+                const uint32_t cnt = T > 0 ? wave_event_fast<P>(c, lh, o0, n0, o1, n1, o2, n2, R, T, px, py)
+                                           : wave_event_pruned<P>(c, lh, o0, n0, o1, n1, o2, n2, px, py);
+                if (lane_id() == 0) sres[te] = (int32_t)cnt;
             }
             __syncthreads();
             // Results of the sub-block, one lane per event (coalesced).
