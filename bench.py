@@ -3,8 +3,9 @@
 
 One step = one trig_select call over the whole resident batch (validation,
 triplet counting, accept flags and the ordered accepted-id list) in the
-production form (workgroups staging event blocks in LDS, with exact pair
-pruning).  The plain one-wave-per-event brute-force form is timed beside it on
+production form: the batched form (workgroups staging event blocks in LDS,
+exact pair pruning) with the launch shape the library's autotuner picks on
+this batch during the warm-up.  The plain one-wave-per-event brute-force form is timed beside it on
 the same input, and both must produce identical counts.  A serving leg then
 streams timeslices cut from the same events through the serving runtime at a
 fixed offered load and reports p50/p99 slice latency.  Inputs are generated on the host
@@ -58,14 +59,17 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="medium_1m", choices=sorted(WORKLOAD_TEXT))
     ap.add_argument("--test", default="msd", choices=["msd", "msd_fit", "window"])
-    ap.add_argument("--form", default="pruned")
-    ap.add_argument("--compare", default="plain,pruned,persistent",
+    ap.add_argument("--form", default="auto",
+                    help="form of the timed step (auto: trig_autotune picks the shape in the warm-up)")
+    ap.add_argument("--compare", default="plain,pruned,persistent_pruned,binned",
                     help="other forms timed on the same input (comma separated)")
     ap.add_argument("--compare-steps", type=int, default=5, help="timed steps of each compared form")
     ap.add_argument("--cpu-seconds", type=float, default=12.0,
                     help="target wall time of the CPU-oracle baseline sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-form", action="store_true", help="time only --form (profiling runs)")
+    ap.add_argument("--shape", default="", metavar="HB,NW,EB",
+                    help="explicit block_hits,block_waves,block_events for --form (profiling runs)")
     ap.add_argument("--serve-slices", type=int, default=100,
                     help="timeslices of the serving leg (0 = skip it)")
     ap.add_argument("--serve-load", type=float, default=1e7, help="offered load of the serving leg, events/s")
@@ -108,14 +112,17 @@ def load_traffic(kernel: str, workload: str, form: str):
     return float(rec["bytes_per_launch"])
 
 
-def time_form(torch, trig, hip_events, dev_in, n_events, form, test, steps, warmup, compact=True):
+def time_form(torch, trig, hip_events, dev_in, n_events, form, test, steps, warmup, compact=True, shape=None):
     off, x, y = dev_in
     stream = torch.cuda.current_stream().cuda_stream
     counts = torch.empty(n_events, dtype=torch.int32, device="cuda")
     accept = torch.empty(n_events, dtype=torch.uint8, device="cuda")
     ids = torch.empty(n_events, dtype=torch.int32, device="cuda")
     n_acc = torch.zeros(1, dtype=torch.int32, device="cuda")
-    p = trig.make_params(test=test, flags=trig.FORMS[form] | (trig.TRIG_OUT_COMPACT if compact else 0))
+    kw = {}
+    if shape:
+        kw = dict(zip(("block_hits", "block_waves", "block_events"), shape))
+    p = trig.make_params(test=test, flags=trig.FORMS[form] | (trig.TRIG_OUT_COMPACT if compact else 0), **kw)
     p.out_accepted_ids = ids.data_ptr()
     p.out_n_accepted = n_acc.data_ptr()
     ws_bytes = trig.trig_workspace_bytes(n_events, p)
@@ -131,6 +138,17 @@ def time_form(torch, trig, hip_events, dev_in, n_events, form, test, steps, warm
         if rc:
             raise trig.TrigError(rc, trig.trig_last_error_detail())
 
+    tuned = None
+    if p.flags & trig.TRIG_EXEC_AUTOTUNE:
+        # the library's autotuner picks the launch shape on this batch
+        # (untimed, part of the warm-up)
+        rc, info = trig.trig_autotune(ev, hits, p, counts.data_ptr(), accept.data_ptr(), 3, stream)
+        if rc:
+            raise trig.TrigError(rc, trig.trig_last_error_detail())
+        tuned = {"n_candidates": info.n_candidates, "mult_class": info.mult_class,
+                 "form": "binned" if info.binned else "batched", "block_hits": info.block_hits,
+                 "block_waves": info.block_waves, "block_events": info.block_events,
+                 "persistent": bool(info.persistent), "ms_best": info.ms_best, "ms_rule": info.ms_rule}
     for _ in range(warmup):
         call()
     torch.cuda.synchronize()
@@ -153,6 +171,7 @@ def time_form(torch, trig, hip_events, dev_in, n_events, form, test, steps, warm
         "accept": accept,
         "ids": ids[: int(n_acc.item())],
         "n_accepted": int(n_acc.item()),
+        "autotuned": tuned,
     }
 
 
@@ -258,7 +277,9 @@ def main():
     torch.cuda.synchronize()
 
     log(f"[bench] timing form={args.form} steps={args.steps} warmup={args.warmup}")
-    main_r = time_form(torch, trig, hip_events, dev_in, n_ev, args.form, args.test, args.steps, args.warmup)
+    shape = tuple(int(v) for v in args.shape.split(",")) if args.shape else None
+    main_r = time_form(torch, trig, hip_events, dev_in, n_ev, args.form, args.test, args.steps, args.warmup,
+                       shape=shape)
     ms_per_step = 1e3 * main_r["elapsed_s"] / args.steps
     value = n_ev * args.steps / main_r["elapsed_s"]
     log(f"[bench] {args.form}: {ms_per_step:.3f} ms/step, {value:.4g} events/s, "
@@ -268,8 +289,16 @@ def main():
     # 8 B per hit, 4 B count per event (plain kernel: +1 B flag)
     kern_bytes = 12 * n_ev + 8 * hits + 4 * n_ev
     kern_s = main_r["kernel_ms_mean"] / 1e3
-    dominant = ("k_block" if "pruned" in args.form else
-                "k_persistent" if "persistent" in args.form else "k_plain")
+    tuned = main_r["autotuned"]
+    if tuned:
+        dominant = "k_binned" if tuned["form"] == "binned" else (
+            "k_block_pipe" if tuned["persistent"] else "k_block")
+    elif "binned" in args.form:
+        dominant = "k_binned"
+    elif "pruned" in args.form:
+        dominant = "k_block_pipe" if "persistent" in args.form else "k_block"
+    else:
+        dominant = "k_persistent" if "persistent" in args.form else "k_plain"
     traffic = load_traffic(dominant, args.workload, args.form)
     roofline = {"kernel": dominant, "bound": "hbm", "achieved": kern_bytes / kern_s / 1e9,
                 "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -335,7 +364,9 @@ def main():
         "dtype": "f32",
         "data": "synthetic (seeded generator; stands in for the paper's simulated CBM events)",
         "config": {"workload": f"{args.workload}: {WORKLOAD_TEXT[args.workload]}", "n_events": n_ev,
-                   "n_hits": hits, "test": args.test, "form": args.form, "seed": 0},
+                   "n_hits": hits, "test": args.test, "form": args.form, "seed": 0,
+                   "shape": list(shape) if shape else None},
+        "autotuned": tuned,
         "roofline": roofline,
         "cpu_baseline": cpu,
         "triplet_tests_per_s_effective": triplets * args.steps / main_r["elapsed_s"],

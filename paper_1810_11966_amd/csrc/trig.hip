@@ -50,7 +50,7 @@ constexpr int kCompactItems = 4;    // events per thread in compaction
 constexpr int kPersistWaves = 4;    // waves per workgroup, persistent form
 constexpr int kPersistBatch = 4;    // work units taken per atomic
 constexpr int kDefaultTileUnits = 8;  // pair tiles (of 64 pairs) per work unit
-constexpr int kBlockResident = 8;      // persistent batched workgroups per CU
+constexpr int kClaimsPerGroup = 8;    // pipelined batched form: block claims per workgroup
 
 template <class T>
 struct Chunk;
@@ -614,24 +614,49 @@ __global__ void k_zero_u32(unsigned* p) { *p = 0u; }
 struct BlockShape {
     int hb, nw, eb;
 };
+// Events per block that fill `fill` of an hb-hit block at the batch's mean
+// event size.
+int events_for_fill(double fill, int hb, int nw, int n_events, int n_hits) {
+    const double mean = std::max(n_events > 0 ? (double)n_hits / n_events : 1.0, 1.0);
+    int eb = (int)std::max(1.0, std::min((double)kMaxEB, std::floor(fill * hb / mean)));
+    if (eb >= nw) eb -= eb % nw;  // whole rounds of events over the waves
+    return eb;
+}
+
 BlockShape choose_block_shape(const trig_params* p, int n_events, int n_hits) {
     const double mean = std::max(n_events > 0 ? (double)n_hits / n_events : 1.0, 1.0);
     int hb = p->block_hits;
     if (hb <= 0) hb = 0.6 * 1024 / mean >= 8.0 ? 1024 : 0.6 * 2048 / mean >= 8.0 ? 2048 : 4096;
     int nw = p->block_waves;
-    if (nw <= 0) nw = hb / 1024;
+    if (nw <= 0) nw = std::min(4, hb / 512);
     int eb = p->block_events;
-    if (eb <= 0) eb = (int)std::max(1.0, std::min((double)kMaxEB, std::floor(0.6 * hb / mean)));
+    if (eb <= 0) eb = events_for_fill(0.6, hb, nw, n_events, n_hits);
     return {hb, nw, eb};
 }
 
 using BlockKernel = void (*)(const int32_t*, int, const float*, const float*, Consts, int, int, unsigned*, int,
                              int32_t*, uint8_t*, uint32_t*);
 
+// Workgroups of `kern` that fit on one CU at once (cached per kernel).
+int resident_per_cu(BlockKernel kern, int threads) {
+    static std::mutex mu;
+    static std::map<BlockKernel, int> cache;
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(kern);
+    if (it != cache.end()) return it->second;
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), threads, 0) !=
+            hipSuccess ||
+        per_cu < 1)
+        per_cu = 1;
+    cache[kern] = per_cu;
+    return per_cu;
+}
+
 template <class P>
-BlockKernel block_kernel(int hb, int nw) {
+BlockKernel block_kernel(int hb, int nw, bool pipelined) {
 #define TRIG_BLOCK_CASE(H, W) \
-    if (hb == H && nw == W) return k_block<P, H, W>;
+    if (hb == H && nw == W) return pipelined ? k_block_pipe<P, H, W> : k_block<P, H, W>;
     TRIG_BLOCK_CASE(1024, 1) TRIG_BLOCK_CASE(1024, 2) TRIG_BLOCK_CASE(1024, 4)
     TRIG_BLOCK_CASE(2048, 1) TRIG_BLOCK_CASE(2048, 2) TRIG_BLOCK_CASE(2048, 4)
     TRIG_BLOCK_CASE(4096, 1) TRIG_BLOCK_CASE(4096, 2) TRIG_BLOCK_CASE(4096, 4)
@@ -644,21 +669,27 @@ int launch_block(const trig_events_csr* ev, const trig_hits* h, const trig_param
                  const Layout& L, char* ws, int32_t* counts, uint8_t* accept, hipStream_t s) {
     const int n = ev->n_events;
     const BlockShape bs = choose_block_shape(p, n, h->n_hits);
-    const BlockKernel kern = block_kernel<P>(bs.hb, bs.nw);
+    const int vec = ((reinterpret_cast<uintptr_t>(h->x) | reinterpret_cast<uintptr_t>(h->y)) & 15) == 0;
+    // Block stealing uses the pipelined kernel, which needs 16-byte aligned
+    // hit arrays; otherwise one workgroup per block.
+    const bool pipelined = (p->flags & TRIG_EXEC_PERSISTENT) && vec;
+    const BlockKernel kern = block_kernel<P>(bs.hb, bs.nw, pipelined);
     if (!kern) return fail(TRIG_EINVAL, "block_hits must be 1024, 2048 or 4096 and block_waves 1, 2 or 4");
     const int n_blocks = (int)cdiv(n, bs.eb);
     unsigned* counter = nullptr;
     unsigned grid = (unsigned)n_blocks;
-    if (p->flags & TRIG_EXEC_PERSISTENT) {
+    if (pipelined) {
         counter = reinterpret_cast<unsigned*>(ws + L.counter_off);
         hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(1), 0, s, counter);
         if (int r = check_launch("k_zero_u32")) return r;
-        grid = (unsigned)std::min<int64_t>(n_blocks, (int64_t)device_cus() * kBlockResident * (4 / bs.nw));
+        grid = (unsigned)std::min<int64_t>(n_blocks, (int64_t)device_cus() * resident_per_cu(kern, bs.nw * kWave));
     }
-    const int vec = ((reinterpret_cast<uintptr_t>(h->x) | reinterpret_cast<uintptr_t>(h->y)) & 15) == 0;
+    // Pipelined kernel: blocks per claim, about kClaimsPerGroup claims per
+    // workgroup (one atomic on one counter per claim).
+    const int aux = pipelined ? (int)std::max<int64_t>(1, n_blocks / ((int64_t)grid * kClaimsPerGroup)) : vec;
     if (mark_start(s)) return fail(TRIG_EHIP, "hipEventRecord(start)");
     hipLaunchKernelGGL(kern, dim3(grid), dim3(bs.nw * kWave), 0, s, ev->layer_offsets, n, h->x, h->y, c, bs.eb,
-                       n_blocks, counter, vec, counts, accept, p->out_status);
+                       n_blocks, counter, aux, counts, accept, p->out_status);
     if (int r = check_launch("k_block")) return r;
     if (mark_stop(s)) return fail(TRIG_EHIP, "hipEventRecord(stop)");
     return TRIG_OK;
@@ -714,10 +745,6 @@ struct TunedShape {
     bool binned;  // the binned form (hb, nw, fill unused)
 };
 
-int events_for_fill(double fill, int hb, int n_events, int n_hits) {
-    const double mean = std::max(n_events > 0 ? (double)n_hits / n_events : 1.0, 1.0);
-    return (int)std::max(1.0, std::min((double)kMaxEB, std::floor(fill * hb / mean)));
-}
 
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int, int>, TunedShape> g_tuned;  // (device, test, class)
@@ -749,7 +776,7 @@ trig_params resolve_autotune(const trig_params* p, int n_events, int n_hits) {
         if (t.binned) return q;
         if (!q.block_hits) q.block_hits = t.hb;
         if (!q.block_waves) q.block_waves = t.nw;
-        if (!q.block_events) q.block_events = events_for_fill(t.fill, q.block_hits, n_events, n_hits);
+        if (!q.block_events) q.block_events = events_for_fill(t.fill, q.block_hits, q.block_waves, n_events, n_hits);
         if (t.persistent) q.flags |= TRIG_EXEC_PERSISTENT;
     }
     return q;
@@ -874,7 +901,7 @@ int trig_autotune(const trig_events_csr* ev, const trig_hits* hits, const trig_p
             q.flags = (t.binned ? TRIG_EXEC_BINNED : TRIG_EXEC_PRUNED) | (t.persistent ? TRIG_EXEC_PERSISTENT : 0u);
             q.block_hits = t.hb;
             q.block_waves = t.nw;
-            q.block_events = events_for_fill(t.fill, t.hb, n, n_hits);
+            q.block_events = events_for_fill(t.fill, t.hb, t.nw, n, n_hits);
             q.out_accepted_ids = nullptr;
             q.out_n_accepted = nullptr;
             double total = 0.0;

@@ -357,138 +357,329 @@ __device__ __forceinline__ void stage_hits(const float* __restrict__ x, const fl
     }
 }
 
+// LDS of the block kernels.
+template <int HB, int NW>
+struct BlockLds {
+    // HB hits plus up to 3 before the first and 3 after the last (4-aligned copy)
+    float stage_x[HB + 8];
+    float stage_y[HB + 8];
+    float pbuf_x[NW][kPBuf];
+    float pbuf_y[NW][kPBuf];
+    int4 desc0[kMaxEB], desc1[kMaxEB];
+    int32_t soff[3 * kMaxEB + 1];
+    int32_t sres[kMaxEB];
+    int s_block, s_next, s_bad;
+};
+
+// CSR checks of the block's events (offsets in L.soff); malformed events get
+// -1 here.  Returns (workgroup-uniform) whether any event was malformed.
+template <int HB, int NW>
+__device__ bool block_validate(BlockLds<HB, NW>& L, const Consts& c, int e0, int ne, int32_t* counts,
+                               uint8_t* accept, uint32_t* status) {
+    constexpr int NT = NW * kWave;
+    if (threadIdx.x == 0) L.s_bad = 0;
+    __syncthreads();
+    for (int t = threadIdx.x; t < ne; t += NT) {
+        const int a0 = L.soff[3 * t], a1 = L.soff[3 * t + 1], a2 = L.soff[3 * t + 2], a3 = L.soff[3 * t + 3];
+        if (!(0 <= a0 && a0 <= a1 && a1 <= a2 && a2 <= a3 && a3 <= c.n_hits)) {
+            counts[e0 + t] = -1;
+            accept[e0 + t] = 0;
+            if (status) atomicOr(status, TRIG_STATUS_MALFORMED);
+            atomicOr(&L.s_bad, 1);
+        }
+    }
+    __syncthreads();
+    return uniform_i(L.s_bad) != 0;
+}
+
+// Descriptors of events [cur, cur + nsub) of a staged sub-block (local hit
+// index = global index - a0), one lane per event; events decided without
+// pairs get their result here (0 for an empty layer, -2 for a count beyond
+// int32).  Ends with a barrier.
+template <int HB, int NW>
+__device__ void block_descriptors(BlockLds<HB, NW>& L, int cur, int nsub, int a0) {
+    constexpr int NT = NW * kWave;
+    for (int te = threadIdx.x; te < nsub; te += NT) {
+        const int ev = cur + te;
+        const int b0 = L.soff[3 * ev], b1 = L.soff[3 * ev + 1], b2 = L.soff[3 * ev + 2], b3 = L.soff[3 * ev + 3];
+        const int n0 = b1 - b0, n1 = b2 - b1, n2 = b3 - b2;
+        const int64_t n01 = (int64_t)n0 * n1;
+        int R = 0, T = 0, res = 0, work = 0;
+        if (n2 > 0 && (n01 > (int64_t)INT32_MAX || n01 * n2 > (int64_t)INT32_MAX)) {
+            res = -2;
+        } else if (n0 > 0 && n1 > 0 && n2 > 0) {
+            work = 1;
+            lane_layout(n0, n1, R, T);
+        }
+        L.desc0[te] = make_int4(b0 - a0, n0, b1 - a0, n1);
+        L.desc1[te] = make_int4(b2 - a0, n2, work ? R : 0, T);
+        L.sres[te] = res;
+    }
+    __syncthreads();
+}
+
+// Counts of the described events from the staged hits (events round-robin
+// over the waves, a static assignment), then the results of events
+// [e_first, e_first + nsub) with one lane per event.  Ends with a barrier.
+template <class P, int HB, int NW>
+__device__ void block_count(BlockLds<HB, NW>& L, const Consts& c, int e_first, int nsub, int32_t* counts,
+                            uint8_t* accept, uint32_t* status) {
+    constexpr int NT = NW * kWave;
+    const int w = uniform_i(threadIdx.x / kWave);
+    float* px = L.pbuf_x[w];
+    float* py = L.pbuf_y[w];
+    const LdsHits lh{L.stage_x, L.stage_y};
+    for (int te = w; te < nsub; te += NW) {
+        const int4 d0 = L.desc0[te], d1 = L.desc1[te];
+        const int o0 = uniform_i(d0.x), n0 = uniform_i(d0.y), o1 = uniform_i(d0.z), n1 = uniform_i(d0.w);
+        const int o2 = uniform_i(d1.x), n2 = uniform_i(d1.y), R = uniform_i(d1.z), T = uniform_i(d1.w);
+        if (R == 0) continue;  // decided in the descriptor pass
+        const uint32_t cnt = T > 0 ? wave_event_fast<P>(c, lh, o0, n0, o1, n1, o2, n2, R, T, px, py)
+                                   : wave_event_pruned<P>(c, lh, o0, n0, o1, n1, o2, n2, px, py);
+        if (lane_id() == 0) L.sres[te] = (int32_t)cnt;
+    }
+    __syncthreads();
+    for (int te = threadIdx.x; te < nsub; te += NT) {
+        const int32_t r = L.sres[te];
+        counts[e_first + te] = r;
+        accept[e_first + te] = (uint8_t)(r >= 0 && r >= c.min_triplets);
+        if (r < 0 && status) atomicOr(status, TRIG_STATUS_OVERFLOW);
+    }
+    __syncthreads();
+}
+
+// Whole block [e0, e0 + ne) with its offsets in L.soff: malformed blocks
+// event by event from HBM; otherwise sub-blocks of consecutive events whose
+// hits fit in LDS are staged and counted (an event larger than LDS is read
+// from HBM by wave 0).  Ends with a barrier.
+template <class P, int HB, int NW>
+__device__ void block_general(BlockLds<HB, NW>& L, const Consts& c, const float* __restrict__ x,
+                              const float* __restrict__ y, int e0, int ne, bool bad, bool vec, int32_t* counts,
+                              uint8_t* accept, uint32_t* status) {
+    constexpr int NT = NW * kWave;
+    const int w = uniform_i(threadIdx.x / kWave);
+    float* px = L.pbuf_x[w];
+    float* py = L.pbuf_y[w];
+    const GlobalHits ghits{x, y};
+    if (bad) {
+        for (int t = w; t < ne; t += NW) {
+            const int a0 = L.soff[3 * t], a1 = L.soff[3 * t + 1], a2 = L.soff[3 * t + 2], a3 = L.soff[3 * t + 3];
+            if (0 <= a0 && a0 <= a1 && a1 <= a2 && a2 <= a3 && a3 <= c.n_hits)
+                wave_event<P>(c, ghits, 0, a0, a1, a2, a3, e0 + t, counts, accept, status, px, py);
+        }
+        __syncthreads();
+        return;
+    }
+    // Well-formed block: offsets are non-decreasing over it.
+    int cur = 0;
+    while (cur < ne) {
+        const int base = L.soff[3 * cur];
+        const int t = (int)threadIdx.x;
+        // Events from cur on whose hits still fit: a prefix, counted NT at a time.
+        int nfit = 0;
+        for (int t0 = 0;; t0 += NT) {
+            const int tt = t0 + t;
+            const bool fits = (cur + tt < ne) && (L.soff[3 * (cur + tt + 1)] - base <= HB);
+            const int c1 = uniform_i(__syncthreads_count(fits));
+            nfit += c1;
+            if (c1 < NT) break;
+        }
+        if (nfit == 0) {
+            // One event larger than LDS: wave 0 reads it from HBM.
+            if (w == 0)
+                wave_event<P>(c, ghits, 0, L.soff[3 * cur], L.soff[3 * cur + 1], L.soff[3 * cur + 2],
+                              L.soff[3 * cur + 3], e0 + cur, counts, accept, status, px, py);
+            __syncthreads();
+            cur += 1;
+            continue;
+        }
+        const int end = cur + nfit;
+        const int nh = L.soff[3 * end] - base;
+        stage_hits<HB, NT>(x, y, base, nh, c.n_hits, vec, L.stage_x, L.stage_y);
+        block_descriptors(L, cur, nfit, base & ~3);
+        block_count<P>(L, c, e0 + cur, nfit, counts, accept, status);
+        cur = end;
+    }
+}
+
+// The block kernel (one block of eb consecutive events per workgroup).
+// `vec`: x and y are 16-byte aligned (the pipelined kernel's same argument
+// slot carries its claim chunk instead).
 template <class P, int HB, int NW>
 __global__ __launch_bounds__(NW * kWave) void k_block(const int32_t* __restrict__ off, int n_events,
                                                          const float* __restrict__ x,
                                                          const float* __restrict__ y, Consts c, int eb,
-                                                         int n_blocks, unsigned* block_counter, int vec,
+                                                         int n_blocks, unsigned* /*unused*/, int vec,
                                                          int32_t* __restrict__ counts,
                                                          uint8_t* __restrict__ accept, uint32_t* status) {
-    // HB hits plus up to 3 before the first and 3 after the last (4-aligned copy)
-    __shared__ __align__(16) float stage_x[HB + 8];
-    __shared__ __align__(16) float stage_y[HB + 8];
+    __shared__ __align__(16) BlockLds<HB, NW> L;
     constexpr int NT = NW * kWave;
-    __shared__ __align__(16) float pbuf_x[NW][kPBuf];
-    __shared__ __align__(16) float pbuf_y[NW][kPBuf];
-    __shared__ int32_t soff[3 * kMaxEB + 1];
-    __shared__ int4 desc0[kMaxEB], desc1[kMaxEB];
-    __shared__ int32_t sres[kMaxEB];
-    __shared__ int s_block, s_bad;
-    const int w = uniform_i(threadIdx.x / kWave);
-    float* px = pbuf_x[w];
-    float* py = pbuf_y[w];
-    const GlobalHits ghits{x, y};
-    int iter = 0;
-    for (;; ++iter) {
-        if (threadIdx.x == 0) {
-            if (block_counter)
-                s_block = (int)atomicAdd(block_counter, 1u);
-            else
-                s_block = iter == 0 ? (int)blockIdx.x : n_blocks;
-            s_bad = 0;
+    const int b = blockIdx.x;
+    if (b >= n_blocks) return;
+    const int e0 = b * eb;
+    const int ne = min(eb, n_events - e0);
+    for (int t = threadIdx.x; t <= 3 * ne; t += NT) L.soff[t] = off[3 * (int64_t)e0 + t];
+    __syncthreads();
+    const bool bad = block_validate(L, c, e0, ne, counts, accept, status);
+    block_general<P>(L, c, x, y, e0, ne, bad, vec != 0, counts, accept, status);
+}
+
+// Hits of one block held in registers between their load and their LDS
+// store: the float4 groups of [a0, a0 + 4 nq) (a0 = base rounded down to a
+// multiple of 4) that lie entirely below n_hits, loaded unconditionally
+// (clamped), so that every load is in flight at once.  The rest (at most
+// three hits below n_hits) is copied by thread 0 at the store.  The groups
+// are named members (G<k> holds group k of this thread), not an array, so
+// that they stay in registers across the pipeline loop.
+typedef float f32x4 __attribute__((ext_vector_type(4)));  // a native vector (float4 copies are memcpys)
+
+template <int K, int NT>
+struct HitGroups {
+    f32x4 vx, vy;
+    HitGroups<K - 1, NT> rest;
+    __device__ __forceinline__ void load(const float* __restrict__ x, const float* __restrict__ y, int a0,
+                                         int nq_full) {
+        const int q = min((int)threadIdx.x + (K - 1) * NT, nq_full - 1);
+        vx = *reinterpret_cast<const f32x4*>(x + a0 + 4 * q);
+        vy = *reinterpret_cast<const f32x4*>(y + a0 + 4 * q);
+        rest.load(x, y, a0, nq_full);
+    }
+    __device__ __forceinline__ void store(int nq_full, float* xs, float* ys) const {
+        const int q = (int)threadIdx.x + (K - 1) * NT;
+        if (q < nq_full) {
+            reinterpret_cast<f32x4*>(xs)[q] = vx;
+            reinterpret_cast<f32x4*>(ys)[q] = vy;
         }
-        __syncthreads();
-        const int b = uniform_i(s_block);
-        if (b >= n_blocks) break;
+        rest.store(nq_full, xs, ys);
+    }
+};
+template <int NT>
+struct HitGroups<0, NT> {
+    __device__ __forceinline__ void load(const float*, const float*, int, int) {}
+    __device__ __forceinline__ void store(int, float*, float*) const {}
+};
+
+template <int HB, int NT>
+struct HitPrefetch {
+    static constexpr int Q = (HB + 6) / 4 / NT + 1;  // float4 groups per thread, upper bound
+    HitGroups<Q, NT> g;
+    int nq_full;
+    __device__ __forceinline__ void issue(const float* __restrict__ x, const float* __restrict__ y, int base,
+                                          int nh, int n_hits) {
+        const int a0 = base & ~3;
+        const int nq = (base + nh - a0 + 3) >> 2;
+        nq_full = min(nq, (n_hits - a0) >> 2);
+        if (nq_full > 0) g.load(x, y, a0, nq_full);
+    }
+    __device__ __forceinline__ void store(const float* __restrict__ x, const float* __restrict__ y, int base,
+                                          int nh, float* xs, float* ys) const {
+        const int a0 = base & ~3;
+        g.store(nq_full, xs, ys);
+        if (threadIdx.x == 0)
+            for (int h = a0 + 4 * max(nq_full, 0); h < base + nh; ++h) {
+                xs[h - a0] = x[h];
+                ys[h - a0] = y[h];
+            }
+    }
+};
+
+// Persistent block kernel with a software pipeline: workgroups take chunks
+// of `chunk` consecutive blocks from *block_counter (zero at launch; one
+// atomic per chunk, each claimed one chunk ahead), and while a block is
+// counted from LDS the next block's offsets have arrived and its hits are in
+// flight into registers.  Blocks that are malformed or do not fit in LDS take
+// the general path.  Needs x and y 16-byte aligned.
+template <class P, int HB, int NW>
+__global__ __launch_bounds__(NW * kWave) void k_block_pipe(const int32_t* __restrict__ off, int n_events,
+                                                              const float* __restrict__ x,
+                                                              const float* __restrict__ y, Consts c, int eb,
+                                                              int n_blocks, unsigned* block_counter, int chunk,
+                                                              int32_t* __restrict__ counts,
+                                                              uint8_t* __restrict__ accept, uint32_t* status) {
+    __shared__ __align__(16) BlockLds<HB, NW> L;
+    constexpr int NT = NW * kWave;
+    const int t = (int)threadIdx.x;
+    HitPrefetch<HB, NT> pf;
+    // Prologue: claim two chunks, load the first block's offsets, prefetch its hits.
+    if (t == 0) {
+        L.s_block = (int)atomicAdd(block_counter, 1u);
+        L.s_next = (int)atomicAdd(block_counter, 1u);
+    }
+    __syncthreads();
+    // Block indices as int64 products: chunk * claims may pass int32 range.
+    auto chunk_start = [&](int claimed) {
+        return (int)min((int64_t)claimed * chunk, (int64_t)n_blocks);
+    };
+    int b = chunk_start(uniform_i(L.s_block));
+    int cur_first = b;
+    int cur_end = min(b + chunk, n_blocks);
+    int next_first = chunk_start(uniform_i(L.s_next));
+    if (b >= n_blocks) return;  // workgroup-uniform, before any further barrier
+    {
+        const int e0 = b * eb, ne = min(eb, n_events - e0);
+        for (int q = t; q <= 3 * ne; q += NT) L.soff[q] = off[3 * (int64_t)e0 + q];
+    }
+    __syncthreads();
+    int pf_ok;  // the hits of block b are in pf
+    {
+        const int ne = min(eb, n_events - b * eb);
+        const int base = L.soff[0], end = L.soff[3 * ne];
+        pf_ok = (0 <= base && base <= end && end <= c.n_hits && end - base <= HB);
+        if (pf_ok) pf.issue(x, y, base, end - base, c.n_hits);
+    }
+    for (;;) {
         const int e0 = b * eb;
         const int ne = min(eb, n_events - e0);
-        for (int t = threadIdx.x; t <= 3 * ne; t += NT) soff[t] = off[3 * (int64_t)e0 + t];
+        // At a chunk's first block, claim the chunk after the next one.
+        const bool first_of_chunk = b == cur_first;
+        unsigned claim = 0;
+        if (first_of_chunk && t == 0) claim = atomicAdd(block_counter, 1u);
+        const int bn = b + 1 < cur_end ? b + 1 : next_first;
+        // Offsets of the next block: issued now, stored after this block's descriptors.
+        constexpr int OQ = (3 * kMaxEB + 1 + NT - 1) / NT;
+        int on[OQ];
+        const bool has_next = bn < n_blocks;
+        const int e0n = bn * eb;
+        const int nen = has_next ? min(eb, n_events - e0n) : 0;
+#pragma unroll
+        for (int k = 0; k < OQ; ++k) {
+            const int q = t + k * NT;
+            on[k] = (has_next && q <= 3 * nen) ? off[3 * (int64_t)e0n + q] : 0;
+        }
+        const bool bad = block_validate(L, c, e0, ne, counts, accept, status);
+        const bool regular = !bad && pf_ok;
+        if (regular) {
+            const int base = L.soff[0];
+            const int nh = L.soff[3 * ne] - base;
+            pf.store(x, y, base, nh, L.stage_x, L.stage_y);
+            block_descriptors(L, 0, ne, base & ~3);
+        } else {
+            block_general<P>(L, c, x, y, e0, ne, bad, true, counts, accept, status);
+        }
+        // L.soff is free: the next block's offsets, then its hits in flight.
+#pragma unroll
+        for (int k = 0; k < OQ; ++k) {
+            const int q = t + k * NT;
+            if (has_next && q <= 3 * nen) L.soff[q] = on[k];
+        }
+        if (first_of_chunk && t == 0) L.s_next = (int)claim;
         __syncthreads();
-        // Per-event CSR checks; malformed events get -1 here.
-        for (int t = threadIdx.x; t < ne; t += NT) {
-            const int a0 = soff[3 * t], a1 = soff[3 * t + 1], a2 = soff[3 * t + 2], a3 = soff[3 * t + 3];
-            if (!(0 <= a0 && a0 <= a1 && a1 <= a2 && a2 <= a3 && a3 <= c.n_hits)) {
-                counts[e0 + t] = -1;
-                accept[e0 + t] = 0;
-                if (status) atomicOr(status, TRIG_STATUS_MALFORMED);
-                atomicOr(&s_bad, 1);
-            }
+        if (has_next) {
+            const int base = L.soff[0], end = L.soff[3 * nen];
+            pf_ok = (0 <= base && base <= end && end <= c.n_hits && end - base <= HB);
+            if (pf_ok) pf.issue(x, y, base, end - base, c.n_hits);
         }
-        __syncthreads();
-        if (uniform_i(s_bad)) {
-            // Irregular block: every well-formed event straight from HBM.
-            for (int t = w; t < ne; t += NW) {
-                const int a0 = soff[3 * t], a1 = soff[3 * t + 1], a2 = soff[3 * t + 2], a3 = soff[3 * t + 3];
-                if (0 <= a0 && a0 <= a1 && a1 <= a2 && a2 <= a3 && a3 <= c.n_hits)
-                    wave_event<P>(c, ghits, 0, a0, a1, a2, a3, e0 + t, counts, accept, status, px, py);
-            }
-            __syncthreads();
-            if (!block_counter) break;
-            continue;
+        const int claimed = uniform_i(L.s_next);  // valid after a first block's barrier above
+        if (regular) block_count<P>(L, c, e0, ne, counts, accept, status);
+        if (!has_next) break;
+        if (b + 1 >= cur_end) {
+            // Move on to the next chunk; the one after it was claimed at
+            // this chunk's first block (or in the prologue).
+            cur_first = next_first;
+            cur_end = min(next_first + chunk, n_blocks);
+            next_first = chunk_start(claimed);
         }
-        // Well-formed block: offsets are non-decreasing over it.  Stage
-        // sub-blocks of consecutive events whose hits fit in LDS.
-        int cur = 0;
-        while (cur < ne) {
-            const int base = soff[3 * cur];
-            const int t = (int)threadIdx.x;
-            // Events from cur on whose hits still fit: a prefix, counted NT at a time.
-            int nfit = 0;
-            for (int t0 = 0;; t0 += NT) {
-                const int tt = t0 + t;
-                const bool fits = (cur + tt < ne) && (soff[3 * (cur + tt + 1)] - base <= HB);
-                const int c1 = uniform_i(__syncthreads_count(fits));
-                nfit += c1;
-                if (c1 < NT) break;
-            }
-            if (nfit == 0) {
-                // One event larger than LDS: wave 0 reads it from HBM.
-                if (w == 0)
-                    wave_event<P>(c, ghits, 0, soff[3 * cur], soff[3 * cur + 1], soff[3 * cur + 2],
-                                  soff[3 * cur + 3], e0 + cur, counts, accept, status, px, py);
-                __syncthreads();
-                cur += 1;
-                continue;
-            }
-            const int end = cur + nfit;
-            const int nh = soff[3 * end] - base;
-            const int nsub = end - cur;
-            stage_hits<HB, NT>(x, y, base, nh, c.n_hits, vec != 0, stage_x, stage_y);
-            // Per-event descriptors, one lane per event: local offsets,
-            // sizes, lane layout; events decided without pairs get their
-            // result here (0 for an empty layer, -2 for a count beyond int32).
-            const int a0 = base & ~3;
-            for (int te = t; te < nsub; te += NT) {
-                const int ev = cur + te;
-                const int b0 = soff[3 * ev], b1 = soff[3 * ev + 1], b2 = soff[3 * ev + 2], b3 = soff[3 * ev + 3];
-                const int n0 = b1 - b0, n1 = b2 - b1, n2 = b3 - b2;
-                const int64_t n01 = (int64_t)n0 * n1;
-                int R = 0, T = 0, res = 0, work = 0;
-                if (n2 > 0 && (n01 > (int64_t)INT32_MAX || n01 * n2 > (int64_t)INT32_MAX)) {
-                    res = -2;
-                } else if (n0 > 0 && n1 > 0 && n2 > 0) {
-                    work = 1;
-                    lane_layout(n0, n1, R, T);
-                }
-                desc0[te] = make_int4(b0 - a0, n0, b1 - a0, n1);
-                desc1[te] = make_int4(b2 - a0, n2, work ? R : 0, T);
-                sres[te] = res;
-            }
-            __syncthreads();
-            // Events round-robin over the waves (a static assignment: no
-            // per-wave claim loop).
-            const LdsHits lh{stage_x, stage_y};
-            for (int te = w; te < nsub; te += NW) {
-                const int4 d0 = desc0[te], d1 = desc1[te];
-                const int o0 = uniform_i(d0.x), n0 = uniform_i(d0.y), o1 = uniform_i(d0.z), n1 = uniform_i(d0.w);
-                const int o2 = uniform_i(d1.x), n2 = uniform_i(d1.y), R = uniform_i(d1.z), T = uniform_i(d1.w);
-                if (R == 0) continue;  // decided in the descriptor pass
-                const uint32_t cnt = T > 0 ? wave_event_fast<P>(c, lh, o0, n0, o1, n1, o2, n2, R, T, px, py)
-                                           : wave_event_pruned<P>(c, lh, o0, n0, o1, n1, o2, n2, px, py);
-                if (lane_id() == 0) sres[te] = (int32_t)cnt;
-            }
-            __syncthreads();
-            // Results of the sub-block, one lane per event (coalesced).
-            for (int te = t; te < nsub; te += NT) {
-                const int32_t r = sres[te];
-                counts[e0 + cur + te] = r;
-                accept[e0 + cur + te] = (uint8_t)(r >= 0 && r >= c.min_triplets);
-                if (r < 0 && status) atomicOr(status, TRIG_STATUS_OVERFLOW);
-            }
-            __syncthreads();
-            cur = end;
-        }
-        if (!block_counter) break;
+        b = bn;
     }
 }
 
