@@ -619,7 +619,7 @@ struct BlockShape {
 int events_for_fill(double fill, int hb, int nw, int n_events, int n_hits) {
     const double mean = std::max(n_events > 0 ? (double)n_hits / n_events : 1.0, 1.0);
     int eb = (int)std::max(1.0, std::min((double)kMaxEB, std::floor(fill * hb / mean)));
-    if (eb >= nw) eb -= eb % nw;  // whole rounds of events over the waves
+    if (nw > 0 && eb >= nw) eb -= eb % nw;  // whole rounds of events over the waves
     return eb;
 }
 
@@ -901,7 +901,7 @@ int trig_autotune(const trig_events_csr* ev, const trig_hits* hits, const trig_p
             q.flags = (t.binned ? TRIG_EXEC_BINNED : TRIG_EXEC_PRUNED) | (t.persistent ? TRIG_EXEC_PERSISTENT : 0u);
             q.block_hits = t.hb;
             q.block_waves = t.nw;
-            q.block_events = events_for_fill(t.fill, t.hb, t.nw, n, n_hits);
+            q.block_events = t.binned ? 0 : events_for_fill(t.fill, t.hb, t.nw, n, n_hits);
             q.out_accepted_ids = nullptr;
             q.out_n_accepted = nullptr;
             double total = 0.0;
