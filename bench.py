@@ -90,7 +90,7 @@ def algorithmic(sets_counts, n_events):
 def kernel_source_hash():
     h = hashlib.sha256()
     for p in ("paper_1810_11966_amd/csrc/trig.hip", "paper_1810_11966_amd/csrc/trig_device.hpp",
-              "paper_1810_11966_amd/csrc/trig_block.hpp"):
+              "paper_1810_11966_amd/csrc/trig_block.hpp", "paper_1810_11966_amd/csrc/trig_binned.hpp"):
         with open(os.path.join(ROOT, p), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
@@ -104,7 +104,7 @@ def load_traffic(kernel: str, workload: str, form: str):
         return None
     try:
         with open(path) as f:
-            rec = json.load(f).get(f"{kernel}/{workload}/{form}")
+            rec = json.load(f).get("records", {}).get(f"{kernel}/{workload}/{form}")
     except (OSError, ValueError):
         return None
     if not rec or rec.get("source_hash") != kernel_source_hash():
@@ -300,10 +300,17 @@ def main():
     else:
         dominant = "k_persistent" if "persistent" in args.form else "k_plain"
     traffic = load_traffic(dominant, args.workload, args.form)
-    roofline = {"kernel": dominant, "bound": "hbm", "achieved": kern_bytes / kern_s / 1e9,
-                "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": kern_bytes / kern_s / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
-                "algorithmic_bytes": kern_bytes}
+    if dominant in ("k_plain", "k_persistent"):
+        # brute force: bound by the fp32 vector ALU (ops per triplet x triplets)
+        ops = OPS_PER_TRIPLET[args.test] * triplets
+        roofline = {"kernel": dominant, "bound": "alu", "achieved": ops / kern_s / 1e12,
+                    "peak": VALU_F32_PEAK_TOPS, "unit": "TFLOP/s", "frac": ops / kern_s / 1e12 / VALU_F32_PEAK_TOPS,
+                    "traffic": traffic, "ops_per_triplet": OPS_PER_TRIPLET[args.test]}
+    else:
+        roofline = {"kernel": dominant, "bound": "hbm", "achieved": kern_bytes / kern_s / 1e9,
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": kern_bytes / kern_s / 1e9 / HBM_PEAK_GBS, "traffic": traffic,
+                    "algorithmic_bytes": kern_bytes}
 
     extra = {}
     plain_info = None
