@@ -240,9 +240,9 @@ typedef struct {
 /* Times the batched form's launch shapes and the binned form on this batch
  * and records the fastest for the batch's multiplicity class (per device and
  * test), for later calls with TRIG_EXEC_AUTOTUNE.  Candidates: the built-in
- * rule's shape; block_hits 1024/2048/4096 x block_waves 1/2/4 x block fill
- * 0.4/0.6/0.8 of the LDS capacity (in mean event sizes) x block stealing
- * off/on; the binned form with and without stealing.  Each is timed `reps`
+ * rule's shape; block_hits 1024/2048/4096 x block_waves 2/4 x block fill
+ * 0.5/0.7/0.85/1.0 of the LDS capacity (in mean event sizes) x block
+ * stealing off/on; the binned form with and without stealing.  Each is timed `reps`
  * times (1..100) after one warm-up; every candidate computes the same
  * counts.  Arguments are those
  * of trig_select, with TRIG_EXEC_AUTOTUNE set in p->flags; block_* fields of

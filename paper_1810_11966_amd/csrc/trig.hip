@@ -51,6 +51,7 @@ constexpr int kPersistWaves = 4;    // waves per workgroup, persistent form
 constexpr int kPersistBatch = 4;    // work units taken per atomic
 constexpr int kDefaultTileUnits = 8;  // pair tiles (of 64 pairs) per work unit
 constexpr int kClaimsPerGroup = 8;    // pipelined batched form: block claims per workgroup
+constexpr double kRuleFill = 0.85;    // built-in rule: hits per block over the LDS capacity
 
 template <class T>
 struct Chunk;
@@ -626,11 +627,11 @@ int events_for_fill(double fill, int hb, int nw, int n_events, int n_hits) {
 BlockShape choose_block_shape(const trig_params* p, int n_events, int n_hits) {
     const double mean = std::max(n_events > 0 ? (double)n_hits / n_events : 1.0, 1.0);
     int hb = p->block_hits;
-    if (hb <= 0) hb = 0.6 * 1024 / mean >= 8.0 ? 1024 : 0.6 * 2048 / mean >= 8.0 ? 2048 : 4096;
+    if (hb <= 0) hb = kRuleFill * 1024 / mean >= 16.0 ? 1024 : kRuleFill * 2048 / mean >= 16.0 ? 2048 : 4096;
     int nw = p->block_waves;
     if (nw <= 0) nw = std::min(4, hb / 512);
     int eb = p->block_events;
-    if (eb <= 0) eb = events_for_fill(0.6, hb, nw, n_events, n_hits);
+    if (eb <= 0) eb = events_for_fill(kRuleFill, hb, nw, n_events, n_hits);
     return {hb, nw, eb};
 }
 
@@ -917,19 +918,19 @@ int trig_autotune(const trig_events_csr* ev, const trig_hits* hits, const trig_p
             ms = (float)(total / reps);
             return TRIG_OK;
         };
-        // The built-in rule's shape first (its fill is 0.6).
+        // The built-in rule's shape first.
         trig_params rp = *p;
         rp.block_hits = rp.block_waves = rp.block_events = 0;
         const BlockShape r0 = choose_block_shape(&rp, n, n_hits);
-        TunedShape best{r0.hb, r0.nw, 0.6, false, false};
+        TunedShape best{r0.hb, r0.nw, kRuleFill, false, false};
         int rc = time_shape(best, res.ms_rule);
         res.ms_best = res.ms_rule;
         if (rc == TRIG_OK) res.n_candidates = 1;
-        const int hbs[3] = {1024, 2048, 4096}, nws[3] = {1, 2, 4};
-        const double fills[3] = {0.4, 0.6, 0.8};
+        const int hbs[3] = {1024, 2048, 4096}, nws[2] = {2, 4};
+        const double fills[4] = {0.5, 0.7, 0.85, 1.0};
         for (int a = 0; a < 3 && rc == TRIG_OK; ++a)
-            for (int b = 0; b < 3 && rc == TRIG_OK; ++b)
-                for (int f = 0; f < 3 && rc == TRIG_OK; ++f)
+            for (int b = 0; b < 2 && rc == TRIG_OK; ++b)
+                for (int f = 0; f < 4 && rc == TRIG_OK; ++f)
                     for (int ps = 0; ps < 2 && rc == TRIG_OK; ++ps) {
                         const TunedShape t{hbs[a], nws[b], fills[f], ps == 1, false};
                         float ms = 0.0f;

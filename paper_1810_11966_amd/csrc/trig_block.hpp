@@ -30,7 +30,7 @@
 
 namespace trig {
 
-constexpr int kPBuf = 128;     // per-wave buffer of layer-0 values (float2)
+constexpr int kPBuf = 64;      // per-wave buffer of layer-0 values (float2)
 constexpr int kMaxEB = 128;    // events per block at most
 
 // Small exact quotients without integer division: for 0 <= a < 4096 and
@@ -215,29 +215,49 @@ __device__ uint32_t wave_event_pruned(const Consts& c, const H& hits, int o0, in
     return cnt;
 }
 
-// Passing triplets of an event with 1 <= n1 <= 64 and n0 <= the buffer fill
-// for its lane layout (one layer-1 pass, one buffer fill): the same
-// computation as wave_event_pruned with its loops taken once.  R and T come
-// from the per-event descriptor (lane_layout).
+// Fast path (one layer-1 pass, one buffer fill; R and T from lane_layout):
+// lane L holds layer-1 hit j of copy g and its partial q; the layer-0
+// partials of the event go to px/py (NaN past n0).
 template <class P, class H>
-__device__ uint32_t wave_event_fast(const Consts& c, const H& hits, int o0, int n0, int o1, int n1, int o2,
-                                    int n2, int R, int T, float* __restrict__ px, float* __restrict__ py) {
+__device__ __forceinline__ void fast_setup(const Consts& c, const H& hits, int o0, int n0, int o1, int n1, int R,
+                                           int T, float* __restrict__ px, float* __restrict__ py, int& g, int& j,
+                                           float2& q) {
     const int lane = (int)lane_id();
-    int g = 0, j = lane;
+    g = 0;
+    j = lane;
     if (R > 1) {
         g = div_small(lane, n1);
         j = lane - g * n1;
     }
     const bool jv = (g < R) && (j < n1);
     if (!jv) g = 0;
-    const float2 q = jv ? P::layer1(c, hits.at(o1 + j)) : nan2();
+    q = jv ? P::layer1(c, hits.at(o1 + j)) : nan2();
     const int npad = T * R;
     for (int t = lane; t < npad; t += kWave) {
         const float2 v = t < n0 ? P::layer0(c, hits.at(o0 + t)) : nan2();
         px[t] = v.x;
         py[t] = v.y;
     }
-    wave_lds_sync();
+}
+
+// Smallest prefilter score of the four pairs (g T + t .. g T + t + 3, j)
+// (fmin drops NaN scores; all NaN gives NaN, which fails every bound).
+template <class P>
+__device__ __forceinline__ float fast_group(const Consts& c, const float4* ppx, const float4* ppy, int t, float2 q) {
+    const float4 vx = ppx[t >> 2], vy = ppy[t >> 2];
+    const float s0 = P::score(c, make_float2(vx.x, vy.x), q);
+    const float s1 = P::score(c, make_float2(vx.y, vy.y), q);
+    const float s2 = P::score(c, make_float2(vx.z, vy.z), q);
+    const float s3 = P::score(c, make_float2(vx.w, vy.w), q);
+    return __builtin_fminf(__builtin_fminf(s0, s1), __builtin_fminf(s2, s3));
+}
+
+// Exact pass over all pairs of the fast-path layout (taken only when some
+// prefilter score reached the bound): the exact pair test per pair, then the
+// surviving pairs completed against layer 2.
+template <class P, class H>
+__device__ uint32_t fast_exact(const Consts& c, const H& hits, int o0, int o1, int o2, int n2, int T, int g, int j,
+                               float2 q, const float* px, const float* py) {
     uint32_t cnt = 0;
     auto finish = [&](uint64_t m, int t) {
         while (m) {
@@ -250,21 +270,34 @@ __device__ uint32_t wave_event_fast(const Consts& c, const H& hits, int o0, int 
     };
     const float4* ppx = reinterpret_cast<const float4*>(px + g * T);
     const float4* ppy = reinterpret_cast<const float4*>(py + g * T);
-    const float bnd = P::bound(c);
     for (int t = 0; t < T; t += 4) {
         const float4 vx = ppx[t >> 2], vy = ppy[t >> 2];
-        const float s0 = P::score(c, make_float2(vx.x, vy.x), q);
-        const float s1 = P::score(c, make_float2(vx.y, vy.y), q);
-        const float s2 = P::score(c, make_float2(vx.z, vy.z), q);
-        const float s3 = P::score(c, make_float2(vx.w, vy.w), q);
-        const float smin = __builtin_fminf(__builtin_fminf(s0, s1), __builtin_fminf(s2, s3));
-        if (wave_any(smin <= bnd)) {
-            finish(P::pair_mask(c, make_float2(vx.x, vy.x), q), t);
-            finish(P::pair_mask(c, make_float2(vx.y, vy.y), q), t + 1);
-            finish(P::pair_mask(c, make_float2(vx.z, vy.z), q), t + 2);
-            finish(P::pair_mask(c, make_float2(vx.w, vy.w), q), t + 3);
-        }
+        finish(P::pair_mask(c, make_float2(vx.x, vy.x), q), t);
+        finish(P::pair_mask(c, make_float2(vx.y, vy.y), q), t + 1);
+        finish(P::pair_mask(c, make_float2(vx.z, vy.z), q), t + 2);
+        finish(P::pair_mask(c, make_float2(vx.w, vy.w), q), t + 3);
     }
+    return cnt;
+}
+
+// Passing triplets of an event with 1 <= n1 <= 64 and n0 <= the buffer fill
+// for its lane layout (one layer-1 pass, one buffer fill): the computation of
+// wave_event_pruned with its loops taken once, and the prefilter minimum
+// taken over the whole event before one vote.  R and T come from the
+// per-event descriptor (lane_layout).
+template <class P, class H>
+__device__ uint32_t wave_event_fast(const Consts& c, const H& hits, int o0, int n0, int o1, int n1, int o2,
+                                    int n2, int R, int T, float* __restrict__ px, float* __restrict__ py) {
+    int g, j;
+    float2 q;
+    fast_setup<P>(c, hits, o0, n0, o1, n1, R, T, px, py, g, j, q);
+    wave_lds_sync();
+    const float4* ppx = reinterpret_cast<const float4*>(px + g * T);
+    const float4* ppy = reinterpret_cast<const float4*>(py + g * T);
+    float m = __builtin_nanf("");
+    for (int t = 0; t < T; t += 4) m = __builtin_fminf(m, fast_group<P>(c, ppx, ppy, t, q));
+    uint32_t cnt = 0;
+    if (wave_any(m <= P::bound(c))) cnt = fast_exact<P>(c, hits, o0, o1, o2, n2, T, g, j, q, px, py);
     wave_lds_sync();
     return cnt;
 }
@@ -365,7 +398,10 @@ struct BlockLds {
     float stage_y[HB + 8];
     float pbuf_x[NW][kPBuf];
     float pbuf_y[NW][kPBuf];
-    int4 desc0[kMaxEB], desc1[kMaxEB];
+    // Event descriptors, 13-bit fields (local hit indices < HB + 8 <= 4104,
+    // layer sizes <= HB <= 4096): da = o0 | n0 << 13 | R << 26 (R <= 16),
+    // db = o1 | n1 << 13 | (T / 4) << 26 (T <= 64), dc = o2 | n2 << 13.
+    uint32_t da[kMaxEB], db[kMaxEB], dc[kMaxEB];
     int32_t soff[3 * kMaxEB + 1];
     int32_t sres[kMaxEB];
     int s_block, s_next, s_bad;
@@ -411,8 +447,9 @@ __device__ void block_descriptors(BlockLds<HB, NW>& L, int cur, int nsub, int a0
             work = 1;
             lane_layout(n0, n1, R, T);
         }
-        L.desc0[te] = make_int4(b0 - a0, n0, b1 - a0, n1);
-        L.desc1[te] = make_int4(b2 - a0, n2, work ? R : 0, T);
+        L.da[te] = (uint32_t)(b0 - a0) | ((uint32_t)n0 << 13) | ((uint32_t)(work ? R : 0) << 26);
+        L.db[te] = (uint32_t)(b1 - a0) | ((uint32_t)n1 << 13) | ((uint32_t)(T >> 2) << 26);
+        L.dc[te] = (uint32_t)(b2 - a0) | ((uint32_t)n2 << 13);
         L.sres[te] = res;
     }
     __syncthreads();
@@ -430,9 +467,13 @@ __device__ void block_count(BlockLds<HB, NW>& L, const Consts& c, int e_first, i
     float* py = L.pbuf_y[w];
     const LdsHits lh{L.stage_x, L.stage_y};
     for (int te = w; te < nsub; te += NW) {
-        const int4 d0 = L.desc0[te], d1 = L.desc1[te];
-        const int o0 = uniform_i(d0.x), n0 = uniform_i(d0.y), o1 = uniform_i(d0.z), n1 = uniform_i(d0.w);
-        const int o2 = uniform_i(d1.x), n2 = uniform_i(d1.y), R = uniform_i(d1.z), T = uniform_i(d1.w);
+        const uint32_t da = (uint32_t)uniform_i((int)L.da[te]);
+        const uint32_t db = (uint32_t)uniform_i((int)L.db[te]);
+        const uint32_t dc = (uint32_t)uniform_i((int)L.dc[te]);
+        constexpr uint32_t kF = (1u << 13) - 1;
+        const int o0 = (int)(da & kF), n0 = (int)((da >> 13) & kF), R = (int)(da >> 26);
+        const int o1 = (int)(db & kF), n1 = (int)((db >> 13) & kF), T = (int)(db >> 26) * 4;
+        const int o2 = (int)(dc & kF), n2 = (int)((dc >> 13) & kF);
         if (R == 0) continue;  // decided in the descriptor pass
         const uint32_t cnt = T > 0 ? wave_event_fast<P>(c, lh, o0, n0, o1, n1, o2, n2, R, T, px, py)
                                    : wave_event_pruned<P>(c, lh, o0, n0, o1, n1, o2, n2, px, py);

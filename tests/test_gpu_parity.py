@@ -349,7 +349,7 @@ def test_autotune_records_and_matches_oracle(gpu, test):
     if test == "msd_fit":
         assert info.n_candidates == 0
     else:
-        assert info.n_candidates == 1 + 3 * 3 * 3 * 2 + 2
+        assert info.n_candidates == 1 + 3 * 2 * 4 * 2 + 2
         assert 0 < info.ms_best <= info.ms_rule
         if info.binned:
             assert info.block_hits == 0
