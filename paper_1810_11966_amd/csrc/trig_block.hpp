@@ -455,6 +455,39 @@ __device__ void block_descriptors(BlockLds<HB, NW>& L, int cur, int nsub, int a0
     __syncthreads();
 }
 
+// CSR checks and descriptors of the block's events in one pass, one lane per
+// event (local hit index = global index - a0): malformed events get -1 and
+// set L.s_bad (zero on entry); the descriptors are used only when no event
+// is malformed and the block is staged whole.  No barrier.
+template <int HB, int NW>
+__device__ __forceinline__ void block_check_describe(BlockLds<HB, NW>& L, const Consts& c, int e0, int ne, int a0,
+                                                     int32_t* counts, uint8_t* accept, uint32_t* status) {
+    constexpr int NT = NW * kWave;
+    for (int te = threadIdx.x; te < ne; te += NT) {
+        const int b0 = L.soff[3 * te], b1 = L.soff[3 * te + 1], b2 = L.soff[3 * te + 2], b3 = L.soff[3 * te + 3];
+        if (!(0 <= b0 && b0 <= b1 && b1 <= b2 && b2 <= b3 && b3 <= c.n_hits)) {
+            counts[e0 + te] = -1;
+            accept[e0 + te] = 0;
+            if (status) atomicOr(status, TRIG_STATUS_MALFORMED);
+            atomicOr(&L.s_bad, 1);
+            continue;
+        }
+        const int n0 = b1 - b0, n1 = b2 - b1, n2 = b3 - b2;
+        const int64_t n01 = (int64_t)n0 * n1;
+        int R = 0, T = 0, res = 0, work = 0;
+        if (n2 > 0 && (n01 > (int64_t)INT32_MAX || n01 * n2 > (int64_t)INT32_MAX)) {
+            res = -2;
+        } else if (n0 > 0 && n1 > 0 && n2 > 0) {
+            work = 1;
+            lane_layout(n0, n1, R, T);
+        }
+        L.da[te] = (uint32_t)(b0 - a0) | ((uint32_t)n0 << 13) | ((uint32_t)(work ? R : 0) << 26);
+        L.db[te] = (uint32_t)(b1 - a0) | ((uint32_t)n1 << 13) | ((uint32_t)(T >> 2) << 26);
+        L.dc[te] = (uint32_t)(b2 - a0) | ((uint32_t)n2 << 13);
+        L.sres[te] = res;
+    }
+}
+
 // Counts of the described events from the staged hits (events round-robin
 // over the waves, a static assignment), then the results of events
 // [e_first, e_first + nsub) with one lane per event.  Ends with a barrier.
@@ -543,28 +576,6 @@ __device__ void block_general(BlockLds<HB, NW>& L, const Consts& c, const float*
     }
 }
 
-// The block kernel (one block of eb consecutive events per workgroup).
-// `vec`: x and y are 16-byte aligned (the pipelined kernel's same argument
-// slot carries its claim chunk instead).
-template <class P, int HB, int NW>
-__global__ __launch_bounds__(NW * kWave) void k_block(const int32_t* __restrict__ off, int n_events,
-                                                         const float* __restrict__ x,
-                                                         const float* __restrict__ y, Consts c, int eb,
-                                                         int n_blocks, unsigned* /*unused*/, int vec,
-                                                         int32_t* __restrict__ counts,
-                                                         uint8_t* __restrict__ accept, uint32_t* status) {
-    __shared__ __align__(16) BlockLds<HB, NW> L;
-    constexpr int NT = NW * kWave;
-    const int b = blockIdx.x;
-    if (b >= n_blocks) return;
-    const int e0 = b * eb;
-    const int ne = min(eb, n_events - e0);
-    for (int t = threadIdx.x; t <= 3 * ne; t += NT) L.soff[t] = off[3 * (int64_t)e0 + t];
-    __syncthreads();
-    const bool bad = block_validate(L, c, e0, ne, counts, accept, status);
-    block_general<P>(L, c, x, y, e0, ne, bad, vec != 0, counts, accept, status);
-}
-
 // Hits of one block held in registers between their load and their LDS
 // store: the float4 groups of [a0, a0 + 4 nq) (a0 = base rounded down to a
 // multiple of 4) that lie entirely below n_hits, loaded unconditionally
@@ -623,6 +634,42 @@ struct HitPrefetch {
             }
     }
 };
+
+// The block kernel (one block of eb consecutive events per workgroup).
+// `vec`: x and y are 16-byte aligned (the pipelined kernel's same argument
+// slot carries its claim chunk instead).  A block whose hits fit in LDS is
+// staged whole: its hit loads are issued first, the events are checked and
+// described while they are in flight, and one barrier later the counting
+// starts.  Other blocks take the general path.
+template <class P, int HB, int NW>
+__global__ __launch_bounds__(NW * kWave) void k_block(const int32_t* __restrict__ off, int n_events,
+                                                         const float* __restrict__ x,
+                                                         const float* __restrict__ y, Consts c, int eb,
+                                                         int n_blocks, unsigned* /*unused*/, int vec,
+                                                         int32_t* __restrict__ counts,
+                                                         uint8_t* __restrict__ accept, uint32_t* status) {
+    __shared__ __align__(16) BlockLds<HB, NW> L;
+    constexpr int NT = NW * kWave;
+    const int b = blockIdx.x;
+    if (b >= n_blocks) return;
+    const int e0 = b * eb;
+    const int ne = min(eb, n_events - e0);
+    for (int t = threadIdx.x; t <= 3 * ne; t += NT) L.soff[t] = off[3 * (int64_t)e0 + t];
+    if (threadIdx.x == 0) L.s_bad = 0;
+    __syncthreads();
+    const int base = uniform_i(L.soff[0]), end = uniform_i(L.soff[3 * ne]);
+    const bool whole = vec && 0 <= base && base <= end && end <= c.n_hits && end - base <= HB;
+    HitPrefetch<HB, NT> pf;
+    if (whole) pf.issue(x, y, base, end - base, c.n_hits);
+    block_check_describe(L, c, e0, ne, base & ~3, counts, accept, status);
+    if (whole) pf.store(x, y, base, end - base, L.stage_x, L.stage_y);
+    __syncthreads();
+    const bool bad = uniform_i(L.s_bad) != 0;
+    if (whole && !bad)
+        block_count<P>(L, c, e0, ne, counts, accept, status);
+    else
+        block_general<P>(L, c, x, y, e0, ne, bad, vec != 0, counts, accept, status);
+}
 
 // Persistent block kernel with a software pipeline: workgroups take chunks
 // of `chunk` consecutive blocks from *block_counter (zero at launch; one
