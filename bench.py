@@ -212,25 +212,35 @@ def serving_leg(s, full_counts, test, n_slices, load, n_streams, seed=11):
         srv.submit(slices[0].offsets, slices[0].x, slices[0].y)
         srv.poll(60000)
         origin = srv.now()
-        done, tickets, wall = serve.run_stream(srv, slices, arrivals, pace=True, poll_ms=1, deadline_s=240)
+        done, tickets, wall = serve.run_stream(srv, slices, arrivals, pace=True, poll_ms=1, deadline_s=240,
+                                               submit_threads=4)
         st = srv.stats()
-    lat, qwait, ev_done = [], [], 0
+    lat, qwait, ev_done, rows = [], [], 0, []
     for i, sl in enumerate(slices):
         f = done[tickets[i]]
         if f.status != 0 or not np.array_equal(f.counts, full_counts[sl.first: sl.first + sl.n_events]):
             print(f"bench.py: served slice {i} differs from the full-batch result", file=sys.stderr)
             sys.exit(1)
-        lat.append(f.t_done - (origin + arrivals[i]))
+        arrive = origin + arrivals[i]
+        lat.append(f.t_done - arrive)
         qwait.append(f.t_admit - f.t_submit)
         ev_done += sl.n_events
+        rows.append({"latency_ms": 1e3 * (f.t_done - arrive), "events": sl.n_events,
+                     "input_mb": (sl.x.size * 8 + sl.offsets.size * 4) / 1e6,
+                     "submit_delay_ms": 1e3 * (f.t_submit - arrive), "admit_ms": 1e3 * (f.t_admit - f.t_submit),
+                     "admit_to_done_ms": 1e3 * (f.t_done - f.t_admit)})
     lat = np.array(lat) * 1e3
+    mb = np.array([r["input_mb"] for r in rows])
+    fit = np.linalg.lstsq(np.vstack([np.ones_like(mb), mb]).T, lat, rcond=None)[0]
     return {"slices": n_slices, "slice_events": "U[10000, 1000000]", "offered_events_per_s": load,
             "arrival_rate_per_s": rate, "events_per_s": ev_done / wall, "wall_s": wall,
             "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
             "max_ms": float(lat.max()), "mean_admission_wait_ms": 1e3 * float(np.mean(qwait)),
-            "streams": n_streams, "max_in_flight": int(st.max_in_flight),
+            "streams": n_streams, "submit_threads": 4, "max_in_flight": int(st.max_in_flight),
             "latency": "scheduled arrival to result on the host (includes the copy into pinned staging, "
                        "H2D, kernels, D2H)",
+            "latency_fit_ms": {"intercept": float(fit[0]), "per_mb": float(fit[1])},
+            "slowest": sorted(rows, key=lambda r: -r["latency_ms"])[:3],
             "counts_identical_to_full_batch": True}
 
 

@@ -75,7 +75,8 @@ typedef struct {
     size_t hbm_in_use, hbm_peak;
 } trig_server_stats;
 
-/* Creates a server (allocates the HBM arena, pinned staging, streams and a
+/* Creates a server (allocates the HBM arena and pinned staging, writes the
+ * staging once so that its pages are in place, creates the streams and a
  * dispatcher thread).  Errors: TRIG_EINVAL for bad sizes or parameters
  * (trig_select's checks), TRIG_EHIP if an allocation fails. */
 int trig_server_create(const trig_server_config *cfg, trig_server **out);

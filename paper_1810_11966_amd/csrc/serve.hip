@@ -56,6 +56,7 @@ struct CopySeg {
     size_t bytes;
 };
 constexpr size_t kCopyParallelMin = 8u << 20;  // below this, one memcpy per segment
+constexpr size_t kStageChunk = 32u << 20;      // staging is published in chunks of this size
 constexpr unsigned kCopyThreadsMax = 8;
 
 void copy_segments(const CopySeg* seg, int n_seg) {
@@ -84,6 +85,9 @@ struct Slice {
     uint64_t ticket = 0;
     int32_t n_events = 0, n_hits = 0;
     size_t pin_off = 0, dev_off = 0, ws_bytes = 0;
+    size_t staged = 0;    // bytes of the input prefix (offsets | x | y) in pinned staging
+    size_t issued = 0;    // bytes of it whose copy to the device is enqueued
+    bool launched = false;  // selection and result copy enqueued
     int stream = -1;
     State state = State::Queued;
     int32_t status = TRIG_OK;
@@ -126,19 +130,42 @@ struct trig_server {
         return trig_workspace_bytes(&ev, &p);
     }
 
-    // Enqueue copies, selection and result copy of an admitted slice on its
-    // stream (called with mu held).
+    // An admitted slice (mu held): takes stream si; its input is copied to the
+    // device as far as it is staged, the rest by progress() as submit()
+    // publishes it.
     void launch(Slice& s, int si) {
-        const Layout L(s.n_events, s.n_hits, s.ws_bytes);
-        char* d = dev_base + s.dev_off;
-        char* h = pin_base + s.pin_off;
-        hipStream_t st = streams[si];
         s.stream = si;
         s.state = State::InFlight;
         s.t_admit = now();
         stream_ticket[si] = s.ticket;
+        ++stats.in_flight;
+        if (stats.in_flight > stats.max_in_flight) stats.max_in_flight = stats.in_flight;
+        if (adm.arena().in_use() > stats.hbm_peak) stats.hbm_peak = adm.arena().in_use();
+        progress(s);
+    }
+
+    // Enqueues the copy of newly staged input and, once all of it is on its
+    // way, the selection, the result copy and the completion event (mu held).
+    void progress(Slice& s) {
+        if (s.launched) return;
+        const Layout L(s.n_events, s.n_hits, s.ws_bytes);
+        char* d = dev_base + s.dev_off;
+        char* h = pin_base + s.pin_off;
+        hipStream_t st = streams[s.stream];
+        const size_t total = L.status;  // offsets | x | y
         int rc = TRIG_OK;
-        if (hipMemcpyAsync(d, h, L.counts, hipMemcpyHostToDevice, st) != hipSuccess) rc = TRIG_EHIP;
+        if (s.staged > s.issued) {
+            if (hipMemcpyAsync(d + s.issued, h + s.issued, s.staged - s.issued, hipMemcpyHostToDevice, st) !=
+                hipSuccess)
+                rc = TRIG_EHIP;
+            s.issued = s.staged;
+        }
+        if (rc == TRIG_OK && s.issued < total) return;  // more to come
+        s.launched = true;
+        if (rc == TRIG_OK &&
+            hipMemcpyAsync(d + L.status, h + L.status, L.counts - L.status, hipMemcpyHostToDevice, st) !=
+                hipSuccess)
+            rc = TRIG_EHIP;
         if (rc == TRIG_OK) {
             trig_params p = cfg.params;
             p.flags |= TRIG_OUT_COMPACT;
@@ -155,11 +182,8 @@ struct trig_server {
         if (rc == TRIG_OK &&
             hipMemcpyAsync(h + L.status, d + L.status, L.host_bytes - L.status, hipMemcpyDeviceToHost, st) != hipSuccess)
             rc = TRIG_EHIP;
-        if (rc == TRIG_OK && hipEventRecord(events[si], st) != hipSuccess) rc = TRIG_EHIP;
+        if (rc == TRIG_OK && hipEventRecord(events[s.stream], st) != hipSuccess) rc = TRIG_EHIP;
         s.status = rc;
-        ++stats.in_flight;
-        if (stats.in_flight > stats.max_in_flight) stats.max_in_flight = stats.in_flight;
-        if (adm.arena().in_use() > stats.hbm_peak) stats.hbm_peak = adm.arena().in_use();
     }
 
     // Marks a slice finished (mu held): frees its device memory and stream.
@@ -199,6 +223,11 @@ struct trig_server {
                 const uint64_t t = stream_ticket[si];
                 if (!t) continue;
                 Slice& s = slices[t];
+                if (!s.launched) progress(s);
+                if (!s.launched) {
+                    busy = true;  // waiting for submit() to stage the rest
+                    continue;
+                }
                 if (s.status != TRIG_OK || hipEventQuery(events[si]) == hipSuccess) {
                     finish(s);
                     any = true;
@@ -243,6 +272,21 @@ int trig_server_create(const trig_server_config* cfg, trig_server** out) {
         if (s->dev_base) (void)hipFree(s->dev_base);
         delete s;
         return TRIG_EHIP;
+    }
+    // Touch the whole pinned arena once (in parallel): its first CPU writes
+    // are an order of magnitude slower than later ones, and would otherwise
+    // land on the first slices' latency.
+    {
+        const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+        const unsigned nt = std::min(kCopyThreadsMax, hw);
+        const size_t total = cfg->pinned_budget_bytes;
+        std::vector<std::thread> th;
+        for (unsigned q = 0; q < nt; ++q)
+            th.emplace_back([=] {
+                const size_t lo = total * q / nt, hi = total * (q + 1) / nt;
+                std::memset(s->pin_base + lo, 0, hi - lo);
+            });
+        for (auto& t : th) t.join();
     }
     s->streams.resize(cfg->n_streams);
     s->events.resize(cfg->n_streams);
@@ -293,18 +337,37 @@ int trig_server_submit(trig_server* s, const int32_t* offsets, const float* x, c
         sl.ws_bytes = ws;
         sl.state = State::Queued;
         sl.t_submit = s->now();
-        ++s->stats.pending;  // counted now; the staging below completes before it can be admitted
+        ++s->stats.pending;
+        // Queued before it is staged: it may be admitted (and its input start
+        // moving to the device) while the copy below is still running.
+        s->adm.enqueue(t, L.dev_bytes);
+        ++s->stats.submitted;
     }
+    s->cv_work.notify_one();
     char* h = s->pin_base + pin_off;
+    std::memset(h + L.status, 0, 4);
+    // Stage in layout order, publishing the staged prefix chunk by chunk.
     const CopySeg seg[3] = {{h + L.off, reinterpret_cast<const char*>(offsets), 4 * (size_t)(3 * n_events + 1)},
                             {h + L.x, reinterpret_cast<const char*>(x), n_hits ? 4 * (size_t)n_hits : 0},
                             {h + L.y, reinterpret_cast<const char*>(y), n_hits ? 4 * (size_t)n_hits : 0}};
-    copy_segments(seg, 3);
-    std::memset(h + L.status, 0, 4);
-    {
-        std::lock_guard<std::mutex> lk(s->mu);
-        s->adm.enqueue(t, L.dev_bytes);
-        ++s->stats.submitted;
+    const size_t seg_end[3] = {L.x, L.y, L.status};  // the next segment's start (padding included)
+    for (int k = 0; k < 3; ++k) {
+        for (size_t done = 0; done < seg[k].bytes;) {
+            const size_t piece = std::min(kStageChunk, seg[k].bytes - done);
+            const CopySeg part{seg[k].dst + done, seg[k].src + done, piece};
+            copy_segments(&part, 1);
+            done += piece;
+            const size_t prefix = done == seg[k].bytes ? seg_end[k] : (size_t)(seg[k].dst - h) + done;
+            {
+                std::lock_guard<std::mutex> lk(s->mu);
+                s->slices[t].staged = prefix;
+            }
+            s->cv_work.notify_one();
+        }
+        if (seg[k].bytes == 0) {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->slices[t].staged = seg_end[k];
+        }
     }
     s->cv_work.notify_one();
     *ticket = t;

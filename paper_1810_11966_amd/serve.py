@@ -162,34 +162,61 @@ class Server:
 
 
 def run_stream(server: Server, slices, arrivals_s, pace: bool = True, poll_ms: int = 1,
-               deadline_s: float = 300.0):
+               deadline_s: float = 300.0, submit_threads: int = 1):
     """Submits ``slices`` (EventSet-like objects with offsets, x, y) at
     ``arrivals_s`` (seconds from now; if pace is False, as fast as possible)
     and returns {ticket: Finished} plus the index -> ticket map and the wall
-    time.  Busy servers are retried after polling.  Raises TimeoutError if
-    the stream has not finished after ``deadline_s``."""
+    time.  With ``submit_threads`` > 1, slices are submitted by that many
+    threads (concurrent arrivals stage in parallel; each thread takes the next
+    slice in arrival order).  Busy servers are retried after a short wait.
+    Raises TimeoutError if the stream has not finished after ``deadline_s``."""
+    import threading
+
     done, tickets = {}, {}
     start = time.perf_counter()
-    i = 0
-    while i < len(slices) or len(done) < len(slices):
-        if time.perf_counter() - start > deadline_s:
-            raise TimeoutError(f"stream unfinished: {i} submitted, {len(done)} done")
-        if i < len(slices) and (not pace or time.perf_counter() - start >= arrivals_s[i]):
+    lock = threading.Lock()
+    next_i = [0]
+    errors = []
+
+    def submitter():
+        while True:
+            with lock:
+                i = next_i[0]
+                next_i[0] += 1
+            if i >= len(slices):
+                return
+            if pace:
+                dt = arrivals_s[i] - (time.perf_counter() - start)
+                if dt > 0:
+                    time.sleep(dt)
             s = slices[i]
-            t = server.submit(s.offsets, s.x, s.y)
-            if t is not None:
-                tickets[i] = t
-                i += 1
-                continue
-        wait = 0
-        if i >= len(slices) or not pace:
-            wait = poll_ms
-        f = server.poll(wait)
+            while True:
+                if time.perf_counter() - start > deadline_s:
+                    errors.append(TimeoutError(f"slice {i} not accepted before the deadline"))
+                    return
+                try:
+                    t = server.submit(s.offsets, s.x, s.y)
+                except Exception as e:  # surfaced in the caller
+                    errors.append(e)
+                    return
+                if t is not None:
+                    with lock:
+                        tickets[i] = t
+                    break
+                time.sleep(poll_ms / 1e3)
+
+    threads = [threading.Thread(target=submitter, daemon=True) for _ in range(max(1, submit_threads))]
+    for th in threads:
+        th.start()
+    while len(done) < len(slices):
+        if errors:
+            raise errors[0]
+        if time.perf_counter() - start > deadline_s:
+            raise TimeoutError(f"stream unfinished: {len(tickets)} submitted, {len(done)} done")
+        f = server.poll(poll_ms)
         while f is not None:
             done[f.ticket] = f
             f = server.poll(0)
-        if i < len(slices) and pace:
-            dt = arrivals_s[i] - (time.perf_counter() - start)
-            if dt > 0:
-                time.sleep(min(dt, poll_ms / 1e3))
+    for th in threads:
+        th.join()
     return done, tickets, time.perf_counter() - start
