@@ -128,7 +128,7 @@ enum {
                                    key interval can pass (MSD: |a|, |b| <=
                                    beta; window: the slope windows), with the
                                    interval ends rounded outwards; same
-                                   counts.  Events with more than 512 hits in
+                                   counts.  Events with more than 256 hits in
                                    layer 1 or 2 take the pruned path.  With
                                    TRIG_EXEC_PERSISTENT workgroups take event
                                    groups from a counter (needs workspace).

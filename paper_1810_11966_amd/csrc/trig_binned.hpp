@@ -36,7 +36,7 @@
 
 namespace trig {
 
-constexpr int kBinCap = 512;            // layer-1 / layer-2 hits per event in LDS
+constexpr int kBinCap = 256;            // layer-1 / layer-2 hits per event in LDS
 constexpr int kBinRounds = kBinCap / kWave;
 
 // Next binary32 value above f (f not NaN; +inf stays).

@@ -187,7 +187,7 @@ def special_values_events(seed):
     # a vertex track among hits at the origin
     events.append([[(0.0, 0.0)] * 4 + [track((0.3, 0.3))[l]] for l in range(3)])
     # more hits than the binned form keeps in LDS (layer 1, layer 2)
-    for sizes in ((20, 700, 20), (20, 20, 700), (5, 513, 512)):
+    for sizes in ((20, 700, 20), (20, 20, 700), (5, 513, 512), (20, 256, 256), (20, 257, 30), (30, 40, 257)):
         layers = [noisy(n) for n in sizes]
         for l in range(3):
             layers[l][0] = track((0.05, -0.2))[l]
