@@ -418,16 +418,6 @@ float pair_bound(float qmax) {
     });
 }
 
-// Largest finite binary32 k >= 0 with f32(by * k) <= bx (by, bx >= 0): then
-// |v| <= by implies f32(|v| * k) <= f32(by * k) <= bx.
-float prefilter_scale(float by, float bx) {
-    const float k = largest_with([&](float v) {
-        volatile float prod = by * v;
-        return (float)prod <= bx;
-    });
-    return std::isinf(k) ? std::numeric_limits<float>::max() : k;
-}
-
 Consts make_consts(const trig_params* p, int n_hits) {
     Consts c;
     const double z0 = p->z[0], z1 = p->z[1], z2 = p->z[2];
@@ -448,8 +438,8 @@ Consts make_consts(const trig_params* p, int n_hits) {
     c.qmax_y = fold_threshold(p->msd_max[1], p->ndf);
     c.beta_x = pair_bound(c.qmax_x);
     c.beta_y = pair_bound(c.qmax_y);
-    c.pre_k_msd = prefilter_scale(c.beta_y, c.beta_x);
-    c.pre_k_win = prefilter_scale(p->slope_window[1], p->slope_window[0]);
+    c.pre_msd = std::max(c.beta_x, c.beta_y);
+    c.pre_win = std::max(p->slope_window[0], p->slope_window[1]);
     c.win_x = p->slope_window[0];
     c.win_y = p->slope_window[1];
     c.bin_r = p->test == TRIG_TEST_SLOPE_WINDOW ? c.win_x : std::nextafter(c.beta_x, INFINITY);

@@ -76,13 +76,15 @@ struct MsdPrune {
         const float ay = p.y + q.y;
         return lanes(__builtin_fabsf(ax) <= c.beta_x) & lanes(__builtin_fabsf(ay) <= c.beta_y);
     }
-    // Prefilter score: pair_mask's lane set is within {score <= bound()}.
-    __device__ static __forceinline__ float score(const Consts& c, float2 p, float2 q) {
+    // Prefilter score: pair_mask's lane set is within {score <= bound()}
+    // (|a_x| <= beta_x and |a_y| <= beta_y imply max(|a_x|, |a_y|) <= the
+    // larger beta; same binary32 a as the exact test, no rounding of its own).
+    __device__ static __forceinline__ float score(const Consts&, float2 p, float2 q) {
         const float ax = p.x + q.x;
         const float ay = p.y + q.y;
-        return __builtin_fmaxf(__builtin_fabsf(ax), __builtin_fabsf(ay) * c.pre_k_msd);
+        return __builtin_fmaxf(__builtin_fabsf(ax), __builtin_fabsf(ay));
     }
-    __device__ static __forceinline__ float bound(const Consts& c) { return c.beta_x; }
+    __device__ static __forceinline__ float bound(const Consts& c) { return c.pre_msd; }
     // Passing triplets of the surviving pair (hi, hj) over layer-2 hits
     // [o2, o2 + n2): lanes over k, the binary32 test of include/trig.h.
     template <class H>
@@ -121,10 +123,11 @@ struct WindowPrune {
     __device__ static __forceinline__ uint64_t pair_mask(const Consts& c, float2 p, float2 q) {
         return lanes(__builtin_fabsf(q.x - p.x) < c.win_x) & lanes(__builtin_fabsf(q.y - p.y) < c.win_y);
     }
-    __device__ static __forceinline__ float score(const Consts& c, float2 p, float2 q) {
-        return __builtin_fmaxf(__builtin_fabsf(q.x - p.x), __builtin_fabsf(q.y - p.y) * c.pre_k_win);
+    __device__ static __forceinline__ float score(const Consts&, float2 p, float2 q) {
+        return __builtin_fmaxf(__builtin_fabsf(q.x - p.x), __builtin_fabsf(q.y - p.y));
     }
-    __device__ static __forceinline__ float bound(const Consts& c) { return c.win_x; }
+    // |d_x| < W_x and |d_y| < W_y imply max(|d_x|, |d_y|) <= the larger window.
+    __device__ static __forceinline__ float bound(const Consts& c) { return c.pre_win; }
     template <class H>
     __device__ static uint32_t complete(const Consts& c, const H& hits, int hi, int /*hj*/, int o2, int n2) {
         const float2 ci = hits.at(hi);

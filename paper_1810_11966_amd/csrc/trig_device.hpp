@@ -27,11 +27,10 @@ struct Consts {
     float qmax_x, qmax_y;
     // MSD pair bound: largest binary32 b >= 0 with f32(b * b) <= qmax, per plane
     float beta_x, beta_y;
-    // Pair prefilter of the batched form: one bound and a y-plane scale, so
-    // that (|u| <= bx and |v| <= by) implies max(|u|, f32(|v| * k)) <= bx.
-    // MSD: bx = beta_x, k = largest binary32 with f32(beta_y * k) <= beta_x.
-    // Window: the same with the windows in place of beta.
-    float pre_k_msd, pre_k_win;
+    // Pair prefilter of the batched form: (|u| <= bx and |v| <= by) implies
+    // max(|u|, |v|) <= max(bx, by).  MSD: the larger beta; window: the larger
+    // window.
+    float pre_msd, pre_win;
     // TRIG_TEST_SLOPE_WINDOW
     float win_x, win_y;
     // Binned form: half-width of the key interval around a hit's centre
