@@ -135,21 +135,32 @@ __device__ Bins build_bins(const Consts& c, const float* __restrict__ x, const f
         }
     }
     wave_lds_sync();
-    // Exclusive scan of the cell sizes: lane L owns cells [L*per, L*per + per).
+    // Exclusive scan of the cell sizes: lane L owns cells [L*per, L*per + per)
+    // (per = 1, 2 or 4), read and written with one vector access per lane
+    // (consecutive lanes, consecutive addresses: no bank conflicts).
+    static_assert(kBinCap <= 4 * kWave, "at most four cells per lane");
     const int per = b.n_cells / kWave;  // n_cells is a multiple of 64
-    int local = 0;
-    for (int q = 0; q < per; ++q) local += end[lane * per + q];
+    int4 sz = make_int4(0, 0, 0, 0);
+    if (per == 4)
+        sz = reinterpret_cast<const int4*>(end)[lane];
+    else if (per == 2)
+        sz = make_int4(reinterpret_cast<const int2*>(end)[lane].x, reinterpret_cast<const int2*>(end)[lane].y, 0, 0);
+    else
+        sz.x = end[lane];
+    const int local = (sz.x + sz.y) + (sz.z + sz.w);
     int incl = local;
     for (int d = 1; d < kWave; d <<= 1) {
         const int v = __shfl_up(incl, d);
         if (lane >= d) incl += v;
     }
-    int run = incl - local;
-    for (int q = 0; q < per; ++q) {
-        const int sz = end[lane * per + q];
-        end[lane * per + q] = run;  // start of the cell
-        run += sz;
-    }
+    const int s0 = incl - local;  // starts of the lane's cells
+    const int4 st = make_int4(s0, s0 + sz.x, s0 + sz.x + sz.y, s0 + sz.x + sz.y + sz.z);
+    if (per == 4)
+        reinterpret_cast<int4*>(end)[lane] = st;
+    else if (per == 2)
+        reinterpret_cast<int2*>(end)[lane] = make_int2(st.x, st.y);
+    else
+        end[lane] = st.x;
     wave_lds_sync();
     // Scatter; afterwards end[cell] is the end of the cell.
 #pragma unroll
