@@ -309,31 +309,34 @@ constexpr int kBinResident = 6;  // persistent binned workgroups per CU (LDS bou
 
 // One wave per event, events [4 b, 4 b + 4) for workgroup block b.
 // Non-persistent when block_counter == nullptr (b = blockIdx.x); otherwise
-// workgroups take blocks from *block_counter (zero at launch) until none is
-// left.  Events with more than kBinCap hits in layer 1 or 2 take the
-// pair-pruned path from HBM.
+// workgroups take chunks of `chunk` consecutive blocks from *block_counter
+// (zero at launch; one atomic per chunk) until none is left.  Events with
+// more than kBinCap hits in layer 1 or 2 take the pair-pruned path from HBM.
 template <class B>
 __global__ __launch_bounds__(kBinWaves * kWave) void k_binned(
     const int32_t* __restrict__ off, int n_events, const float* __restrict__ x, const float* __restrict__ y,
-    Consts c, unsigned* block_counter, int32_t* __restrict__ counts, uint8_t* __restrict__ accept,
+    Consts c, unsigned* block_counter, int chunk, int32_t* __restrict__ counts, uint8_t* __restrict__ accept,
     uint32_t* status) {
     __shared__ __align__(16) BinLds lds_all[kBinWaves];
-    __shared__ unsigned s_block;
+    __shared__ unsigned s_chunk;
     const int w = uniform_i((int)(threadIdx.x / kWave));
     BinLds& L = lds_all[w];
-    const unsigned n_blocks = (unsigned)(((int64_t)n_events + kBinWaves - 1) / kBinWaves);
-    unsigned blk = blockIdx.x;
+    const int64_t n_blocks = ((int64_t)n_events + kBinWaves - 1) / kBinWaves;
+    int64_t first = blockIdx.x, last = first + 1;
     for (;;) {
         if (block_counter) {
             // every branch below depends on workgroup-uniform values only
-            if (threadIdx.x == 0) s_block = atomicAdd(block_counter, 1u);
+            if (threadIdx.x == 0) s_chunk = atomicAdd(block_counter, 1u);
             __syncthreads();
-            blk = (unsigned)uniform_i((int)s_block);
+            first = (int64_t)(unsigned)uniform_i((int)s_chunk) * chunk;
+            last = min(first + chunk, n_blocks);
             __syncthreads();
         }
-        if (blk >= n_blocks) break;
-        const int e = (int)blk * kBinWaves + w;
-        if (e < n_events) {
+        if (first >= n_blocks) break;
+        for (int64_t blk = first; blk < last; ++blk) {
+            const int64_t e64 = blk * kBinWaves + w;
+            if (e64 >= n_events) continue;
+            const int e = (int)e64;
             EventRange ev;
             int32_t cnt = load_event(off, e, c.n_hits, ev);
             if (cnt == 0 && ev.n0 > 0 && ev.n1 > 0 && ev.n2 > 0) {
@@ -699,9 +702,11 @@ int launch_binned(const trig_events_csr* ev, const trig_hits* h, const trig_para
         if (int r = check_launch("k_zero_u32")) return r;
         grid = (unsigned)std::min<int64_t>(n_blocks, (int64_t)device_cus() * kBinResident);
     }
+    // Persistent: chunks of blocks per claim, about kClaimsPerGroup claims per workgroup.
+    const int chunk = counter ? (int)std::max<int64_t>(1, n_blocks / ((int64_t)grid * kClaimsPerGroup)) : 1;
     if (mark_start(s)) return fail(TRIG_EHIP, "hipEventRecord(start)");
     hipLaunchKernelGGL(k_binned<B>, dim3(grid), dim3(kBinWaves * kWave), 0, s, ev->layer_offsets, n, h->x, h->y, c,
-                       counter, counts, accept, p->out_status);
+                       counter, chunk, counts, accept, p->out_status);
     if (int r = check_launch("k_binned")) return r;
     if (mark_stop(s)) return fail(TRIG_EHIP, "hipEventRecord(stop)");
     return TRIG_OK;
