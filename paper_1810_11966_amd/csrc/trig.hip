@@ -312,8 +312,10 @@ constexpr int kBinResident = 6;  // persistent binned workgroups per CU (LDS bou
 // workgroups take chunks of `chunk` consecutive blocks from *block_counter
 // (zero at launch; one atomic per chunk) until none is left.  Events with
 // more than kBinCap hits in layer 1 or 2 take the pair-pruned path from HBM.
+// The register budget is held to kBinResident waves per SIMD, the occupancy
+// its LDS allows (one wave per SIMD per workgroup).
 template <class B>
-__global__ __launch_bounds__(kBinWaves * kWave) void k_binned(
+__global__ __launch_bounds__(kBinWaves * kWave) __attribute__((amdgpu_waves_per_eu(kBinResident))) void k_binned(
     const int32_t* __restrict__ off, int n_events, const float* __restrict__ x, const float* __restrict__ y,
     Consts c, unsigned* block_counter, int chunk, int32_t* __restrict__ counts, uint8_t* __restrict__ accept,
     uint32_t* status) {

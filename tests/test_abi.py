@@ -195,6 +195,37 @@ def test_msd_kernels_have_no_fma_or_packed_fp32(isa):
         assert not bad, (name, bad[:5])
 
 
+def kernel_descriptors(isa_text):
+    """{kernel: {field: int}} from the .amdhsa_kernel blocks."""
+    out, name = {}, None
+    for line in isa_text.splitlines():
+        t = line.strip()
+        if t.startswith(".amdhsa_kernel "):
+            name = t.split()[1]
+            out[name] = {}
+        elif t.startswith(".end_amdhsa_kernel"):
+            name = None
+        elif name and t.startswith(".amdhsa_"):
+            parts = t.split()
+            if len(parts) == 2 and parts[1].lstrip("-").isdigit():
+                out[name][parts[0][len(".amdhsa_"):]] = int(parts[1])
+    return out
+
+
+def test_kernel_resources(isa):
+    """No kernel spills to scratch; the binned kernels fit six waves per SIMD
+    (their LDS allows six 4-wave workgroups per CU): at most 80 VGPRs plus
+    AGPRs out of the 512 per SIMD lane."""
+    desc = kernel_descriptors(isa)
+    assert len(desc) >= 10
+    for name, d in desc.items():
+        assert d["private_segment_fixed_size"] == 0, name
+    binned = {k: v for k, v in desc.items() if "k_binned" in k}
+    assert len(binned) == 2
+    for name, d in binned.items():
+        assert d["next_free_vgpr"] <= 80, (name, d["next_free_vgpr"])
+
+
 def test_fp32_subnormals_enabled(isa):
     modes = re.findall(r"\.amdhsa_float_denorm_mode_32\s+(\d+)", isa)
     assert modes and all(m == "3" for m in modes)
