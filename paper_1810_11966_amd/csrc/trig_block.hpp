@@ -23,7 +23,9 @@
 // part of a; for n1 <= 32 the 64 lanes hold R = floor(64/n1) copies of the
 // layer-1 hits, copy g scanning layer-0 hits i = g, g+R, g+2R, ... so that
 // few lanes idle.  The layer-0 part of a (or the layer-0 slope) is computed
-// once per hit into a per-wave LDS buffer and read with a broadcast.
+// once per hit into a per-wave LDS buffer and read with a broadcast.  An
+// event that fits one pass takes layer 0 into the lanes instead when that
+// needs fewer buffer steps (the pair tests are symmetric in the two layers).
 #pragma once
 
 #include "trig_device.hpp"
@@ -31,6 +33,7 @@
 namespace trig {
 
 constexpr int kPBuf = 64;      // per-wave buffer of layer-0 values (float2)
+static_assert(kPBuf == kWave, "the fast path fills the buffer with one entry per lane");
 constexpr int kMaxEB = 128;    // events per block at most
 
 // Small exact quotients without integer division: for 0 <= a < 4096 and
@@ -69,6 +72,11 @@ struct MsdPrune {
     }
     __device__ static __forceinline__ float2 layer1(const Consts& c, float2 h) {
         return make_float2(c.U1 * h.x, c.U1 * h.y);
+    }
+    // layer0 (l == 0) or layer1 (l == 1), l wave-uniform: the same product.
+    __device__ static __forceinline__ float2 layer(const Consts& c, float2 h, int l) {
+        const float u = uniform_f(l ? c.U1 : c.U0);
+        return make_float2(u * h.x, u * h.y);
     }
     // Lanes whose pair can still pass: |f32(P + Q)| <= beta in both planes.
     __device__ static __forceinline__ uint64_t pair_mask(const Consts& c, float2 p, float2 q) {
@@ -119,6 +127,10 @@ struct WindowPrune {
     }
     __device__ static __forceinline__ float2 layer1(const Consts& c, float2 h) {
         return make_float2(h.x / c.z1, h.y / c.z1);
+    }
+    __device__ static __forceinline__ float2 layer(const Consts& c, float2 h, int l) {
+        const float z = uniform_f(l ? c.z1 : c.z0);
+        return make_float2(h.x / z, h.y / z);
     }
     __device__ static __forceinline__ uint64_t pair_mask(const Consts& c, float2 p, float2 q) {
         return lanes(__builtin_fabsf(q.x - p.x) < c.win_x) & lanes(__builtin_fabsf(q.y - p.y) < c.win_y);
@@ -218,57 +230,65 @@ __device__ uint32_t wave_event_pruned(const Consts& c, const H& hits, int o0, in
     return cnt;
 }
 
-// Fast path (one layer-1 pass, one buffer fill; R and T from lane_layout):
-// lane L holds layer-1 hit j of copy g and its partial q; the layer-0
-// partials of the event go to px/py (NaN past n0).
+// Fast path (one lane pass, one buffer fill of at most kPBuf <= kWave
+// entries; R, T and the orientation from event_layout).  One of layers 0 and 1 goes to the lanes (layer l = S ? 0 :
+// 1, offset oL, nL hits), the other to the LDS buffer (offset oB, nB hits):
+// lane L holds lane-layer hit j of copy g and its partial q; the buffer
+// layer's partials go to px/py (NaN past nB).  Both pair tests depend on the
+// two partials symmetrically (a sum, or the absolute value of a difference,
+// which binary32 gives the same either way round), so the orientation does
+// not change a count.
 template <class P, class H>
-__device__ __forceinline__ void fast_setup(const Consts& c, const H& hits, int o0, int n0, int o1, int n1, int R,
-                                           int T, float* __restrict__ px, float* __restrict__ py, int& g, int& j,
-                                           float2& q) {
+__device__ __forceinline__ void fast_setup(const Consts& c, const H& hits, int oB, int nB, int oL, int nL, int S,
+                                           int R, int T, float* __restrict__ px, float* __restrict__ py, int& g,
+                                           int& j, float2& q) {
     const int lane = (int)lane_id();
     g = 0;
     j = lane;
     if (R > 1) {
-        g = div_small(lane, n1);
-        j = lane - g * n1;
+        g = div_small(lane, nL);
+        j = lane - g * nL;
     }
-    const bool jv = (g < R) && (j < n1);
+    const bool jv = (g < R) && (j < nL);
     if (!jv) g = 0;
-    q = jv ? P::layer1(c, hits.at(o1 + j)) : nan2();
-    const int npad = T * R;
-    for (int t = lane; t < npad; t += kWave) {
-        const float2 v = t < n0 ? P::layer0(c, hits.at(o0 + t)) : nan2();
-        px[t] = v.x;
-        py[t] = v.y;
-    }
+    // Branch-free: every lane reads an in-range hit (indices clamped) and
+    // selects NaN where it has none; the whole kPBuf-entry buffer (>= T R
+    // entries) is written.
+    const float nan = __builtin_nanf("");
+    const float2 hq = P::layer(c, hits.at(oL + min(j, nL - 1)), S ? 0 : 1);
+    q = make_float2(jv ? hq.x : nan, jv ? hq.y : nan);
+    const float2 v = P::layer(c, hits.at(oB + min(lane, nB - 1)), S ? 1 : 0);
+    px[lane] = lane < nB ? v.x : nan;
+    py[lane] = lane < nB ? v.y : nan;
 }
 
-// Smallest prefilter score of the four pairs (g T + t .. g T + t + 3, j)
-// (fmin drops NaN scores; all NaN gives NaN, which fails every bound).
+// m folded with the prefilter scores of the four pairs (g T + t .. g T + t +
+// 3, j): fmin drops NaN scores; all NaN leaves m, and NaN fails every bound.
 template <class P>
-__device__ __forceinline__ float fast_group(const Consts& c, const float4* ppx, const float4* ppy, int t, float2 q) {
+__device__ __forceinline__ float fast_fold(const Consts& c, const float4* ppx, const float4* ppy, int t, float2 q,
+                                           float m) {
     const float4 vx = ppx[t >> 2], vy = ppy[t >> 2];
     const float s0 = P::score(c, make_float2(vx.x, vy.x), q);
     const float s1 = P::score(c, make_float2(vx.y, vy.y), q);
     const float s2 = P::score(c, make_float2(vx.z, vy.z), q);
     const float s3 = P::score(c, make_float2(vx.w, vy.w), q);
-    return __builtin_fminf(__builtin_fminf(s0, s1), __builtin_fminf(s2, s3));
+    return __builtin_fminf(__builtin_fminf(__builtin_fminf(__builtin_fminf(m, s0), s1), s2), s3);
 }
 
 // Exact pass over all pairs of the fast-path layout (taken only when some
 // prefilter score reached the bound): the exact pair test per pair, then the
-// surviving pairs completed against layer 2.
+// surviving pairs completed against layer 2 (layer-0 hit first).
 template <class P, class H>
-__device__ uint32_t fast_exact(const Consts& c, const H& hits, int o0, int o1, int o2, int n2, int T, int g, int j,
-                               float2 q, const float* px, const float* py) {
+__device__ uint32_t fast_exact(const Consts& c, const H& hits, int oB, int oL, int S, int o2, int n2, int T, int g,
+                               int j, float2 q, const float* px, const float* py) {
     uint32_t cnt = 0;
     auto finish = [&](uint64_t m, int t) {
         while (m) {
             const int L = __builtin_ctzll(m);
             m &= m - 1;
-            const int iL = __builtin_amdgcn_readlane(g, L) * T + t;
-            const int jL = __builtin_amdgcn_readlane(j, L);
-            cnt += P::complete(c, hits, o0 + iL, o1 + jL, o2, n2);
+            const int hB = oB + __builtin_amdgcn_readlane(g, L) * T + t;
+            const int hL = oL + __builtin_amdgcn_readlane(j, L);
+            cnt += S ? P::complete(c, hits, hL, hB, o2, n2) : P::complete(c, hits, hB, hL, o2, n2);
         }
     };
     const float4* ppx = reinterpret_cast<const float4*>(px + g * T);
@@ -283,35 +303,55 @@ __device__ uint32_t fast_exact(const Consts& c, const H& hits, int o0, int o1, i
     return cnt;
 }
 
-// Passing triplets of an event with 1 <= n1 <= 64 and n0 <= the buffer fill
-// for its lane layout (one layer-1 pass, one buffer fill): the computation of
-// wave_event_pruned with its loops taken once, and the prefilter minimum
-// taken over the whole event before one vote.  R and T come from the
-// per-event descriptor (lane_layout).
+// Passing triplets of an event that fits one lane pass and one buffer fill
+// in the orientation S (S = 0: layer 1 in the lanes, as wave_event_pruned;
+// S = 1: layer 0): the computation of wave_event_pruned with its loops taken
+// once, and the prefilter minimum taken over the whole event before one
+// vote.  R, T and S come from the per-event descriptor (event_layout).
 template <class P, class H>
 __device__ uint32_t wave_event_fast(const Consts& c, const H& hits, int o0, int n0, int o1, int n1, int o2,
-                                    int n2, int R, int T, float* __restrict__ px, float* __restrict__ py) {
+                                    int n2, int R, int T, int S, float* __restrict__ px, float* __restrict__ py) {
+    const int oB = S ? o1 : o0, nB = S ? n1 : n0;
+    const int oL = S ? o0 : o1, nL = S ? n0 : n1;
     int g, j;
     float2 q;
-    fast_setup<P>(c, hits, o0, n0, o1, n1, R, T, px, py, g, j, q);
+    fast_setup<P>(c, hits, oB, nB, oL, nL, S, R, T, px, py, g, j, q);
     wave_lds_sync();
     const float4* ppx = reinterpret_cast<const float4*>(px + g * T);
     const float4* ppy = reinterpret_cast<const float4*>(py + g * T);
     float m = __builtin_nanf("");
-    for (int t = 0; t < T; t += 4) m = __builtin_fminf(m, fast_group<P>(c, ppx, ppy, t, q));
+    int t = 0;
+    for (; t + 8 <= T; t += 8) m = fast_fold<P>(c, ppx, ppy, t + 4, q, fast_fold<P>(c, ppx, ppy, t, q, m));
+    if (t < T) m = fast_fold<P>(c, ppx, ppy, t, q, m);
     uint32_t cnt = 0;
-    if (wave_any(m <= P::bound(c))) cnt = fast_exact<P>(c, hits, o0, o1, o2, n2, T, g, j, q, px, py);
+    if (wave_any(m <= P::bound(c))) cnt = fast_exact<P>(c, hits, oB, oL, S, o2, n2, T, g, j, q, px, py);
     wave_lds_sync();
     return cnt;
 }
 
-// Lane layout of wave_event_pruned for one buffer fill: R copies of layer 1
-// and T (a multiple of 4) layer-0 entries per copy; T = 0 when the event
-// needs more than one layer-1 pass or buffer fill.
-__device__ __forceinline__ void lane_layout(int n0, int n1, int& R, int& T) {
-    R = n1 <= kWave / 2 ? min(div_small(kWave, n1), kPBuf / 4) : 1;
+// Lane layout of wave_event_pruned for one buffer fill with nL hits in the
+// lanes and nB in the buffer: R copies of the lane layer and T (a multiple
+// of 4) buffer entries per copy; T = 0 when the event needs more than one
+// lane pass or buffer fill.
+__device__ __forceinline__ void lane_layout(int nB, int nL, int& R, int& T) {
+    R = nL <= kWave / 2 ? min(div_small(kWave, nL), kPBuf / 4) : 1;
     const int chunk = div_small(kPBuf, 4 * R) * 4 * R;
-    T = (n1 <= kWave && n0 <= chunk) ? div_small(n0 + 4 * R - 1, 4 * R) * 4 : 0;
+    T = (nL <= kWave && nB <= chunk) ? div_small(nB + 4 * R - 1, 4 * R) * 4 : 0;
+}
+
+// Layout of an event with n0, n1 >= 1: layer 1 in the lanes (S = 0, the
+// layout of wave_event_pruned), or layer 0 (S = 1) when only that fits the
+// fast path or it takes fewer buffer steps (T).  T = 0: general path.
+__device__ __forceinline__ void event_layout(int n0, int n1, int& R, int& T, int& S) {
+    int R1, T1;
+    lane_layout(n0, n1, R, T);
+    lane_layout(n1, n0, R1, T1);
+    S = 0;
+    if (T1 > 0 && (T == 0 || T1 < T)) {
+        R = R1;
+        T = T1;
+        S = 1;
+    }
 }
 
 // Count of event e (absolute index) whose CSR range was checked by the
@@ -402,8 +442,8 @@ struct BlockLds {
     float pbuf_x[NW][kPBuf];
     float pbuf_y[NW][kPBuf];
     // Event descriptors, 13-bit fields (local hit indices < HB + 8 <= 4104,
-    // layer sizes <= HB <= 4096): da = o0 | n0 << 13 | R << 26 (R <= 16),
-    // db = o1 | n1 << 13 | (T / 4) << 26 (T <= 64), dc = o2 | n2 << 13.
+    // layer sizes <= HB <= 4096): da = o0 | n0 << 13 | R << 26 (R <= 16) |
+    // S << 31, db = o1 | n1 << 13 | (T / 4) << 26 (T <= 64), dc = o2 | n2 << 13.
     uint32_t da[kMaxEB], db[kMaxEB], dc[kMaxEB];
     int32_t soff[3 * kMaxEB + 1];
     int32_t sres[kMaxEB];
@@ -443,14 +483,15 @@ __device__ void block_descriptors(BlockLds<HB, NW>& L, int cur, int nsub, int a0
         const int b0 = L.soff[3 * ev], b1 = L.soff[3 * ev + 1], b2 = L.soff[3 * ev + 2], b3 = L.soff[3 * ev + 3];
         const int n0 = b1 - b0, n1 = b2 - b1, n2 = b3 - b2;
         const int64_t n01 = (int64_t)n0 * n1;
-        int R = 0, T = 0, res = 0, work = 0;
+        int R = 0, T = 0, S = 0, res = 0, work = 0;
         if (n2 > 0 && (n01 > (int64_t)INT32_MAX || n01 * n2 > (int64_t)INT32_MAX)) {
             res = -2;
         } else if (n0 > 0 && n1 > 0 && n2 > 0) {
             work = 1;
-            lane_layout(n0, n1, R, T);
+            event_layout(n0, n1, R, T, S);
         }
-        L.da[te] = (uint32_t)(b0 - a0) | ((uint32_t)n0 << 13) | ((uint32_t)(work ? R : 0) << 26);
+        L.da[te] = (uint32_t)(b0 - a0) | ((uint32_t)n0 << 13) | ((uint32_t)(work ? R : 0) << 26) |
+                   ((uint32_t)S << 31);
         L.db[te] = (uint32_t)(b1 - a0) | ((uint32_t)n1 << 13) | ((uint32_t)(T >> 2) << 26);
         L.dc[te] = (uint32_t)(b2 - a0) | ((uint32_t)n2 << 13);
         L.sres[te] = res;
@@ -477,14 +518,15 @@ __device__ __forceinline__ void block_check_describe(BlockLds<HB, NW>& L, const 
         }
         const int n0 = b1 - b0, n1 = b2 - b1, n2 = b3 - b2;
         const int64_t n01 = (int64_t)n0 * n1;
-        int R = 0, T = 0, res = 0, work = 0;
+        int R = 0, T = 0, S = 0, res = 0, work = 0;
         if (n2 > 0 && (n01 > (int64_t)INT32_MAX || n01 * n2 > (int64_t)INT32_MAX)) {
             res = -2;
         } else if (n0 > 0 && n1 > 0 && n2 > 0) {
             work = 1;
-            lane_layout(n0, n1, R, T);
+            event_layout(n0, n1, R, T, S);
         }
-        L.da[te] = (uint32_t)(b0 - a0) | ((uint32_t)n0 << 13) | ((uint32_t)(work ? R : 0) << 26);
+        L.da[te] = (uint32_t)(b0 - a0) | ((uint32_t)n0 << 13) | ((uint32_t)(work ? R : 0) << 26) |
+                   ((uint32_t)S << 31);
         L.db[te] = (uint32_t)(b1 - a0) | ((uint32_t)n1 << 13) | ((uint32_t)(T >> 2) << 26);
         L.dc[te] = (uint32_t)(b2 - a0) | ((uint32_t)n2 << 13);
         L.sres[te] = res;
@@ -507,11 +549,12 @@ __device__ void block_count(BlockLds<HB, NW>& L, const Consts& c, int e_first, i
         const uint32_t db = (uint32_t)uniform_i((int)L.db[te]);
         const uint32_t dc = (uint32_t)uniform_i((int)L.dc[te]);
         constexpr uint32_t kF = (1u << 13) - 1;
-        const int o0 = (int)(da & kF), n0 = (int)((da >> 13) & kF), R = (int)(da >> 26);
+        const int o0 = (int)(da & kF), n0 = (int)((da >> 13) & kF), R = (int)((da >> 26) & 31u);
+        const int S = (int)(da >> 31);
         const int o1 = (int)(db & kF), n1 = (int)((db >> 13) & kF), T = (int)(db >> 26) * 4;
         const int o2 = (int)(dc & kF), n2 = (int)((dc >> 13) & kF);
         if (R == 0) continue;  // decided in the descriptor pass
-        const uint32_t cnt = T > 0 ? wave_event_fast<P>(c, lh, o0, n0, o1, n1, o2, n2, R, T, px, py)
+        const uint32_t cnt = T > 0 ? wave_event_fast<P>(c, lh, o0, n0, o1, n1, o2, n2, R, T, S, px, py)
                                    : wave_event_pruned<P>(c, lh, o0, n0, o1, n1, o2, n2, px, py);
         if (lane_id() == 0) L.sres[te] = (int32_t)cnt;
     }

@@ -41,6 +41,9 @@ struct Consts {
 };
 
 __device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
+__device__ __forceinline__ float uniform_f(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+}
 
 __device__ __forceinline__ unsigned lane_id() { return threadIdx.x & (kWave - 1); }
 

@@ -205,6 +205,22 @@ def test_ragged_layer_sizes(gpu):
                     assert_parity(gpu, s, test, form, f"ragged tile_pairs={tp}", tile_pairs=tp)
 
 
+def test_layer_orientation_grid(gpu):
+    """Layer-0/1 size pairs on both sides of the lane-count boundaries (32,
+    64) and of the per-wave buffer (48 or 64 entries): events that put layer 1
+    into the lanes, events that put layer 0 there, and events of the general
+    path; each has an exact track, so the exact pass of either orientation
+    must find it."""
+    ns = (1, 4, 7, 16, 21, 31, 32, 33, 40, 48, 49, 63, 64, 65, 80)
+    sizes = [(a, b, 9) for a in ns for b in ns] + [(a, b, 70) for a in (5, 33, 65) for b in (5, 33, 65)]
+    for seed in (2, 3):
+        s = helpers.ragged_sizes_set(sizes, seed=seed)
+        for test in ("msd", "window"):
+            for form in ("pruned", "persistent_pruned", "auto"):
+                c = assert_parity(gpu, s, test, form, f"orientation grid seed={seed}")
+        assert (c > 0).all()
+
+
 def test_dense_and_mixture_samples(gpu):
     dense = synth.make_event_set(synth.DENSE_100K, n_events=400)
     mix = synth.make_event_set(synth.MIXTURE_4M, n_events=4000)
