@@ -75,7 +75,7 @@ struct MsdPrune {
     }
     // layer0 (l == 0) or layer1 (l == 1), l wave-uniform: the same product.
     __device__ static __forceinline__ float2 layer(const Consts& c, float2 h, int l) {
-        const float u = uniform_f(l ? c.U1 : c.U0);
+        const float u = select_uniform(l, c.U1, c.U0);
         return make_float2(u * h.x, u * h.y);
     }
     // Lanes whose pair can still pass: |f32(P + Q)| <= beta in both planes.
@@ -129,7 +129,7 @@ struct WindowPrune {
         return make_float2(h.x / c.z1, h.y / c.z1);
     }
     __device__ static __forceinline__ float2 layer(const Consts& c, float2 h, int l) {
-        const float z = uniform_f(l ? c.z1 : c.z0);
+        const float z = select_uniform(l, c.z1, c.z0);
         return make_float2(h.x / z, h.y / z);
     }
     __device__ static __forceinline__ uint64_t pair_mask(const Consts& c, float2 p, float2 q) {
@@ -230,9 +230,10 @@ __device__ uint32_t wave_event_pruned(const Consts& c, const H& hits, int o0, in
     return cnt;
 }
 
-// Fast path (one lane pass, one buffer fill of at most kPBuf <= kWave
-// entries; R, T and the orientation from event_layout).  One of layers 0 and 1 goes to the lanes (layer l = S ? 0 :
-// 1, offset oL, nL hits), the other to the LDS buffer (offset oB, nB hits):
+// Fast path (one lane pass, one buffer fill of at most kPBuf = kWave
+// entries; R, T and the orientation from event_layout).  One of layers 0
+// and 1 goes to the lanes (layer l = S ? 0 : 1, offset oL, nL hits), the
+// other to the LDS buffer (offset oB, nB hits):
 // lane L holds lane-layer hit j of copy g and its partial q; the buffer
 // layer's partials go to px/py (NaN past nB).  Both pair tests depend on the
 // two partials symmetrically (a sum, or the absolute value of a difference,
@@ -243,12 +244,10 @@ __device__ __forceinline__ void fast_setup(const Consts& c, const H& hits, int o
                                            int R, int T, float* __restrict__ px, float* __restrict__ py, int& g,
                                            int& j, float2& q) {
     const int lane = (int)lane_id();
-    g = 0;
-    j = lane;
-    if (R > 1) {
-        g = div_small(lane, nL);
-        j = lane - g * nL;
-    }
+    // floor(lane / nL) for every R: with R = 1 (nL > 32) lanes past nL get
+    // g = 1 and no hit
+    g = div_small(lane, nL);
+    j = lane - g * nL;
     const bool jv = (g < R) && (j < nL);
     if (!jv) g = 0;
     // Branch-free: every lane reads an in-range hit (indices clamped) and
@@ -556,7 +555,7 @@ __device__ void block_count(BlockLds<HB, NW>& L, const Consts& c, int e_first, i
         if (R == 0) continue;  // decided in the descriptor pass
         const uint32_t cnt = T > 0 ? wave_event_fast<P>(c, lh, o0, n0, o1, n1, o2, n2, R, T, S, px, py)
                                    : wave_event_pruned<P>(c, lh, o0, n0, o1, n1, o2, n2, px, py);
-        if (lane_id() == 0) L.sres[te] = (int32_t)cnt;
+        L.sres[te] = (int32_t)cnt;  // uniform: every lane stores the same value
     }
     __syncthreads();
     for (int te = threadIdx.x; te < nsub; te += NT) {

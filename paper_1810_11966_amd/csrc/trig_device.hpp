@@ -41,8 +41,14 @@ struct Consts {
 };
 
 __device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
-__device__ __forceinline__ float uniform_f(float v) {
-    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, v)));
+// cond ? a : b for wave-uniform operands, on the scalar unit (a compare
+// and a scalar select; the compiler would otherwise select per lane).
+__device__ __forceinline__ float select_uniform(int cond, float a, float b) {
+    const int c = uniform_i(cond);
+    const int ia = uniform_i(__builtin_bit_cast(int, a)), ib = uniform_i(__builtin_bit_cast(int, b));
+    int r;
+    asm("s_cmp_lg_u32 %1, 0\n\ts_cselect_b32 %0, %2, %3" : "=s"(r) : "s"(c), "s"(ia), "s"(ib) : "scc");
+    return __builtin_bit_cast(float, r);
 }
 
 __device__ __forceinline__ unsigned lane_id() { return threadIdx.x & (kWave - 1); }
