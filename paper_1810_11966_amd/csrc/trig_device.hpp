@@ -54,11 +54,15 @@ __device__ __forceinline__ float select_uniform(int cond, float a, float b) {
 __device__ __forceinline__ unsigned lane_id() { return threadIdx.x & (kWave - 1); }
 
 // Order this wave's LDS writes before its later LDS reads (and keep the
-// compiler from moving memory operations across).
+// compiler from moving memory operations across).  Within one wave only the
+// LDS counter has to drain (s_waitcnt lgkmcnt(0); vmcnt and expcnt left at
+// their maxima, the gfx9 encoding): global loads in flight, such as the next
+// block's prefetch, keep flying.  A workgroup fence would wait for those too.
 __device__ __forceinline__ void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    asm volatile("" ::: "memory");
+    __builtin_amdgcn_s_waitcnt(0xC07F);
     __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    asm volatile("" ::: "memory");
 }
 
 // Number of lanes of the wave with pred set (the lane mask goes straight to
