@@ -88,11 +88,26 @@ struct Bins {
     }
 };
 
-// Counting sort of the hits [o, o + n) (n <= kBinCap) of one layer into
-// cells of the key K::key, storing K::payload in cell order.  Whole wave.
+// The hits [o, o + n) (1 <= n <= kBinCap) of one layer in registers, hit
+// r kWave + lane in round r; the loads are issued together and unguarded
+// (indices clamped to the layer), so that several layers can be in flight.
+struct LayerRegs {
+    float x[kBinRounds], y[kBinRounds];
+    __device__ __forceinline__ void load(const float* __restrict__ xs, const float* __restrict__ ys, int o, int n) {
+        const int lane = (int)lane_id();
+#pragma unroll
+        for (int r = 0; r < kBinRounds; ++r) {
+            const int t = min(r * kWave + lane, n - 1);
+            x[r] = xs[o + t];
+            y[r] = ys[o + t];
+        }
+    }
+};
+
+// Counting sort of the n hits of one layer (held in h) into cells of the key
+// K::key, storing K::payload in cell order.  Whole wave.
 template <class K>
-__device__ Bins build_bins(const Consts& c, const float* __restrict__ x, const float* __restrict__ y, int o,
-                           int n, int* end, float* pa, float* pb) {
+__device__ Bins build_bins(const Consts& c, const LayerRegs& h, int n, int* end, float* pa, float* pb) {
     const int lane = (int)lane_id();
     float key[kBinRounds];
     float2 pay[kBinRounds];
@@ -102,9 +117,8 @@ __device__ Bins build_bins(const Consts& c, const float* __restrict__ x, const f
         const int t = r * kWave + lane;
         key[r] = __builtin_nanf("");
         if (t < n) {
-            const float xv = x[o + t], yv = y[o + t];
-            key[r] = K::key(c, xv, yv);
-            pay[r] = K::payload(c, xv, yv);
+            key[r] = K::key(c, h.x[r], h.y[r]);
+            pay[r] = K::payload(c, h.x[r], h.y[r]);
         }
         if (__builtin_isfinite(key[r])) {
             lo = __builtin_fminf(lo, key[r]);
@@ -272,12 +286,27 @@ struct WindowBin {
 template <class B>
 __device__ uint32_t wave_event_binned(const Consts& c, const float* __restrict__ x, const float* __restrict__ y,
                                       int o0, int n0, int o1, int n1, int o2, int n2, BinLds& L) {
-    const Bins b1 = build_bins<typename B::Key1>(c, x, y, o1, n1, L.end1, L.a1, L.b1);
-    const Bins b2 = build_bins<typename B::Key2>(c, x, y, o2, n2, L.end2, L.a2, L.b2);
+    // The loads of layers 1 and 2 and of layer 0's first round in flight at
+    // once (one HBM latency, not three); later layer-0 rounds are loaded one
+    // round ahead.  Indices are clamped to the layers (n0, n1, n2 >= 1).
+    const int lane = (int)lane_id();
+    LayerRegs h1, h2;
+    h1.load(x, y, o1, n1);
+    h2.load(x, y, o2, n2);
+    float xi = x[o0 + min(lane, n0 - 1)], yi = y[o0 + min(lane, n0 - 1)];
+    const Bins b1 = build_bins<typename B::Key1>(c, h1, n1, L.end1, L.a1, L.b1);
+    const Bins b2 = build_bins<typename B::Key2>(c, h2, n2, L.end2, L.a2, L.b2);
     uint32_t cnt = 0;
     for (int i0 = 0; i0 < n0; i0 += kWave) {
-        const int i = i0 + (int)lane_id();
-        if (i < n0) cnt += B::count_i(c, x[o0 + i], y[o0 + i], b1, b2, L);
+        float xn = 0.0f, yn = 0.0f;
+        if (i0 + kWave < n0) {  // wave-uniform
+            const int in = min(i0 + kWave + lane, n0 - 1);
+            xn = x[o0 + in];
+            yn = y[o0 + in];
+        }
+        if (i0 + lane < n0) cnt += B::count_i(c, xi, yi, b1, b2, L);
+        xi = xn;
+        yi = yn;
     }
     cnt = wave_sum_u(cnt);
     wave_lds_sync();  // the next event rebuilds the cells
