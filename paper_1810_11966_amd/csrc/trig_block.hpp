@@ -658,7 +658,12 @@ struct HitGroups<0, NT> {
 
 template <int HB, int NT>
 struct HitPrefetch {
-    static constexpr int Q = (HB + 6) / 4 / NT + 1;  // float4 groups per thread, upper bound
+    // Blocks of at most kCap = HB - 4 hits: with base - a0 <= 3 they span at
+    // most ceil((kCap + 3) / 4) = HB / 4 float4 groups (HB a multiple of 4),
+    // so Q groups per thread hold them; larger blocks take the general path.
+    static_assert(HB % 4 == 0, "block capacity a multiple of 4");
+    static constexpr int kCap = HB - 4;
+    static constexpr int Q = (HB / 4 + NT - 1) / NT;  // float4 groups per thread
     HitGroups<Q, NT> g;
     int nq_full;
     __device__ __forceinline__ void issue(const float* __restrict__ x, const float* __restrict__ y, int base,
@@ -703,8 +708,9 @@ __global__ __launch_bounds__(NW * kWave) void k_block(const int32_t* __restrict_
     if (threadIdx.x == 0) L.s_bad = 0;
     __syncthreads();
     const int base = uniform_i(L.soff[0]), end = uniform_i(L.soff[3 * ne]);
-    const bool whole = vec && 0 <= base && base <= end && end <= c.n_hits && end - base <= HB;
-    HitPrefetch<HB, NT> pf;
+    using Prefetch = HitPrefetch<HB, NT>;
+    const bool whole = vec && 0 <= base && base <= end && end <= c.n_hits && end - base <= Prefetch::kCap;
+    Prefetch pf;
     if (whole) pf.issue(x, y, base, end - base, c.n_hits);
     block_check_describe(L, c, e0, ne, base & ~3, counts, accept, status);
     if (whole) pf.store(x, y, base, end - base, L.stage_x, L.stage_y);
@@ -757,7 +763,7 @@ __global__ __launch_bounds__(NW * kWave) void k_block_pipe(const int32_t* __rest
     {
         const int ne = min(eb, n_events - b * eb);
         const int base = L.soff[0], end = L.soff[3 * ne];
-        pf_ok = (0 <= base && base <= end && end <= c.n_hits && end - base <= HB);
+        pf_ok = (0 <= base && base <= end && end <= c.n_hits && end - base <= HitPrefetch<HB, NT>::kCap);
         if (pf_ok) pf.issue(x, y, base, end - base, c.n_hits);
     }
     for (;;) {
@@ -799,7 +805,7 @@ __global__ __launch_bounds__(NW * kWave) void k_block_pipe(const int32_t* __rest
         __syncthreads();
         if (has_next) {
             const int base = L.soff[0], end = L.soff[3 * nen];
-            pf_ok = (0 <= base && base <= end && end <= c.n_hits && end - base <= HB);
+            pf_ok = (0 <= base && base <= end && end <= c.n_hits && end - base <= HitPrefetch<HB, NT>::kCap);
             if (pf_ok) pf.issue(x, y, base, end - base, c.n_hits);
         }
         const int claimed = uniform_i(L.s_next);  // valid after a first block's barrier above
