@@ -48,18 +48,6 @@ __device__ __forceinline__ float next_up(float f) {
 }
 __device__ __forceinline__ float next_down(float f) { return -next_up(-f); }
 
-__device__ __forceinline__ float wave_min_f(float v) {
-    for (int d = 1; d < kWave; d <<= 1) v = __builtin_fminf(v, __shfl_xor(v, d));
-    return v;
-}
-__device__ __forceinline__ float wave_max_f(float v) {
-    for (int d = 1; d < kWave; d <<= 1) v = __builtin_fmaxf(v, __shfl_xor(v, d));
-    return v;
-}
-__device__ __forceinline__ uint32_t wave_sum_u(uint32_t v) {
-    for (int d = 1; d < kWave; d <<= 1) v += (uint32_t)__shfl_xor((int)v, d);
-    return v;
-}
 
 // LDS of one wave: cell ends and the two payload floats per hit, in cell
 // order, for layers 1 and 2.  Float arrays first (16-byte aligned: the
@@ -162,12 +150,7 @@ __device__ Bins build_bins(const Consts& c, const LayerRegs& h, int n, int* end,
     else
         sz.x = end[lane];
     const int local = (sz.x + sz.y) + (sz.z + sz.w);
-    int incl = local;
-    for (int d = 1; d < kWave; d <<= 1) {
-        const int v = __shfl_up(incl, d);
-        if (lane >= d) incl += v;
-    }
-    const int s0 = incl - local;  // starts of the lane's cells
+    const int s0 = wave_inclusive_sum(local) - local;  // starts of the lane's cells
     const int4 st = make_int4(s0, s0 + sz.x, s0 + sz.x + sz.y, s0 + sz.x + sz.y + sz.z);
     if (per == 4)
         reinterpret_cast<int4*>(end)[lane] = st;

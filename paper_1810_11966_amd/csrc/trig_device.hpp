@@ -73,6 +73,72 @@ __device__ __forceinline__ uint32_t wave_popc(bool pred) {
 
 __device__ __forceinline__ bool wave_any(bool pred) { return __builtin_amdgcn_ballot_w64(pred) != 0ull; }
 
+// Cross-lane steps on the vector unit (DPP, gfx9 controls) for whole-wave
+// code (all 64 lanes active).  dpp_i<C, ROWS>(old, v): lanes of the rows of 16
+// in the mask ROWS take v from the lane that control C names; other lanes,
+// and lanes whose source lies outside their row, keep `old`.
+constexpr int kDppQuadXor1 = 0xB1;     // quad_perm [1, 0, 3, 2]
+constexpr int kDppQuadXor2 = 0x4E;     // quad_perm [2, 3, 0, 1]
+constexpr int kDppRowShr = 0x110;      // row_shr:n = kDppRowShr + n
+constexpr int kDppRowMirror = 0x140;   // lane i of a row takes lane 15 - i
+constexpr int kDppHalfMirror = 0x141;  // lane i of a half row takes lane 7 - i
+constexpr int kDppBcast15 = 0x142;     // with rows 0xA: rows 1, 3 take lane 15 of the row before
+constexpr int kDppBcast31 = 0x143;     // with rows 0xC: rows 2, 3 take lane 31
+
+template <int C, int ROWS = 0xF>
+__device__ __forceinline__ int dpp_i(int old, int v) {
+    return __builtin_amdgcn_update_dpp(old, v, C, ROWS, 0xF, false);
+}
+template <int C, int ROWS = 0xF>
+__device__ __forceinline__ float dpp_f(float old, float v) {
+    return __builtin_bit_cast(float, dpp_i<C, ROWS>(__builtin_bit_cast(int, old), __builtin_bit_cast(int, v)));
+}
+
+// Wave-wide min, max and sum (result in every lane's return value, taken
+// from lane 63): butterflies within quads, mirrors within rows of 16 (every
+// lane then holds its row's result), then the row broadcasts carry rows 0-2
+// into row 3.  fminf/fmaxf drop NaN as the scalar functions do.
+__device__ __forceinline__ float wave_min_f(float v) {
+    v = __builtin_fminf(v, dpp_f<kDppQuadXor1>(v, v));
+    v = __builtin_fminf(v, dpp_f<kDppQuadXor2>(v, v));
+    v = __builtin_fminf(v, dpp_f<kDppHalfMirror>(v, v));
+    v = __builtin_fminf(v, dpp_f<kDppRowMirror>(v, v));
+    v = __builtin_fminf(v, dpp_f<kDppBcast15, 0xA>(v, v));
+    v = __builtin_fminf(v, dpp_f<kDppBcast31, 0xC>(v, v));
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+__device__ __forceinline__ float wave_max_f(float v) {
+    v = __builtin_fmaxf(v, dpp_f<kDppQuadXor1>(v, v));
+    v = __builtin_fmaxf(v, dpp_f<kDppQuadXor2>(v, v));
+    v = __builtin_fmaxf(v, dpp_f<kDppHalfMirror>(v, v));
+    v = __builtin_fmaxf(v, dpp_f<kDppRowMirror>(v, v));
+    v = __builtin_fmaxf(v, dpp_f<kDppBcast15, 0xA>(v, v));
+    v = __builtin_fmaxf(v, dpp_f<kDppBcast31, 0xC>(v, v));
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+__device__ __forceinline__ uint32_t wave_sum_u(uint32_t v) {
+    int x = (int)v;
+    x += dpp_i<kDppQuadXor1>(0, x);
+    x += dpp_i<kDppQuadXor2>(0, x);
+    x += dpp_i<kDppHalfMirror>(0, x);
+    x += dpp_i<kDppRowMirror>(0, x);
+    x += dpp_i<kDppBcast15, 0xA>(0, x);
+    x += dpp_i<kDppBcast31, 0xC>(0, x);
+    return (uint32_t)__builtin_amdgcn_readlane(x, 63);
+}
+// Inclusive prefix sum over the lanes: shifts by 1, 2, 4, 8 within rows
+// (lanes without a source add 0), then the row broadcasts add the totals of
+// the rows before.
+__device__ __forceinline__ int wave_inclusive_sum(int x) {
+    x += dpp_i<kDppRowShr + 1>(0, x);
+    x += dpp_i<kDppRowShr + 2>(0, x);
+    x += dpp_i<kDppRowShr + 4>(0, x);
+    x += dpp_i<kDppRowShr + 8>(0, x);
+    x += dpp_i<kDppBcast15, 0xA>(0, x);
+    x += dpp_i<kDppBcast31, 0xC>(0, x);
+    return x;
+}
+
 // Lane mask of a single comparison.  Combining two comparisons with a scalar
 // AND of their masks (rather than a ballot of `a & b`) keeps each predicate a
 // plain vector compare writing scalar registers.
