@@ -85,23 +85,26 @@ struct LayerRegs {
         const int lane = (int)lane_id();
 #pragma unroll
         for (int r = 0; r < kBinRounds; ++r) {
-            const int t = min(r * kWave + lane, n - 1);
-            x[r] = xs[o + t];
-            y[r] = ys[o + t];
+            x[r] = y[r] = 0.0f;
+            if (r * kWave < n) {  // wave-uniform: rounds past the layer are skipped
+                const int t = min(r * kWave + lane, n - 1);
+                x[r] = xs[o + t];
+                y[r] = ys[o + t];
+            }
         }
     }
 };
 
-// Counting sort of the n hits of one layer (held in h) into cells of the key
-// K::key, storing K::payload in cell order.  Whole wave.
-template <class K>
-__device__ Bins build_bins(const Consts& c, const LayerRegs& h, int n, int* end, float* pa, float* pb) {
+// Counting sort of the n hits of one layer (held in h, n <= NR kWave) into
+// cells of the key K::key, storing K::payload in cell order.  Whole wave.
+template <class K, int NR>
+__device__ Bins build_bins_r(const Consts& c, const LayerRegs& h, int n, int* end, float* pa, float* pb) {
     const int lane = (int)lane_id();
-    float key[kBinRounds];
-    float2 pay[kBinRounds];
+    float key[NR];
+    float2 pay[NR];
     float lo = __builtin_inff(), hi = -__builtin_inff();
 #pragma unroll
-    for (int r = 0; r < kBinRounds; ++r) {
+    for (int r = 0; r < NR; ++r) {
         const int t = r * kWave + lane;
         key[r] = __builtin_nanf("");
         if (t < n) {
@@ -127,9 +130,9 @@ __device__ Bins build_bins(const Consts& c, const LayerRegs& h, int n, int* end,
     b.inv_w = (width > 0.0f && width < __builtin_inff()) ? __builtin_amdgcn_rcpf(width) * (float)b.n_cells : 0.0f;
     for (int t = lane; t < b.n_cells; t += kWave) end[t] = 0;
     wave_lds_sync();
-    int cell[kBinRounds];
+    int cell[NR];
 #pragma unroll
-    for (int r = 0; r < kBinRounds; ++r) {
+    for (int r = 0; r < NR; ++r) {
         cell[r] = -1;
         if (!__builtin_isnan(key[r])) {
             cell[r] = b.cell(key[r]);
@@ -161,7 +164,7 @@ __device__ Bins build_bins(const Consts& c, const LayerRegs& h, int n, int* end,
     wave_lds_sync();
     // Scatter; afterwards end[cell] is the end of the cell.
 #pragma unroll
-    for (int r = 0; r < kBinRounds; ++r) {
+    for (int r = 0; r < NR; ++r) {
         if (cell[r] >= 0) {
             const int pos = atomicAdd(&end[cell[r]], 1);
             pa[pos] = pay[r].x;
@@ -170,6 +173,17 @@ __device__ Bins build_bins(const Consts& c, const LayerRegs& h, int n, int* end,
     }
     wave_lds_sync();
     return b;
+}
+
+// build_bins_r with the fewest rounds that hold the layer (1, 2 or 4 times
+// kWave hits; n <= kBinCap).
+template <class K>
+__device__ __forceinline__ Bins build_bins(const Consts& c, const LayerRegs& h, int n, int* end, float* pa,
+                                           float* pb) {
+    static_assert(kBinRounds == 4, "round counts 1, 2 and 4");
+    if (n <= kWave) return build_bins_r<K, 1>(c, h, n, end, pa, pb);
+    if (n <= 2 * kWave) return build_bins_r<K, 2>(c, h, n, end, pa, pb);
+    return build_bins_r<K, 4>(c, h, n, end, pa, pb);
 }
 
 // ---------------------------------------------------------------- MSD ---
