@@ -177,6 +177,38 @@ __global__ __launch_bounds__(kScanBlock) void k_compact_write(const uint8_t* __r
     if (blockIdx.x == 0 && threadIdx.x == 0) *n_out = partials[n_blocks];
 }
 
+// k_compact_write without the scan kernel before it: each block sums the
+// counts of the blocks before it (at most kPrefixBlocks of them, read from
+// L2), and the last block writes the total.
+constexpr int kPrefixBlocks = 4096;
+
+__global__ __launch_bounds__(kScanBlock) void k_compact_write_prefix(const uint8_t* __restrict__ accept,
+                                                                     int n_events,
+                                                                     const int32_t* __restrict__ partials,
+                                                                     int n_blocks,
+                                                                     int32_t* __restrict__ ids,
+                                                                     int32_t* __restrict__ n_out) {
+    int32_t before = 0;
+    for (int i = (int)threadIdx.x; i < (int)blockIdx.x; i += kScanBlock) before += partials[i];
+    int32_t prefix;
+    block_exclusive_scan<int32_t>(before, prefix);
+    const int64_t base = (int64_t)blockIdx.x * kScanBlock * kCompactItems +
+                         (int64_t)threadIdx.x * kCompactItems;
+    uint8_t f[kCompactItems];
+    int32_t c = 0;
+#pragma unroll
+    for (int k = 0; k < kCompactItems; ++k) {
+        f[k] = (base + k < n_events) ? (accept[base + k] != 0) : 0;
+        c += f[k];
+    }
+    int32_t total;
+    int32_t pos = prefix + block_exclusive_scan<int32_t>(c, total);
+#pragma unroll
+    for (int k = 0; k < kCompactItems; ++k)
+        if (f[k]) ids[pos++] = (int32_t)(base + k);
+    if ((int)blockIdx.x == n_blocks - 1 && threadIdx.x == 0) *n_out = prefix + total;
+}
+
 __global__ void k_store_zero(int32_t* p) { *p = 0; }
 
 // ------------------------------------------------------------ persistent ---
@@ -860,11 +892,18 @@ int trig_select(const trig_events_csr* ev, const trig_hits* hits, const trig_par
         auto* part = reinterpret_cast<int32_t*>(ws + L.compact_off);
         hipLaunchKernelGGL(k_compact_count, dim3(L.compact_blocks), dim3(kScanBlock), 0, s, out_accept, n, part);
         if (int r = check_launch("k_compact_count")) return r;
-        hipLaunchKernelGGL(k_scan_partials<int32_t>, dim3(1), dim3(kScanBlock), 0, s, part, L.compact_blocks);
-        if (int r = check_launch("k_scan_partials")) return r;
-        hipLaunchKernelGGL(k_compact_write, dim3(L.compact_blocks), dim3(kScanBlock), 0, s, out_accept, n, part,
-                           L.compact_blocks, p->out_accepted_ids, p->out_n_accepted);
-        if (int r = check_launch("k_compact_write")) return r;
+        if (L.compact_blocks <= kPrefixBlocks) {
+            // up to 4M events: no scan launch, each block sums the counts before it
+            hipLaunchKernelGGL(k_compact_write_prefix, dim3(L.compact_blocks), dim3(kScanBlock), 0, s, out_accept,
+                               n, part, L.compact_blocks, p->out_accepted_ids, p->out_n_accepted);
+            if (int r = check_launch("k_compact_write_prefix")) return r;
+        } else {
+            hipLaunchKernelGGL(k_scan_partials<int32_t>, dim3(1), dim3(kScanBlock), 0, s, part, L.compact_blocks);
+            if (int r = check_launch("k_scan_partials")) return r;
+            hipLaunchKernelGGL(k_compact_write, dim3(L.compact_blocks), dim3(kScanBlock), 0, s, out_accept, n,
+                               part, L.compact_blocks, p->out_accepted_ids, p->out_n_accepted);
+            if (int r = check_launch("k_compact_write")) return r;
+        }
     }
     g_detail.clear();
     return TRIG_OK;
