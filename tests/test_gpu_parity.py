@@ -345,6 +345,27 @@ def test_medium_1m_full_size_sampled(gpu):
     assert np.array_equal(w["counts"][:6000], c)
 
 
+def test_compaction_both_launch_paths(gpu):
+    """Accepted-id lists on both sides of the compaction's launch split (4096
+    blocks of 1024 events): below it each block sums the counts before it,
+    above it a scan kernel runs.  Small events with many injected exact
+    pairs, so that thousands of events are accepted; ids must be the ascending
+    accepted events, and the oracle checks the counts of three ranges."""
+    spec = synth.EventSetSpec(n_events=4_194_304 + 3000, hits_mean=1.0, p_inject=0.01, sigma=0.0, salt=77)
+    s = synth.make_event_set(spec)
+    for n in (4_194_304, s.n_events):
+        sub = s.subset(0, n)
+        print(f"[compact] events={n}", flush=True)
+        r = run_gpu(gpu, sub, "msd", "pruned")
+        assert r["ids"].size > 1000
+        assert np.array_equal(r["ids"], np.flatnonzero(r["accept"]))
+        for first in (0, n - 5000):
+            part = sub.subset(first, 5000)
+            c, a, _, _ = R.select_set(part, n_threads=THREADS)
+            assert np.array_equal(r["counts"][first:first + 5000], c), (n, first)
+            assert np.array_equal(r["accept"][first:first + 5000], a), (n, first)
+
+
 # -------------------------------------------------------------- autotuner ---
 
 @pytest.mark.parametrize("test", TESTS)
