@@ -47,6 +47,24 @@ __device__ __forceinline__ int div_small(int a, int n) {
     return (int)((float)a * __builtin_amdgcn_rcpf((float)n) + 0.0009765625f);
 }
 
+// floor(lane / n) for 0 <= lane < 64 and 1 <= n <= 64: (lane * r) >> 16 with
+// r = ceil(2^16 / n) (a 24-bit multiply and a shift).  With r n = 2^16 + d,
+// 0 <= d < n, the product is 2^16 lane / n + lane d / n, and lane d / n < 64
+// < 2^16 / n, which never reaches the next multiple of 2^16 / n.  The
+// table is read with a scalar load (n is wave-uniform).
+struct Recip16Table {
+    uint32_t r[kWave + 1];
+    constexpr Recip16Table() : r() {
+        for (int n = 1; n <= kWave; ++n) r[n] = (65536u + (uint32_t)n - 1u) / (uint32_t)n;
+    }
+};
+__constant__ constexpr Recip16Table kRecip16{};
+
+__device__ __forceinline__ int div_lane(int lane, int n) {
+    const uint32_t r = kRecip16.r[uniform_i(n)];
+    return (int)(__umul24((unsigned)lane, r) >> 16);
+}
+
 // Hits of the current sub-block in LDS (structure of arrays), indexed
 // relative to the staged range's 4-aligned start.
 struct LdsHits {
@@ -246,7 +264,7 @@ __device__ __forceinline__ void fast_setup(const Consts& c, const H& hits, int o
     const int lane = (int)lane_id();
     // floor(lane / nL) for every R: with R = 1 (nL > 32) lanes past nL get
     // g = 1 and no hit
-    g = div_small(lane, nL);
+    g = div_lane(lane, nL);
     j = lane - g * nL;
     const bool jv = (g < R) && (j < nL);
     if (!jv) g = 0;

@@ -247,3 +247,14 @@ def test_autotune_argument_checks(lib):
     rc, _ = trig.trig_autotune(ev, hits, fit, 0x2000, 0x3000, 101, 0)
     assert rc == trig.TRIG_EINVAL
     trig.trig_autotune_reset()
+
+
+def test_lane_division_identity():
+    """The batched kernel's lane division: floor(lane / n) = (lane *
+    ceil(2^16 / n)) >> 16 for every lane < 64 and 1 <= n <= 64, with the
+    product inside 24 bits (a 24-bit multiply)."""
+    for n in range(1, 65):
+        r = (65536 + n - 1) // n
+        for lane in range(64):
+            assert lane * r < (1 << 24)
+            assert (lane * r) >> 16 == lane // n, (n, lane)
