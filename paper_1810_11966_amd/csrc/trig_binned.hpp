@@ -18,11 +18,12 @@
 //     layer-2 condition depends on i alone, so an i's count is the product of
 //     its numbers of layer-1 and layer-2 partners.
 //
-// The interval ends are rounded outwards (one binary32 step past the rounded
-// end point), and the cell of a key is a non-decreasing function of the key,
-// so the cells from cell(lower end) to cell(upper end) contain every key in
-// the interval whatever the cell width.  Every candidate then gets the full
-// binary32 test, so the count is exact; a hit whose key is not finite can
+// The interval ends are rounded outwards (by at least one binary32 step
+// past the rounded end point), and the cell of a key is a non-decreasing
+// function of the key, so the cells from cell(lower end) to cell(upper end)
+// contain every key in the interval whatever the cell width.  Every
+// candidate then gets the full binary32 test, so the count is exact; a hit
+// whose key is not finite can
 // never pass (its a or b is infinite or NaN) and is left out.
 //
 // One wave per event.  Cells are built in LDS with a counting sort (histogram
@@ -39,14 +40,19 @@ namespace trig {
 constexpr int kBinCap = 256;            // layer-1 / layer-2 hits per event in LDS
 constexpr int kBinRounds = kBinCap / kWave;
 
-// Next binary32 value above f (f not NaN; +inf stays).
-__device__ __forceinline__ float next_up(float f) {
-    if (f == __builtin_inff()) return f;
-    if (f == 0.0f) return __uint_as_float(1u);  // smallest subnormal
-    const uint32_t b = __float_as_uint(f);
-    return __uint_as_float(f > 0.0f ? b + 1u : b - 1u);
+// f moved outwards by d = f32(f32(|f| 2^-22) + 2^-126), at least one binary32
+// step for any finite f (a step is at most 2^-23 |f| for normal f and 2^-149
+// below), so that the result lies beyond every real number that rounds to f
+// (those lie within 2^-24 |f| + 2^-150 of it): the rounding of the sum and
+// of the final subtraction stay far below the slack d leaves.  Infinities
+// stay infinite (+inf - inf is NaN, which the cell function maps to cell 0:
+// still a superset).  Three vector instructions, no branch.
+__device__ __forceinline__ float widen_down(float f) {
+    return f - (__builtin_fabsf(f) * 0x1p-22f + 0x1p-126f);
 }
-__device__ __forceinline__ float next_down(float f) { return -next_up(-f); }
+__device__ __forceinline__ float widen_up(float f) {
+    return f + (__builtin_fabsf(f) * 0x1p-22f + 0x1p-126f);
+}
 
 
 // LDS of one wave: cell ends and the two payload floats per hit, in cell
@@ -208,7 +214,7 @@ struct MsdBin {
         const float ux = c.U0 * xi;
         const float r = c.bin_r;
         if (!__builtin_isfinite(ux)) return 0;
-        const float lo = next_down(-ux - r), hi = next_up(-ux + r);
+        const float lo = widen_down(-ux - r), hi = widen_up(-ux + r);
         if (hi < b1.kmin || lo > b1.kmax) return 0;
         int j0, j1;
         b1.range(L.end1, lo, hi, j0, j1);
@@ -222,7 +228,7 @@ struct MsdBin {
             const float bx0 = c.V0 * xi + c.V1 * xj;
             const float by0 = c.V0 * yi + c.V1 * yj;
             if (!__builtin_isfinite(bx0)) continue;
-            const float lo2 = next_down(-bx0 - r), hi2 = next_up(-bx0 + r);
+            const float lo2 = widen_down(-bx0 - r), hi2 = widen_up(-bx0 + r);
             if (hi2 < b2.kmin || lo2 > b2.kmax) continue;
             int k0, k1;
             b2.range(L.end2, lo2, hi2, k0, k1);
@@ -258,7 +264,7 @@ struct WindowBin {
                                        const BinLds& L) {
         const float sxi = xi / c.z0, syi = yi / c.z0;
         if (!__builtin_isfinite(sxi)) return 0;
-        const float lo = next_down(sxi - c.bin_r), hi = next_up(sxi + c.bin_r);
+        const float lo = widen_down(sxi - c.bin_r), hi = widen_up(sxi + c.bin_r);
         uint32_t nj = 0, nk = 0;
         if (!(hi < b1.kmin || lo > b1.kmax)) {
             int j0, j1;

@@ -258,3 +258,24 @@ def test_lane_division_identity():
         for lane in range(64):
             assert lane * r < (1 << 24)
             assert (lane * r) >> 16 == lane // n, (n, lane)
+
+
+def test_binned_interval_widening_covers_one_step():
+    """The binned form widens each key-interval end by |f| 2^-22 + 2^-126
+    (binary32 multiply, add, subtract: the kernel's operation order).  The
+    result must lie at or beyond the next binary32 value in that direction
+    for every finite f, so that the cell range covers the exact interval."""
+    import numpy as np
+    f32 = np.float32
+    rng = np.random.default_rng(7)
+    vals = np.concatenate([
+        rng.uniform(-1, 1, 20000).astype(f32) * f32(2.0) ** rng.integers(-149, 128, 20000).astype(f32),
+        np.array([0.0, -0.0, 1e-45, -1e-45, 1.17549435e-38, -1.17549435e-38, 3.4028235e38, -3.4028235e38,
+                  1.0, -1.0, 0.24494897, -0.24494897], dtype=f32)])
+    vals = vals[np.isfinite(vals)]
+    with np.errstate(over="ignore"):
+        d = (np.abs(vals) * f32(2.0 ** -22)).astype(f32) + f32(2.0 ** -126)
+        down = (vals - d).astype(f32)
+        up = (vals + d).astype(f32)
+    assert (down <= np.nextafter(vals, f32(-np.inf))).all()
+    assert (up >= np.nextafter(vals, f32(np.inf))).all()
