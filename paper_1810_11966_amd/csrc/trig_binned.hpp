@@ -23,8 +23,8 @@
 // function of the key, so the cells from cell(lower end) to cell(upper end)
 // contain every key in the interval whatever the cell width.  Every
 // candidate then gets the full binary32 test, so the count is exact; a hit
-// whose key is not finite can
-// never pass (its a or b is infinite or NaN) and is left out.
+// whose key is not finite can never pass (its a or b is infinite or NaN) and
+// is left out.
 //
 // One wave per event.  Cells are built in LDS with a counting sort (histogram
 // of the cell indices, exclusive scan, scatter); events with more than
