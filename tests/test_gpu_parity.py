@@ -345,6 +345,40 @@ def test_medium_1m_full_size_sampled(gpu):
     assert np.array_equal(w["counts"][:6000], c)
 
 
+@pytest.mark.parametrize("name", ["dense_100k", "mixture_4m"])
+def test_dense_and_mixture_full_size_sampled(gpu, name):
+    """The 100k-event high-multiplicity and the 4M-event mixture workloads at
+    full size, autotuned as the benchmark runs them (trig_autotune on the
+    batch, then TRIG_EXEC_AUTOTUNE calls): the autotuned result equals every
+    exact form's on all events, and the oracle checks three ranges of events
+    one by one."""
+    from paper_1810_11966_amd import trig
+    s = synth.make_event_set(synth.WORKLOADS[name])
+    print(f"[full] {name} generated events={s.n_events} hits={s.n_hits}", flush=True)
+    off, x, y = to_dev(gpu, s)
+    trig.trig_autotune_reset()
+    r, info = trig.autotune(off, x, y, test="msd", reps=1, compact=True, want_status=True)
+    gpu.cuda.synchronize()
+    print(f"[full] {name} autotuned binned={info.binned} persistent={info.persistent} "
+          f"shape={info.block_hits},{info.block_waves},{info.block_events}", flush=True)
+    auto = run_gpu(gpu, s, "msd", "auto")
+    assert np.array_equal(r.counts.cpu().numpy(), auto["counts"])
+    for form in ("pruned", "persistent_pruned", "binned", "persistent_binned"):
+        print(f"[full] {name} form={form}", flush=True)
+        got = run_gpu(gpu, s, "msd", form)
+        assert np.array_equal(got["counts"], auto["counts"]), form
+        assert np.array_equal(got["ids"], auto["ids"]), form
+    assert np.array_equal(auto["ids"], np.flatnonzero(auto["accept"]))
+    assert auto["status"] == 0 and auto["ids"].size > 0
+    size = 300 if name == "dense_100k" else 5000
+    for first in (0, s.n_events // 2, s.n_events - size):
+        sub = s.subset(first, size)
+        c, a, _, _ = R.select_set(sub, n_threads=THREADS)
+        assert np.array_equal(auto["counts"][first:first + size], c), (name, first)
+        assert np.array_equal(auto["accept"][first:first + size], a), (name, first)
+    trig.trig_autotune_reset()
+
+
 def test_compaction_both_launch_paths(gpu):
     """Accepted-id lists on both sides of the compaction's launch split (4096
     blocks of 1024 events): below it each block sums the counts before it,
