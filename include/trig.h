@@ -13,9 +13,9 @@
  *      (0.03 for x-z, 0.025 for y-z);
  *   3. select the event if at least two triplets pass.
  * Input hits are grouped into events and carry coordinates (Sec. 3.2, last
- * paragraph; Sec. 4.3, trigger-station hits only and one coordinate array per
+ * paragraph; Sec. 5.3, trigger-station hits only and one coordinate array per
  * axis); the output is the per-event decision and the list of selected events
- * (Sec. 4.3, step 6).
+ * (Sec. 5.3, step 6).
  *
  * Conventions for every entry point:
  *   - Pointers are DEVICE memory unless a comment says "host".  The caller

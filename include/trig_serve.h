@@ -5,7 +5,7 @@
  *
  * The paper's deployment picture (Sec. 2 and Sec. 3.2): event data reach the
  * FLES compute nodes continuously, and on the GPU the transfer of one batch
- * can be hidden behind the computation of another (Sec. 4.3).  This runtime
+ * can be hidden behind the computation of another (Sec. 5.3).  This runtime
  * does that for a stream of timeslices:
  *   - submit() copies a slice (host CSR offsets and x, y) into pinned staging
  *     owned by the server (large slices with a few host threads) and queues

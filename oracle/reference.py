@@ -163,7 +163,7 @@ def basis_c(cfg: OracleConfig) -> np.ndarray:
 
 def accepted_ids(accept: np.ndarray) -> np.ndarray:
     """Ascending ids of accepted events (the list of selected events that the
-    paper transfers back to the host, Sec. 4.3 step 6)."""
+    paper transfers back to the host, Sec. 5.3 step 6)."""
     return np.flatnonzero(np.asarray(accept) != 0).astype(np.int32)
 
 

@@ -4,7 +4,7 @@
 // line through the vertex in x-z and y-z, rejected if the mean square
 // deviation per degree of freedom is above the plane's cut, and the event is
 // selected with at least two passing triplets.  The selected-event list is
-// what the paper copies back to the host (Sec. 4.3, step 6).
+// what the paper copies back to the host (Sec. 5.3, step 6).
 //
 // Kernels
 //   k_plain        one wave per event, all pair tiles, layer-2 hits in LDS
