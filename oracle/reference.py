@@ -17,6 +17,9 @@ Contents
   * ``fp32_error_bound``         a rigorous bound on |Q_fp32 - Q_exact| for the
                                  basis-form fp32 evaluation, used by the pins.
   * ``accepted_ids``             ascending ids of accepted events.
+  * ``filter_stations``          trigger-station filtering, the step before the
+                                 selection: per event the hits of the three
+                                 trigger layers, in input order.
 
 The fp32 decision contract, MSD test (default), per plane c in {x, y} with the
 hits c_i, c_j, c_k of layers 0, 1, 2 (every line one rounding to binary32):
@@ -292,3 +295,36 @@ def fp32_error_bound(ci, cj, ck, z):
     aa = np.abs(a) + da
     bb = np.abs(b) + db
     return 2 * aa * da + da * da + 2 * bb * db + db * db + 4 * u * (aa * aa + bb * bb)
+
+
+def filter_stations(offsets, station, x, y, layers):
+    """Trigger-station filtering, the step before the selection (the paper
+    keeps only the trigger station's hits before the transfer to the GPU,
+    Sec. 5.3, implementation i3).  Written from its definition, event by
+    event: the hits of trigger layer l of event e are the hits h in
+    [offsets[e], offsets[e+1]) with station[h] == layers[l], in input order.
+    An event whose range is not within [0, n_hits], is decreasing or holds
+    more than 2^31 - 1 hits keeps no hit and sets status bit 1.
+
+    Returns (layer_offsets int32[3E+1], x fp32[total], y fp32[total], status)
+    in the selection's input layout (event, then layer)."""
+    offsets = np.asarray(offsets, dtype=np.int64)
+    station = np.asarray(station, dtype=np.uint8)
+    n_events, n_hits = len(offsets) - 1, len(station)
+    starts, xs, ys, status, at = [], [], [], 0, 0
+    for e in range(n_events):
+        a, b = int(offsets[e]), int(offsets[e + 1])
+        ok = 0 <= a <= b <= n_hits and b - a <= 2**31 - 1
+        if not ok:
+            status |= 1
+        for layer in layers:
+            starts.append(at)
+            if ok:
+                idx = a + np.flatnonzero(station[a:b] == layer)
+                xs.append(np.asarray(x)[idx])
+                ys.append(np.asarray(y)[idx])
+                at += len(idx)
+    starts.append(at)
+    cat = (lambda parts: np.concatenate(parts).astype(np.float32) if parts else np.zeros(0, np.float32))
+    return np.asarray(starts, dtype=np.int64).astype(np.int32), cat(xs), cat(ys), status
+

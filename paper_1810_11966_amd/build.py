@@ -22,10 +22,12 @@ CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libtrig.so")
 ISA = os.path.join(ROOT, "_build", "trig-gfx950.s")
-SOURCES = [os.path.join(CSRC, "trig.hip"), os.path.join(CSRC, "probe.hip"), os.path.join(CSRC, "serve.hip")]
+SOURCES = [os.path.join(CSRC, "trig.hip"), os.path.join(CSRC, "probe.hip"), os.path.join(CSRC, "serve.hip"),
+           os.path.join(CSRC, "filter.hip")]
 HEADERS = [os.path.join(CSRC, "trig_device.hpp"), os.path.join(CSRC, "trig_block.hpp"),
            os.path.join(CSRC, "serve_core.hpp"), os.path.join(INCLUDE, "trig.h"),
-           os.path.join(INCLUDE, "trig_probe.h"), os.path.join(INCLUDE, "trig_serve.h")]
+           os.path.join(INCLUDE, "trig_probe.h"), os.path.join(INCLUDE, "trig_serve.h"),
+           os.path.join(INCLUDE, "trig_filter.h")]
 ARCH = "gfx950"
 
 COMMON = ["-std=c++17", "-O3", f"--offload-arch={ARCH}", "-ffp-contract=off",

@@ -272,3 +272,69 @@ def slice_stream(n_slices: int, seed: int = 0, offered_rate: float = 1e7,
 
 def make_slice(size: int, seed: int, recipe: EventSetSpec = SLICE_RECIPE) -> EventSet:
     return make_event_set(replace(recipe, n_events=int(size)), int(seed))
+
+
+# ------------------------------------------------------ all-station events ---
+
+TRIGGER_STATIONS = (13, 14, 15)  # station numbers of trigger layers 0, 1, 2
+N_STATIONS = 16
+
+
+@dataclass
+class RawEventSet:
+    """Events with the hits of every station (input of the station filter):
+    int64 offsets[E+1], uint8 station[H], fp32 x[H], y[H]."""
+    offsets: np.ndarray
+    station: np.ndarray
+    x: np.ndarray
+    y: np.ndarray
+    layers: tuple = TRIGGER_STATIONS
+
+    @property
+    def n_events(self) -> int:
+        return len(self.offsets) - 1
+
+    @property
+    def n_hits(self) -> int:
+        return int(len(self.station))
+
+
+def embed_raw(base: EventSet, other_mean: float = 30.0, shuffle: bool = True, seed: int = 0,
+              layers=TRIGGER_STATIONS, n_stations: int = N_STATIONS, square: bool = False) -> RawEventSet:
+    """The events of ``base`` with hits on every station: the base set's hits
+    of layer l on station ``layers[l]``, and Poisson(other_mean) hits (uniform
+    in the annulus) on each other station.  ``shuffle``: the hits of an event
+    in random order (each trigger layer keeping its hits' order); otherwise
+    in detector order (grouped by station, ascending).  ``square``: the other
+    stations' hits uniform in the square [-200, 200]^2 instead (cheaper; the
+    filter never reads their coordinates).  Filtering the result on
+    ``layers`` gives back ``base`` exactly."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 0x5157]))
+    n = base.n_events
+    lc = np.diff(base.offsets.astype(np.int64)).reshape(n, 3)
+    counts = rng.poisson(other_mean, (n, n_stations)).astype(np.int64)
+    for l, s in enumerate(layers):
+        counts[:, s] = lc[:, l]
+    per_event = counts.sum(axis=1)
+    offsets = np.zeros(n + 1, np.int64)
+    np.cumsum(per_event, out=offsets[1:])
+    station = np.repeat(np.tile(np.arange(n_stations, dtype=np.uint8), n), counts.ravel())
+    total = int(offsets[-1])
+    if square:
+        x = rng.random(total, dtype=np.float32) * np.float32(400.0) - np.float32(200.0)
+        y = rng.random(total, dtype=np.float32) * np.float32(400.0) - np.float32(200.0)
+    else:
+        r = np.sqrt(rng.uniform(20.0 ** 2, 200.0 ** 2, total))
+        phi = rng.uniform(0.0, 2 * np.pi, total)
+        x = (r * np.cos(phi)).astype(np.float32)
+        y = (r * np.sin(phi)).astype(np.float32)
+    if shuffle:
+        ev = np.repeat(np.arange(n, dtype=np.int64), per_event)
+        perm = np.lexsort((rng.random(total), ev))
+        station = station[perm]
+    base_layer = np.repeat(np.tile(np.arange(3), n), lc.ravel())
+    for l, s in enumerate(layers):
+        sel = station == s
+        x[sel] = base.x[base_layer == l]
+        y[sel] = base.y[base_layer == l]
+    return RawEventSet(offsets, station, x, y, tuple(layers))

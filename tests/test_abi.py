@@ -12,7 +12,7 @@ import pytest
 from paper_1810_11966_amd import build, trig
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("trig.h", "trig_probe.h", "trig_serve.h")]
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("trig.h", "trig_probe.h", "trig_serve.h", "trig_filter.h")]
 
 
 @pytest.fixture(scope="module")
