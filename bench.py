@@ -74,6 +74,8 @@ def parse():
                     help="timeslices of the serving leg (0 = skip it)")
     ap.add_argument("--serve-load", type=float, default=1e7, help="offered load of the serving leg, events/s")
     ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--filter-events", type=int, default=100_000,
+                    help="events of the station-filter leg (0: skip it)")
     return ap.parse_args()
 
 
@@ -259,6 +261,48 @@ def cpu_baseline(s, test, target_s):
                       f"off), {threads} threads, compute only, {dt:.2f} s"}, counts
 
 
+def filter_leg(n_events, reps=20, seed=0):
+    """Trigger-station filtering (include/trig_filter.h) on events with about
+    5000 hits on 16 stations in detector order (the trigger layers are three
+    of them, with the 1M-event workload's Poisson(30) hits each): the time of
+    one call (three kernels) on the current stream, bit-exact against the
+    embedded trigger-layer events, and HBM bytes per call against 8 TB/s."""
+    import torch
+    from paper_1810_11966_amd import filter as F
+    from paper_1810_11966_amd import synth
+    base = synth.make_event_set(synth.MEDIUM_1M, n_events=n_events)
+    raw = synth.embed_raw(base, other_mean=378.0, shuffle=False, square=True, seed=seed)
+    d = torch.device("cuda:0")
+    t = [torch.from_numpy(a).to(d) for a in (raw.offsets, raw.station, raw.x, raw.y)]
+    ws = torch.empty(F.workspace_bytes(raw.n_events), dtype=torch.uint8, device=d)
+    r = None
+    for _ in range(3):
+        r = F.filter_stations(*t, raw.layers, base.n_hits, workspace=ws)
+    torch.cuda.synchronize()
+    if not (np.array_equal(r.layer_offsets.cpu().numpy(), base.offsets)
+            and np.array_equal(r.x.cpu().numpy(), base.x) and np.array_equal(r.y.cpu().numpy(), base.y)
+            and int(r.status.cpu()[0]) == 0):
+        print("bench.py: the station filter's output differs from the embedded events", file=sys.stderr)
+        sys.exit(1)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        F.filter_stations(*t, raw.layers, base.n_hits, workspace=ws)
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    # offsets in (8 B/event), station numbers (1 B/hit), x and y of trigger hits in and out (16 B/hit),
+    # offsets out (12 B/event)
+    nbytes = 20 * raw.n_events + raw.n_hits + 16 * base.n_hits
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"workload": f"{raw.n_events} events, {raw.n_hits} hits on 16 stations in detector order "
+                        f"({raw.n_hits / raw.n_events:.0f} per event), {base.n_hits} of them on the trigger layers",
+            "ms": ms, "events_per_s": raw.n_events / (ms * 1e-3), "bit_exact": True,
+            "roofline": {"kernel": "k_filter_count + k_filter_scan + k_filter_scatter", "bound": "hbm",
+                         "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
+                         "algorithmic_bytes": nbytes}}
+
+
 def main():
     args = parse()
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -357,6 +401,13 @@ def main():
         log(f"[bench] serving: p50 {serving['p50_ms']:.2f} ms, p99 {serving['p99_ms']:.2f} ms, "
             f"{serving['events_per_s']:.4g} events/s")
 
+    filt = None
+    if args.filter_events > 0 and not args.only_form:
+        log(f"[bench] station filter leg: {args.filter_events} events")
+        filt = filter_leg(args.filter_events)
+        log(f"[bench] filter: {filt['ms']:.3f} ms, {filt['events_per_s']:.4g} events/s, "
+            f"{filt['roofline']['achieved']:.0f} GB/s")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
@@ -392,6 +443,7 @@ def main():
         "forms": forms,
         "p99_slice_latency_ms": serving["p99_ms"] if serving else None,
         "serving": serving,
+        "station_filter": filt,
         **extra,
     }
     print(json.dumps(out), flush=True)

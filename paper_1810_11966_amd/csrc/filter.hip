@@ -6,7 +6,7 @@
 //
 // Partition: a workgroup of 4 waves owns kFilterEvents consecutive events;
 // wave w takes events w, w + 4, ...  A wave reads an event's station numbers
-// four per lane (one 32-bit load of 4 consecutive hits; 256 hits per step),
+// 32 per lane (two 16-byte loads of consecutive hits, 2048 hits per step),
 // so the hits of lane L precede those of lane L + 1 in a step.  Counts come
 // from wave sums; in the scatter, a hit's rank in its layer is the exclusive
 // prefix over lanes of the per-lane counts plus the count of the lane's
@@ -24,7 +24,7 @@ namespace {
 
 constexpr int kFilterThreads = 256;
 constexpr int kFilterWaves = kFilterThreads / trig::kWave;
-constexpr int kFilterEvents = 64;  // events per workgroup (one per lane of a wave in the block scan)
+constexpr int kFilterEvents = 32;  // events per workgroup (at most one per lane of a wave in the block scan)
 
 struct Range {
     int64_t a, b;
@@ -39,34 +39,66 @@ __device__ __forceinline__ Range event_range(const int64_t* __restrict__ off, in
     return r;
 }
 
-// Station numbers of hits h0 .. h0 + 3 (h0 a multiple of 4 when vec), 0xFF
-// bytes where a hit is past the array; the caller masks hits outside the
-// event.  A padding byte can equal a trigger layer only if the layer number
-// is 255; the event mask excludes those hits anyway.
-__device__ __forceinline__ uint32_t station_word(const uint8_t* __restrict__ st, int64_t h0, int64_t n_hits,
-                                                 bool vec) {
-    if (vec && h0 + 3 < n_hits) return *reinterpret_cast<const uint32_t*>(st + h0);
-    uint32_t w = 0xFFFFFFFFu;
-    for (int k = 0; k < 4; ++k)
-        if (h0 + k < n_hits) w = (w & ~(0xFFu << (8 * k))) | ((uint32_t)st[h0 + k] << (8 * k));
-    return w;
-}
+// Hits per lane and step: a lane reads kLaneHits consecutive station numbers
+// (two 16-byte loads, both in flight at once), a wave kLaneHits * 64.
+constexpr int kLaneHits = 32;
+constexpr int64_t kStepHits = (int64_t)kLaneHits * trig::kWave;
 
-// Per lane: which of its four hits (bits 0..3) belong to layer l, for l = 0, 1, 2.
+typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+
+// Station numbers of hits h0 .. h0 + 31 (h0 a multiple of 16 when vec) as 8
+// words of 4; 0xFF bytes where a hit is past the array (the caller masks
+// hits outside the event, so a padding byte never counts).
+struct LaneStations {
+    uint32_t w[kLaneHits / 4];
+    __device__ __forceinline__ void load(const uint8_t* __restrict__ st, int64_t h0, int64_t n_hits, bool vec) {
+        if (vec && h0 + kLaneHits <= n_hits) {
+            const u32x4 a = *reinterpret_cast<const u32x4*>(st + h0);
+            const u32x4 b = *reinterpret_cast<const u32x4*>(st + h0 + 16);
+            w[0] = a.x; w[1] = a.y; w[2] = a.z; w[3] = a.w;
+            w[4] = b.x; w[5] = b.y; w[6] = b.z; w[7] = b.w;
+            return;
+        }
+#pragma unroll
+        for (int q = 0; q < kLaneHits / 4; ++q) {
+            uint32_t v = 0xFFFFFFFFu;
+            for (int k = 0; k < 4; ++k) {
+                const int64_t h = h0 + 4 * q + k;
+                if (h < n_hits) v = (v & ~(0xFFu << (8 * k))) | ((uint32_t)st[h] << (8 * k));
+            }
+            w[q] = v;
+        }
+    }
+};
+
+// Per lane: which of its kLaneHits hits (bit j = hit h0 + j) belong to trigger
+// layer l, for l = 0, 1, 2, among the hits in [a, b).
 struct LaneMatch {
     uint32_t m[3];
 };
 
-__device__ __forceinline__ LaneMatch match_word(uint32_t w, int64_t h0, int64_t a, int64_t b, uint32_t layers) {
+__device__ __forceinline__ LaneMatch match_lane(const LaneStations& s, int64_t h0, int64_t a, int64_t b,
+                                                 uint32_t layers) {
+    // hits of the event: bits [lo, hi) of the lane's window
+    const int64_t lo = a - h0 > 0 ? a - h0 : 0, hi = b - h0 < kLaneHits ? b - h0 : kLaneHits;
+    uint32_t in = 0;
+    if (hi > lo) {
+        const uint32_t up = hi >= 32 ? 0xFFFFFFFFu : ((1u << hi) - 1u);
+        in = up & ~((1u << lo) - 1u);
+    }
     LaneMatch r{{0u, 0u, 0u}};
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const int64_t h = h0 + k;
-        const uint32_t s = (w >> (8 * k)) & 0xFFu;
-        const bool in = h >= a && h < b;
+    for (int q = 0; q < kLaneHits / 4; ++q) {
 #pragma unroll
-        for (int l = 0; l < 3; ++l) r.m[l] |= (uint32_t)(in && s == ((layers >> (8 * l)) & 0xFFu)) << k;
+        for (int k = 0; k < 4; ++k) {
+            const uint32_t st = (s.w[q] >> (8 * k)) & 0xFFu;
+#pragma unroll
+            for (int l = 0; l < 3; ++l)
+                r.m[l] |= (uint32_t)(st == ((layers >> (8 * l)) & 0xFFu)) << (4 * q + k);
+        }
     }
+#pragma unroll
+    for (int l = 0; l < 3; ++l) r.m[l] &= in;
     return r;
 }
 
@@ -87,11 +119,18 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_count(const int64_t* 
         const Range r = event_range(off, e, n_hits);
         uint32_t c[3] = {0u, 0u, 0u};
         if (r.ok) {
-            for (int64_t base = r.a & ~(int64_t)3; base < r.b; base += 4 * trig::kWave) {
-                const int64_t h0 = base + 4 * lane;
-                const LaneMatch m = match_word(station_word(st, h0, n_hits, vec != 0), h0, r.a, r.b, layers);
+            // double-buffered: the next step's station numbers are in flight
+            // while this step's are matched
+            int64_t base = r.a & ~(int64_t)15;
+            LaneStations cur, nxt;
+            cur.load(st, base + (int64_t)kLaneHits * lane, n_hits, vec != 0);
+            for (; base < r.b; base += kStepHits) {
+                const int64_t h0 = base + (int64_t)kLaneHits * lane;
+                if (base + kStepHits < r.b) nxt.load(st, h0 + kStepHits, n_hits, vec != 0);  // wave-uniform
+                const LaneMatch m = match_lane(cur, h0, r.a, r.b, layers);
 #pragma unroll
                 for (int l = 0; l < 3; ++l) c[l] += (uint32_t)__builtin_popcount(m.m[l]);
+                cur = nxt;
             }
         } else if (lane == 0 && status) {
             atomicOr(status, TRIG_FILTER_MALFORMED);
@@ -143,19 +182,22 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
     const int32_t* __restrict__ counts, const int64_t* __restrict__ partials, int n_blocks, int32_t capacity,
     int32_t* __restrict__ out_off, float* __restrict__ out_x, float* __restrict__ out_y, uint32_t* status) {
     __shared__ int64_t ev_start[kFilterEvents];
+    __shared__ uint16_t lists[kFilterWaves][kStepHits];  // per wave: the step's matched hits
     const int w = trig::uniform_i((int)(threadIdx.x / trig::kWave));
+    uint16_t* list = lists[w];
     const int lane = (int)trig::lane_id();
     const int e_first = (int)blockIdx.x * kFilterEvents;
     const int64_t cap = capacity;
     if (w == 0) {
         // Starts of the workgroup's events: its base plus an exclusive scan of
         // the events' totals, one event per lane.
+        static_assert(kFilterEvents <= trig::kWave, "one event per lane");
         const int e = e_first + lane;
         int32_t tot = 0;
-        if (e < n_events)
+        if (lane < kFilterEvents && e < n_events)
             tot = counts[3 * (int64_t)e] + counts[3 * (int64_t)e + 1] + counts[3 * (int64_t)e + 2];
         const int32_t excl = trig::wave_inclusive_sum(tot) - tot;
-        ev_start[lane] = partials[blockIdx.x] + excl;
+        if (lane < kFilterEvents) ev_start[lane] = partials[blockIdx.x] + excl;
     }
     if ((int)blockIdx.x == n_blocks - 1 && threadIdx.x == 0) {
         const int64_t total = partials[n_blocks];
@@ -177,30 +219,46 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
         }
         const Range r = event_range(off, e, n_hits);
         if (!r.ok) continue;
-        for (int64_t base = r.a & ~(int64_t)3; base < r.b; base += 4 * trig::kWave) {
-            const int64_t h0 = base + 4 * lane;
-            const LaneMatch m = match_word(station_word(st, h0, n_hits, vec != 0), h0, r.a, r.b, layers);
-            int64_t pos[3];
+        int64_t base = r.a & ~(int64_t)15;
+        LaneStations cur, nxt;
+        cur.load(st, base + (int64_t)kLaneHits * lane, n_hits, vec != 0);
+        for (; base < r.b; base += kStepHits) {
+            const int64_t h0 = base + (int64_t)kLaneHits * lane;
+            if (base + kStepHits < r.b) nxt.load(st, h0 + kStepHits, n_hits, vec != 0);  // wave-uniform
+            const LaneMatch m = match_lane(cur, h0, r.a, r.b, layers);
+            cur = nxt;
+            // Each matched hit's place in the step's list (layer 0's hits, then
+            // layer 1's, then layer 2's, each in input order): entry =
+            // layer << 11 | offset in the step.  Then every lane copies entries
+            // lane, lane + 64, ...: one coalesced round trip per 64 hits,
+            // however the trigger hits are spread over the lanes.
+            int32_t at = 0;
+            int32_t list_off[3], tot[3];
 #pragma unroll
             for (int l = 0; l < 3; ++l) {
                 const int n = __builtin_popcount(m.m[l]);
                 const int incl = trig::wave_inclusive_sum(n);
-                pos[l] = s[l] + (incl - n);
-                s[l] += __builtin_amdgcn_readlane(incl, 63);
+                tot[l] = __builtin_amdgcn_readlane(incl, 63);
+                list_off[l] = at;
+                int32_t q = at + (incl - n);
+                for (uint32_t bits = m.m[l]; bits; bits &= bits - 1u)
+                    list[q++] = (uint16_t)((l << 11) | (kLaneHits * lane + __builtin_ctz(bits)));
+                at += tot[l];
             }
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-#pragma unroll
-                for (int l = 0; l < 3; ++l) {
-                    if ((m.m[l] >> k) & 1u) {
-                        const int64_t p = pos[l]++;
-                        if (p >= 0 && p < cap) {  // positions past an int32 block prefix are never written
-                            out_x[p] = x[h0 + k];
-                            out_y[p] = y[h0 + k];
-                        }
-                    }
+            trig::wave_lds_sync();
+            for (int32_t i = lane; i < at; i += trig::kWave) {
+                const uint32_t entry = list[i];
+                const int l = (int)(entry >> 11);
+                const int64_t h = base + (entry & 2047u);
+                const int64_t p = s[l] + (i - (l == 0 ? list_off[0] : (l == 1 ? list_off[1] : list_off[2])));
+                if (p >= 0 && p < cap) {  // positions past an int32 block prefix are never written
+                    out_x[p] = x[h];
+                    out_y[p] = y[h];
                 }
             }
+            trig::wave_lds_sync();  // the next step rewrites the list
+#pragma unroll
+            for (int l = 0; l < 3; ++l) s[l] += tot[l];
         }
     }
 }
@@ -241,7 +299,7 @@ int trig_filter_stations(const trig_raw_events* ev, const trig_filter_params* p,
     auto* partials =
         reinterpret_cast<int64_t*>(static_cast<char*>(p->workspace) + align256(sizeof(int32_t) * 3 * (size_t)n));
     const uint32_t layers = (uint32_t)p->layers[0] | ((uint32_t)p->layers[1] << 8) | ((uint32_t)p->layers[2] << 16);
-    const int vec = (reinterpret_cast<uintptr_t>(ev->station) & 3) == 0;
+    const int vec = (reinterpret_cast<uintptr_t>(ev->station) & 15) == 0;
     hipLaunchKernelGGL(k_filter_count, dim3(nb), dim3(kFilterThreads), 0, s, ev->offsets, n, ev->n_hits,
                        ev->station, layers, vec, counts, partials, p->out_status);
     if (hipGetLastError() != hipSuccess) return TRIG_EHIP;
