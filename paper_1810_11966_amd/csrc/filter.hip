@@ -77,6 +77,18 @@ struct LaneMatch {
     uint32_t m[3];
 };
 
+// Bytes of w equal to the byte v (v4 = v * 0x01010101): bit k set for byte k.
+// A byte of x = w ^ v4 is zero where they are equal; adding 0x7F to each
+// byte's low seven bits carries into its bit 7 exactly when they are not all
+// zero (never into the next byte), so bit 7 of ~(that | x) marks the zero
+// bytes, and one multiply gathers the four marks into bits 21..24.
+__device__ __forceinline__ uint32_t eq_bytes(uint32_t w, uint32_t v4) {
+    const uint32_t x = w ^ v4;
+    const uint32_t t = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;
+    const uint32_t z = ~t & 0x80808080u;
+    return (((z >> 7) * 0x00204081u) >> 21) & 0xFu;
+}
+
 __device__ __forceinline__ LaneMatch match_lane(const LaneStations& s, int64_t h0, int64_t a, int64_t b,
                                                  uint32_t layers) {
     // hits of the event: bits [lo, hi) of the lane's window
@@ -88,14 +100,10 @@ __device__ __forceinline__ LaneMatch match_lane(const LaneStations& s, int64_t h
     }
     LaneMatch r{{0u, 0u, 0u}};
 #pragma unroll
-    for (int q = 0; q < kLaneHits / 4; ++q) {
+    for (int l = 0; l < 3; ++l) {
+        const uint32_t v4 = ((layers >> (8 * l)) & 0xFFu) * 0x01010101u;
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            const uint32_t st = (s.w[q] >> (8 * k)) & 0xFFu;
-#pragma unroll
-            for (int l = 0; l < 3; ++l)
-                r.m[l] |= (uint32_t)(st == ((layers >> (8 * l)) & 0xFFu)) << (4 * q + k);
-        }
+        for (int q = 0; q < kLaneHits / 4; ++q) r.m[l] |= eq_bytes(s.w[q], v4) << (4 * q);
     }
 #pragma unroll
     for (int l = 0; l < 3; ++l) r.m[l] &= in;

@@ -44,3 +44,25 @@ def test_malformed_ranges_keep_no_hit():
         bad = [e for e in range(3) if not (0 <= off[e] <= off[e + 1] <= 6)]
         for e in bad:
             assert lo[3 * e] == lo[3 * e + 3]
+
+
+def test_swar_byte_match_identity():
+    """The filter kernels' byte match: for a 32-bit word w and a byte v,
+    (((~(((x & 0x7F7F7F7F) + 0x7F7F7F7F) | x) & 0x80808080) >> 7) * 0x204081
+    >> 21) & 15, x = w ^ (v * 0x01010101), has bit k set iff byte k of w is v."""
+    rng = np.random.default_rng(9)
+    words = np.concatenate([rng.integers(0, 2**32, 200000, dtype=np.uint64),
+                            np.array([0, 0xFFFFFFFF, 0x80808080, 0x7F7F7F7F, 0x01010101, 0x0D0E0F10,
+                                      0xFF0D00FF], np.uint64)])
+    m32 = np.uint64(0xFFFFFFFF)
+    for v in (0, 1, 13, 14, 15, 127, 128, 255):
+        # also words built from v and its neighbours, the likely borrow cases
+        near = rng.choice(np.array([v, (v + 1) % 256, (v - 1) % 256, v ^ 0x80], np.uint64), (50000, 4))
+        w = np.concatenate([words, near[:, 0] | near[:, 1] << 8 | near[:, 2] << 16 | near[:, 3] << 24])
+        x = w ^ np.uint64(v * 0x01010101)
+        t = (((x & np.uint64(0x7F7F7F7F)) + np.uint64(0x7F7F7F7F)) | x) & m32
+        z = (~t & m32) & np.uint64(0x80808080)
+        got = ((((z >> np.uint64(7)) * np.uint64(0x00204081)) & m32) >> np.uint64(21)) & np.uint64(15)
+        want = sum(((((w >> np.uint64(8 * k)) & np.uint64(255)) == v).astype(np.uint64) << np.uint64(k))
+                   for k in range(4))
+        assert np.array_equal(got, want), v
