@@ -161,27 +161,31 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_count(const int64_t* 
 }
 
 // In-place exclusive scan of partials[0..n) (int64); partials[n] = total.
-// One workgroup, kFilterThreads values per step.
+// One workgroup: thread t sums its run of ceil(n / threads) consecutive
+// partials, one block scan of those sums (Hillis-Steele in LDS), then each
+// thread rewrites its run from its prefix.
 __global__ __launch_bounds__(kFilterThreads) void k_filter_scan(int64_t* partials, int n) {
     __shared__ int64_t buf[kFilterThreads];
-    int64_t carry = 0;
     const int t = (int)threadIdx.x;
-    for (int base = 0; base < n; base += kFilterThreads) {
-        const int i = base + t;
-        const int64_t v = i < n ? partials[i] : 0;
-        buf[t] = v;
+    const int per = (n + kFilterThreads - 1) / kFilterThreads;
+    const int lo = min(n, t * per), hi = min(n, lo + per);
+    int64_t sum = 0;
+    for (int i = lo; i < hi; ++i) sum += partials[i];
+    buf[t] = sum;
+    __syncthreads();
+    for (int d = 1; d < kFilterThreads; d <<= 1) {  // inclusive
+        const int64_t o = t >= d ? buf[t - d] : 0;
         __syncthreads();
-        for (int d = 1; d < kFilterThreads; d <<= 1) {  // inclusive Hillis-Steele scan
-            const int64_t o = t >= d ? buf[t - d] : 0;
-            __syncthreads();
-            buf[t] += o;
-            __syncthreads();
-        }
-        if (i < n) partials[i] = carry + buf[t] - v;
-        carry += buf[kFilterThreads - 1];
+        buf[t] += o;
         __syncthreads();
     }
-    if (t == 0) partials[n] = carry;
+    int64_t run = buf[t] - sum;  // exclusive prefix of this run
+    for (int i = lo; i < hi; ++i) {
+        const int64_t v = partials[i];
+        partials[i] = run;
+        run += v;
+    }
+    if (t == kFilterThreads - 1) partials[n] = buf[t];
 }
 
 __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
