@@ -308,7 +308,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU: the selection is per event and shards trivially by "
-              "event range, and this build has no multi-GPU path; run with --gpus 1.", file=sys.stderr)
+              "event range, and the library has no multi-GPU path; run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch
