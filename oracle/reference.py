@@ -6,31 +6,42 @@ code with it.
 
 Contents
   * ``OracleConfig``             the parameters of the selection.
-  * ``select``                   the plain C oracle (trig_oracle.c) over a batch
-                                 of events: per-event passing-triplet counts,
-                                 accept flags, error bits; fp32 decisions.
+  * ``select``                   the plain C oracle (trig_oracle.c,
+                                 ``trig_select_ref``) over a batch of events:
+                                 per-event passing-triplet counts, accept
+                                 flags, error bits; fp32 decisions.
   * ``select_numpy``             an independent NumPy float32 implementation of
                                  the same fp32 decisions (vectorised per event).
+  * ``msd_disagreements``        per event, the triplets whose decision differs
+                                 between the two evaluation orders of the fit.
   * ``fit_msd_exact``            the paper's fit through the vertex in exact
                                  rational arithmetic (``fractions.Fraction``).
   * ``fit_msd_f64``              the same fit in float64 (vectorised).
-  * ``fp32_error_bound``         a rigorous bound on |Q_fp32 - Q_exact| for the
-                                 basis-form fp32 evaluation, used by the pins.
+  * ``fp32_fit_error_bound``     a rigorous bound on |Q_fp32 - Q_exact| for the
+                                 default (fit written out) evaluation.
+  * ``fp32_error_bound``         the same for the basis-form evaluation.
   * ``accepted_ids``             ascending ids of accepted events.
   * ``filter_stations``          trigger-station filtering, the step before the
                                  selection: per event the hits of the three
                                  trigger layers, in input order.
 
-The fp32 decision contract, MSD test (default), per plane c in {x, y} with the
-hits c_i, c_j, c_k of layers 0, 1, 2 (every line one rounding to binary32):
+The fp32 decision contract, MSD test (default): the fit of Sec. 3.2 step 2
+written out, per plane c in {x, y} with the hits c_i, c_j, c_k of layers 0, 1,
+2 (every line one rounding to binary32 per operation, left to right):
+    Szz = (z0*z0 + z1*z1) + z2*z2,   w = f32(1 / f64(Szz))
+    m   = ((c_i*z0 + c_j*z1) + c_k*z2) * w       slope of c = m z
+    r_l = c_l - m*z_l                             residuals, l = 0, 1, 2
+    Q   = (r0*r0 + r1*r1) + r2*r2
+    pass_c  <=>  Q / ndf <= T_c                  (fp32 division, equality passes)
+
+MSD_BASIS test: the same Q evaluated in an orthonormal basis (u, v) of the
+plane orthogonal to (z0, z1, z2):
     a   = U0*c_i + U1*c_j                      (two products, then one sum)
     b   = (V0*c_i + V1*c_j) + V2*c_k
     Q   = a*a + b*b
-    pass_c  <=>  Q / ndf <= T_c                (fp32 division, equality passes)
 with U0 = f32(z1/n01), U1 = f32(-z0/n01), V0 = f32(z0 z2/d), V1 = f32(z1 z2/d),
 V2 = f32(-s01/d), s01 = z0^2 + z1^2, n01 = sqrt(s01), d = n01 * sqrt(s01 + z2^2),
-all of it in float64 before the final rounding.  (u, v) is an orthonormal basis
-of the plane orthogonal to (z0, z1, z2), so that in exact arithmetic
+all of it in float64 before the final rounding.  In exact arithmetic
 a^2 + b^2 equals the residual sum of squares of the least-squares line
 c = m z through the vertex.
 """
@@ -49,7 +60,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "trig_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
 
-TESTS = {"msd": 0, "window": 1, "msd_fit": 2}
+TESTS = {"msd": 0, "window": 1, "msd_basis": 2}
 INT32_MAX = 2 ** 31 - 1
 
 
@@ -107,11 +118,15 @@ def _load():
         if not os.path.exists(LIB):
             build()
         lib = ctypes.CDLL(LIB)
-        lib.oracle_select.restype = ctypes.c_double
-        lib.oracle_select.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
+        lib.trig_select_ref.restype = ctypes.c_double
+        lib.trig_select_ref.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Cfg),
                                       ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.POINTER(ctypes.c_uint32), ctypes.c_int32]
+        lib.trig_ref_msd_disagreements.restype = ctypes.c_int64
+        lib.trig_ref_msd_disagreements.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
+                                                   ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                                   ctypes.POINTER(_Cfg), ctypes.c_void_p]
         lib.oracle_triplet_msd.restype = ctypes.c_float
         lib.oracle_triplet_msd.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_float,
                                            ctypes.c_float, ctypes.c_float]
@@ -140,15 +155,44 @@ def select(offsets, x, y, cfg: OracleConfig = OracleConfig(), n_threads: int = 1
     accept = np.zeros(n_ev, np.uint8)
     st = ctypes.c_uint32(0)
     c = _to_c(cfg)
-    dt = lib.oracle_select(n_ev, _ptr(off), len(xs), _ptr(xs), _ptr(ys), ctypes.byref(c),
+    dt = lib.trig_select_ref(n_ev, _ptr(off), len(xs), _ptr(xs), _ptr(ys), ctypes.byref(c),
                            _ptr(counts), _ptr(accept), ctypes.byref(st), int(n_threads))
     if dt < 0:
-        raise ValueError("oracle_select rejected its arguments")
+        raise ValueError("trig_select_ref rejected its arguments")
     return counts, accept, int(st.value), float(dt)
 
 
 def select_set(evset, cfg: OracleConfig = OracleConfig(), n_threads: int = 1):
     return select(evset.offsets, evset.x, evset.y, cfg, n_threads)
+
+
+def msd_disagreements(offsets, x, y, cfg: OracleConfig = OracleConfig(), n_threads: int = 1):
+    """Per event, the number of triplets whose decision differs between the
+    MSD (fit written out) and MSD_BASIS evaluations of the fit, both planes
+    (cfg.test is ignored).  int32[E]; malformed events count 0."""
+    from concurrent.futures import ThreadPoolExecutor
+    lib = _load()
+    off = np.ascontiguousarray(offsets, dtype=np.int32)
+    xs = np.ascontiguousarray(x, dtype=np.float32)
+    ys = np.ascontiguousarray(y, dtype=np.float32)
+    n_ev = (len(off) - 1) // 3
+    out = np.zeros(n_ev, np.int32)
+    c = _to_c(cfg)
+    n_threads = max(1, int(n_threads))
+    bounds = np.linspace(0, n_ev, 4 * n_threads + 1).astype(np.int64)
+
+    def run(k):
+        e0, e1 = int(bounds[k]), int(bounds[k + 1])
+        if e1 > e0:
+            part = out[e0:e1]
+            r = lib.trig_ref_msd_disagreements(e0, e1, _ptr(off), len(xs), _ptr(xs), _ptr(ys), ctypes.byref(c),
+                                               part.ctypes.data_as(ctypes.c_void_p))
+            if r < 0:
+                raise ValueError("trig_ref_msd_disagreements rejected its arguments")
+
+    with ThreadPoolExecutor(n_threads) as ex:
+        list(ex.map(run, range(len(bounds) - 1)))
+    return out
 
 
 def triplet_msd_c(cfg: OracleConfig, ci: float, cj: float, ck: float) -> float:
@@ -188,13 +232,13 @@ def _plane_pass_np(ci, cj, ck, cfg: OracleConfig, plane: int):
     """Boolean [n0, n1, n2] array of plane decisions for one event."""
     f32 = np.float32
     T = f32(cfg.msd_max[plane]) if cfg.test != "window" else None
-    if cfg.test == "msd":
+    if cfg.test == "msd_basis":
         U0, U1, V0, V1, V2 = basis_f32(cfg.z)
         a = (U0 * ci)[:, None] + (U1 * cj)[None, :]
         b = ((V0 * ci)[:, None] + (V1 * cj)[None, :])[:, :, None] + (V2 * ck)[None, None, :]
         q = (a * a)[:, :, None] + b * b
         return (q / f32(cfg.ndf)) <= T
-    if cfg.test == "msd_fit":
+    if cfg.test == "msd":
         z = [f32(v) for v in cfg.z]
         szz = (z[0] * z[0] + z[1] * z[1]) + z[2] * z[2]
         w = f32(1.0 / float(szz))
@@ -266,6 +310,54 @@ def fit_msd_f64(ci, cj, ck, z, ndf):
     m = (ci * z0 + cj * z1 + ck * z2) / (z0 * z0 + z1 * z1 + z2 * z2)
     q = (ci - m * z0) ** 2 + (cj - m * z1) ** 2 + (ck - m * z2) ** 2
     return q / ndf
+
+
+def fp32_fit_error_bound(ci, cj, ck, z):
+    """Upper bound on |Q_fp32 - Q_exact| for the default evaluation (the fit
+    written out), before the division by ndf, vectorised over triplets of
+    finite binary32 inputs whose intermediate results stay finite.
+
+    Standard model: every operation returns x(1 + d), |d| <= u = 2^-24 (an
+    intermediate that falls into the subnormal range adds at most 2^-150
+    absolute; the result carries a slack far above that).  With
+    P = sum c_l z_l, A = sum |c_l| z_l, S = sum z_l^2 (exact, on the binary32
+    z), g3 = 3u / (1 - 3u):
+      s = (c_i z0 + c_j z1) + c_k z2:   |s - P| <= g3 A
+      w = (1/S)(1 + e_w), e_w measured on the binary32 w of the contract
+      m = s w (1 + d):                   |m - m*| <= dm =
+            [g3 A (1 + e_w)(1 + u) + |P| (e_w + u + e_w u)] / S
+      t_l = m z_l (1 + d), r_l = (c_l - t_l)(1 + d):
+            |r_l - r*_l| <= dl = dm z_l + u |m| z_l + u |c_l - t_l|,
+            |m| <= |m*| + dm,  |c_l - t_l| <= |r*_l| + dm z_l + u |m| z_l
+      Q = (r0^2 + r1^2) + r2^2, three roundings on each term:
+            |Q - sum r_l^2| <= g3 sum r_l^2
+    hence |Q - Q*| <= sum_l (2 |r*_l| dl + dl^2) + g3 sum_l (|r*_l| + dl)^2,
+    with r*_l = c_l - m* z_l the exact residuals.  Evaluated in float64 with
+    a relative slack of 1e-6 and an absolute one of 1e-30."""
+    u = 2.0 ** -24
+    g3 = 3 * u / (1 - 3 * u)
+    zf = [float(np.float32(v)) for v in z]
+    z32 = [np.float32(v) for v in z]
+    szz32 = (z32[0] * z32[0] + z32[1] * z32[1]) + z32[2] * z32[2]
+    w32 = np.float32(1.0 / float(szz32))
+    S_exact = sum(Fraction(v) ** 2 for v in zf)
+    e_w = float(abs(Fraction(float(w32)) * S_exact - 1))
+    S = float(S_exact)
+    c = [np.asarray(v, dtype=np.float32).astype(np.float64) for v in (ci, cj, ck)]
+    P = sum(cl * zl for cl, zl in zip(c, zf))
+    A = sum(np.abs(cl) * zl for cl, zl in zip(c, zf))
+    mstar = P / S
+    dm = (g3 * A * (1 + e_w) * (1 + u) + np.abs(P) * (e_w + u + e_w * u)) / S
+    mabs = np.abs(mstar) + dm
+    total = 0.0
+    sq = 0.0
+    for cl, zl in zip(c, zf):
+        rstar = cl - mstar * zl
+        ct = np.abs(rstar) + dm * zl + u * mabs * zl
+        dl = dm * zl + u * mabs * zl + u * ct
+        total = total + 2 * np.abs(rstar) * dl + dl * dl
+        sq = sq + (np.abs(rstar) + dl) ** 2
+    return (total + g3 * sq) * (1 + 1e-6) + 1e-30
 
 
 def fp32_error_bound(ci, cj, ck, z):

@@ -24,14 +24,17 @@
  * of the same fit lives in reference.py and pins these decisions.
  *
  * Three tests are provided:
- *   MSD (default)  the fit's residual sum of squares Q evaluated as the squared
- *                  length of the measurement vector's component orthogonal to
- *                  the layer vector z = (z0, z1, z2), in the orthonormal basis
- *                  (u, v) of that plane with u = (z1, -z0, 0)/|(z0, z1)| and
+ *   MSD (default)  the fit of Sec. 3.2 step 2 written out: slope
+ *                  m = sum(c z) / sum(z^2) through the vertex (the division
+ *                  taken as a product with w = 1 / sum(z^2), rounded once),
+ *                  residuals r_l = c_l - m z_l, Q = sum r_l^2.
+ *   MSD_BASIS      the same fit's Q evaluated as the squared length of the
+ *                  measurement vector's component orthogonal to the layer
+ *                  vector z = (z0, z1, z2), in the orthonormal basis (u, v)
+ *                  of that plane with u = (z1, -z0, 0)/|(z0, z1)| and
  *                  v = (z0 z2, z1 z2, -(z0^2 + z1^2)) / (|(z0, z1)| |z|).
- *                  In exact arithmetic Q = min_m sum_l (c_l - m z_l)^2.
- *   MSD_FIT        the same fit written out literally: slope m = sum(c z) /
- *                  sum(z^2), residuals r_l = c_l - m z_l, Q = sum r_l^2.
+ *                  In exact arithmetic Q = min_m sum_l (c_l - m z_l)^2, the
+ *                  same number; in binary32 the two orders round differently.
  *   WINDOW         slope-window test: |c_l/z_l - c_0/z_0| < W for l = 1, 2.
  * For the MSD tests the triplet passes a plane iff fl(Q / ndf) <= T.
  */
@@ -42,7 +45,7 @@
 #include <string.h>
 #include <time.h>
 
-enum { OR_TEST_MSD = 0, OR_TEST_WINDOW = 1, OR_TEST_MSD_FIT = 2 };
+enum { OR_TEST_MSD = 0, OR_TEST_WINDOW = 1, OR_TEST_MSD_BASIS = 2 };
 
 typedef struct {
     int32_t test;
@@ -54,10 +57,10 @@ typedef struct {
 } oracle_cfg;
 
 typedef struct {
-    /* MSD (orthonormal basis of the plane orthogonal to z) */
-    float U0, U1, V0, V1, V2;
-    /* MSD_FIT */
+    /* MSD: layer positions and w = 1 / sum z^2 */
     float zf[3], w;
+    /* MSD_BASIS: orthonormal basis of the plane orthogonal to z */
+    float U0, U1, V0, V1, V2;
 } oracle_consts;
 
 static void make_consts(const oracle_cfg *c, oracle_consts *k) {
@@ -77,7 +80,7 @@ static void make_consts(const oracle_cfg *c, oracle_consts *k) {
     k->w = (float)(1.0 / (double)sz);
 }
 
-/* One plane of the MSD test, basis form. */
+/* One plane of the MSD_BASIS test. */
 static int plane_msd(float ci, float cj, float ck, const oracle_consts *k, float T, float ndf) {
     float a = k->U0 * ci + k->U1 * cj;
     float b = (k->V0 * ci + k->V1 * cj) + k->V2 * ck;
@@ -86,7 +89,7 @@ static int plane_msd(float ci, float cj, float ck, const oracle_consts *k, float
     return msd <= T;
 }
 
-/* One plane of the MSD test, fit written out. */
+/* One plane of the MSD test: the fit through the vertex written out. */
 static int plane_fit(float ci, float cj, float ck, const oracle_consts *k, float T, float ndf) {
     float p0 = ci * k->zf[0], p1 = cj * k->zf[1], p2 = ck * k->zf[2];
     float m = ((p0 + p1) + p2) * k->w;
@@ -127,12 +130,12 @@ static int32_t event_count(const oracle_cfg *c, const oracle_consts *k, const in
                 if (c->test == OR_TEST_WINDOW) {
                     pass = plane_window(x[i], x[j], x[kk], k, c->window[0]) &&
                            plane_window(y[i], y[j], y[kk], k, c->window[1]);
-                } else if (c->test == OR_TEST_MSD_FIT) {
-                    pass = plane_fit(x[i], x[j], x[kk], k, c->msd_max[0], ndf) &&
-                           plane_fit(y[i], y[j], y[kk], k, c->msd_max[1], ndf);
-                } else {
+                } else if (c->test == OR_TEST_MSD_BASIS) {
                     pass = plane_msd(x[i], x[j], x[kk], k, c->msd_max[0], ndf) &&
                            plane_msd(y[i], y[j], y[kk], k, c->msd_max[1], ndf);
+                } else {
+                    pass = plane_fit(x[i], x[j], x[kk], k, c->msd_max[0], ndf) &&
+                           plane_fit(y[i], y[j], y[kk], k, c->msd_max[1], ndf);
                 }
                 cnt += pass;
             }
@@ -184,9 +187,9 @@ static int64_t event_cost(const int32_t *off, int64_t e) {
  * compute time in seconds (thread start to join), or a negative value on bad
  * arguments.  *status receives the OR of per-event error bits (1 malformed
  * CSR range, 2 triplet count not representable in int32). */
-double oracle_select(int32_t n_events, const int32_t *off, int32_t n_hits, const float *x,
-                     const float *y, const oracle_cfg *cfg, int32_t *counts, uint8_t *accept,
-                     uint32_t *status, int32_t n_threads) {
+double trig_select_ref(int32_t n_events, const int32_t *off, int32_t n_hits, const float *x,
+                       const float *y, const oracle_cfg *cfg, int32_t *counts, uint8_t *accept,
+                       uint32_t *status, int32_t n_threads) {
     if (n_events < 0 || (n_events > 0 && (!off || !counts || !accept)) || !cfg || !status)
         return -1.0;
     if (n_threads < 1) n_threads = 1;
@@ -230,15 +233,15 @@ float oracle_triplet_msd(const oracle_cfg *cfg, float ci, float cj, float ck) {
     oracle_consts k;
     make_consts(cfg, &k);
     const float ndf = (float)cfg->ndf;
-    if (cfg->test == OR_TEST_MSD_FIT) {
-        float p0 = ci * k.zf[0], p1 = cj * k.zf[1], p2 = ck * k.zf[2];
-        float m = ((p0 + p1) + p2) * k.w;
-        float r0 = ci - m * k.zf[0], r1 = cj - m * k.zf[1], r2 = ck - m * k.zf[2];
-        return ((r0 * r0 + r1 * r1) + r2 * r2) / ndf;
+    if (cfg->test == OR_TEST_MSD_BASIS) {
+        float a = k.U0 * ci + k.U1 * cj;
+        float b = (k.V0 * ci + k.V1 * cj) + k.V2 * ck;
+        return (a * a + b * b) / ndf;
     }
-    float a = k.U0 * ci + k.U1 * cj;
-    float b = (k.V0 * ci + k.V1 * cj) + k.V2 * ck;
-    return (a * a + b * b) / ndf;
+    float p0 = ci * k.zf[0], p1 = cj * k.zf[1], p2 = ck * k.zf[2];
+    float m = ((p0 + p1) + p2) * k.w;
+    float r0 = ci - m * k.zf[0], r1 = cj - m * k.zf[1], r2 = ck - m * k.zf[2];
+    return ((r0 * r0 + r1 * r1) + r2 * r2) / ndf;
 }
 
 /* The fp32 basis constants (U0, U1, V0, V1, V2), for pin tests. */
@@ -246,4 +249,39 @@ void oracle_basis(const oracle_cfg *cfg, float out[5]) {
     oracle_consts k;
     make_consts(cfg, &k);
     out[0] = k.U0; out[1] = k.U1; out[2] = k.V0; out[3] = k.V1; out[4] = k.V2;
+}
+
+/* Triplets whose decision differs between the MSD and MSD_BASIS evaluations
+ * of the same fit (both planes; cfg->test is ignored), for events
+ * [e0, e1).  per_event[e - e0] (may be NULL) receives each event's number;
+ * malformed events and events whose triplet count int32 cannot hold count 0.
+ * Returns the total, or -1 on bad arguments.  One thread; callers split the
+ * event range. */
+int64_t trig_ref_msd_disagreements(int64_t e0, int64_t e1, const int32_t *off, int32_t n_hits,
+                                   const float *x, const float *y, const oracle_cfg *cfg,
+                                   int32_t *per_event) {
+    if (e0 < 0 || e1 < e0 || (e1 > e0 && !off) || !cfg) return -1;
+    oracle_consts k;
+    make_consts(cfg, &k);
+    const float ndf = (float)cfg->ndf;
+    int64_t total = 0;
+    for (int64_t e = e0; e < e1; ++e) {
+        int64_t o0 = off[3 * e], o1 = off[3 * e + 1], o2 = off[3 * e + 2], o3 = off[3 * e + 3];
+        int32_t d = 0;
+        int ok = 0 <= o0 && o0 <= o1 && o1 <= o2 && o2 <= o3 && o3 <= n_hits;
+        if (ok && (o3 - o2) > 0 && (o1 - o0) * (o2 - o1) > (int64_t)INT32_MAX / (o3 - o2)) ok = 0;
+        if (ok)
+            for (int64_t i = o0; i < o1; ++i)
+                for (int64_t j = o1; j < o2; ++j)
+                    for (int64_t kk = o2; kk < o3; ++kk) {
+                        int fit = plane_fit(x[i], x[j], x[kk], &k, cfg->msd_max[0], ndf) &&
+                                  plane_fit(y[i], y[j], y[kk], &k, cfg->msd_max[1], ndf);
+                        int basis = plane_msd(x[i], x[j], x[kk], &k, cfg->msd_max[0], ndf) &&
+                                    plane_msd(y[i], y[j], y[kk], &k, cfg->msd_max[1], ndf);
+                        d += fit != basis;
+                    }
+        if (per_event) per_event[e - e0] = d;
+        total += d;
+    }
+    return total;
 }

@@ -15,7 +15,7 @@ from paper_1810_11966_amd import synth
 from tests import helpers
 
 Z = (400.0, 410.0, 420.0)
-MODES = ("msd", "msd_fit", "window")
+MODES = ("msd", "msd_basis", "window")
 
 
 def cfg_for(case):
@@ -30,7 +30,7 @@ def test_golden_handbuilt_counts(oracle_lib, case):
     """Closed-form counts of hand-built events (tests/golden/handbuilt.json)."""
     s = helpers.golden_set(case)
     cfg = cfg_for(case)
-    modes = [cfg.test] if cfg.test == "window" else ["msd", "msd_fit"]
+    modes = [cfg.test] if cfg.test == "window" else ["msd", "msd_basis"]
     for mode in modes:
         c = R.OracleConfig(**{**cfg.__dict__, "test": mode})
         counts, accept, status, _ = R.select_set(s, c)
@@ -77,7 +77,7 @@ def test_exact_fit_equality_passes():
     assert q == 4
     cfg = R.OracleConfig(z=(1.0, 2.0, 2.0), msd_max=(4.0, 4.0), ndf=2)
     s = synth.from_layers([[[(3.0, 3.0)], [(0.0, 0.0)], [(0.0, 0.0)]]])
-    for mode in ("msd", "msd_fit"):
+    for mode in ("msd", "msd_basis"):
         c = R.OracleConfig(**{**cfg.__dict__, "test": mode})
         # the fp32 evaluation of this triplet is within a few ulp of 8; the
         # comparison is "<=" so a threshold of 4(1+2^-20) passes, 4(1-2^-20) fails
@@ -87,33 +87,49 @@ def test_exact_fit_equality_passes():
         assert R.select_set(s, dn)[0][0] == 0
 
 
-@pytest.mark.parametrize("mode", ["msd", "msd_fit"])
+@pytest.mark.parametrize("mode", ["msd", "msd_basis"])
 @pytest.mark.parametrize("plane_T", [0.03, 0.025])
 def test_fp32_msd_within_bound_of_exact_fit(oracle_lib, mode, plane_T):
     """The oracle's fp32 MSD of random and near-threshold triplets stays within
-    a rigorous error bound of the exact fit, and its decision equals the exact
-    decision outside that band."""
+    a rigorous error bound of the exact fit (the bound of its own evaluation
+    order), and its decision equals the exact decision outside that band."""
     ci, cj, ck = helpers.near_threshold_triplets(600, seed=11, plane_T=plane_T, rel=3e-3)
     rng = np.random.default_rng(12)
     r = rng.uniform(-200, 200, (200, 3)).astype(np.float32)
     ci, cj, ck = (np.concatenate([a, r[:, i]]) for i, a in enumerate((ci, cj, ck)))
     cfg = R.OracleConfig(test=mode, msd_max=(plane_T, plane_T))
-    bound = R.fp32_error_bound(ci, cj, ck, Z)
+    bound = (R.fp32_fit_error_bound if mode == "msd" else R.fp32_error_bound)(ci, cj, ck, Z)
     T32 = Fraction(float(np.float32(plane_T)))
     decided = 0
     for t in range(len(ci)):
         exact = R.fit_msd_exact(ci[t], cj[t], ck[t], Z, 2)
         got = R.triplet_msd_c(cfg, ci[t], cj[t], ck[t])
-        if mode == "msd":
-            assert abs(Fraction(got) * 2 - exact * 2) <= Fraction(float(bound[t])) * (1 + Fraction(1, 10 ** 6)) \
-                + Fraction(got) * 2 * Fraction(1, 2 ** 23)
-        else:
-            assert abs(float(exact) - got) <= 1e-4 * max(1.0, float(exact))
+        # fl(Q / 2) = Q / 2 exactly or within one rounding of it
+        assert abs(Fraction(got) * 2 - exact * 2) <= Fraction(float(bound[t])) * (1 + Fraction(1, 10 ** 6)) \
+            + Fraction(got) * 2 * Fraction(1, 2 ** 23)
         margin = Fraction(float(bound[t])) / 2 + T32 * Fraction(1, 2 ** 21)
         if abs(exact - T32) > margin:
             decided += 1
             assert (got <= float(T32)) == (exact <= T32)
     assert decided > 600  # most near-threshold cases are outside the band
+
+
+def test_fit_error_bound_is_not_slack_free(oracle_lib):
+    """The default evaluation's bound must hold on triplets built to round
+    badly (large coordinates, steep tracks) and must not be trivially large:
+    on near-threshold triplets it stays below 1e-3 of the cut."""
+    ci, cj, ck = helpers.near_threshold_triplets(400, seed=13, plane_T=0.03, rel=1e-3, slope_max=0.48)
+    b = R.fp32_fit_error_bound(ci, cj, ck, Z)
+    assert (b < 0.06 * 1e-3).all()
+    cfg = R.OracleConfig(test="msd", msd_max=(0.03, 0.03), ndf=1)
+    worst = 0.0
+    for t in range(len(ci)):
+        exact = R.fit_msd_exact(ci[t], cj[t], ck[t], Z, 1)
+        got = Fraction(R.triplet_msd_c(cfg, ci[t], cj[t], ck[t]))
+        err = abs(got - exact)
+        assert err <= Fraction(float(b[t]))
+        worst = max(worst, float(err / Fraction(float(b[t]))))
+    assert worst > 1e-3  # the bound is not off by orders of magnitude
 
 
 def test_fp32_decisions_agree_with_float64_fit(oracle_lib):
@@ -129,8 +145,8 @@ def test_fp32_decisions_agree_with_float64_fit(oracle_lib):
                               np.arange(sl[2].start, sl[2].stop), indexing="ij")
         qx = R.fit_msd_f64(s.x[I], s.x[J], s.x[K], Z, 2)
         qy = R.fit_msd_f64(s.y[I], s.y[J], s.y[K], Z, 2)
-        bx = R.fp32_error_bound(s.x[I], s.x[J], s.x[K], Z) / 2 + 1e-9
-        by = R.fp32_error_bound(s.y[I], s.y[J], s.y[K], Z) / 2 + 1e-9
+        bx = R.fp32_fit_error_bound(s.x[I], s.x[J], s.x[K], Z) / 2 + 1e-9
+        by = R.fp32_fit_error_bound(s.y[I], s.y[J], s.y[K], Z) / 2 + 1e-9
         Tx, Ty = float(np.float32(0.03)), float(np.float32(0.025))
         if (np.abs(qx - Tx) <= bx).any() or (np.abs(qy - Ty) <= by).any():
             continue
@@ -167,7 +183,9 @@ def test_tiny_bruteforce_exact(oracle_lib):
                 for k in range(o[2], o[3]):
                     qx = R.fit_msd_exact(s.x[i], s.x[j], s.x[k], Z, 2)
                     qy = R.fit_msd_exact(s.y[i], s.y[j], s.y[k], Z, 2)
-                    if abs(qx - Tx) < Fraction(1, 10 ** 5) or abs(qy - Ty) < Fraction(1, 10 ** 5):
+                    bx = Fraction(float(R.fp32_fit_error_bound(s.x[i], s.x[j], s.x[k], Z))) / 2
+                    by = Fraction(float(R.fp32_fit_error_bound(s.y[i], s.y[j], s.y[k], Z))) / 2
+                    if abs(qx - Tx) <= bx + Tx / 2 ** 21 or abs(qy - Ty) <= by + Ty / 2 ** 21:
                         ambiguous = True
                     exact += int(qx <= Tx and qy <= Ty)
         if not ambiguous:
@@ -214,7 +232,7 @@ def test_invariant_sign_flip_and_xy_swap(oracle_lib, mode):
     assert np.array_equal(R.select_set(sw, cfg_sw)[0], base)
 
 
-@pytest.mark.parametrize("mode", ["msd", "msd_fit"])
+@pytest.mark.parametrize("mode", ["msd", "msd_basis"])
 def test_invariant_power_of_two_scaling(oracle_lib, mode):
     """Coordinates x 2^k with thresholds x 4^k: every fp32 product and sum
     scales exactly, so every decision is unchanged."""
@@ -337,3 +355,34 @@ def test_special_coordinate_values(oracle_lib, mode):
     # special values only: no layer-0 hit has two finite coordinates below
     # 1e30 in magnitude, so no triplet can pass
     assert c[10] == 0
+
+
+# ------------------------------------------- the two evaluation orders ---
+
+@pytest.mark.parametrize("name,n_events", [("small_10k", None), ("medium_1m", 100_000),
+                                           ("mixture_4m", 5_000), ("dense_100k", 300)])
+def test_evaluation_orders_agree_on_workloads(oracle_lib, name, n_events):
+    """The fit written out (default) and its basis-form evaluation round
+    differently, but on the benchmark workloads no triplet's decision differs:
+    every triplet of the 10k-event workload, the first 100k events of the
+    1M-event workload and samples of the mixture and dense workloads (each
+    triplet decided both ways, both planes)."""
+    spec = synth.WORKLOADS[name]
+    s = synth.make_event_set(spec, n_events=n_events) if n_events else synth.make_event_set(spec)
+    threads = max(1, min(8, len(__import__("os").sched_getaffinity(0))))
+    d = R.msd_disagreements(s.offsets, s.x, s.y, n_threads=threads)
+    assert int(d.sum()) == 0, (name, int((d > 0).sum()))
+
+
+def test_evaluation_orders_can_disagree(oracle_lib):
+    """The disagreement counter itself: near-threshold triplets within a few
+    ulps of the cut are decided differently by the two orders for some
+    triplets (so a zero above is a measurement, not a tautology)."""
+    s = helpers.near_threshold_events(400, 8, seed=21, rel=1e-7)
+    d = R.msd_disagreements(s.offsets, s.x, s.y, n_threads=4)
+    c_fit = R.select_set(s, R.OracleConfig(test="msd"))[0]
+    c_basis = R.select_set(s, R.OracleConfig(test="msd_basis"))[0]
+    assert d.sum() > 0
+    # an event whose counts differ has disagreeing triplets
+    assert ((c_fit != c_basis) <= (d > 0)).all()
+    assert (np.abs(c_fit.astype(np.int64) - c_basis) <= d).all()
