@@ -31,11 +31,19 @@
  * binary32 with round-to-nearest-even, subnormals preserved and no fused
  * multiply-add, in the operation order below, so that an independent
  * implementation reproduces every count bit for bit.  Per plane c in {x, y},
- * for hits c_i, c_j, c_k of layers 0, 1, 2 (each line one binary32 rounding):
+ * for hits c_i, c_j, c_k of layers 0, 1, 2 (each line one binary32 rounding
+ * per operation, left to right):
  *
- *   TRIG_TEST_MSD (default) - the fit's residual sum of squares Q, evaluated
- *     as the squared length of (c_i, c_j, c_k) projected on the plane
- *     orthogonal to z = (z0, z1, z2), in the orthonormal basis
+ *   TRIG_TEST_MSD (default) - the fit of Sec. 3.2 step 2 written out: the
+ *     least-squares slope of the line c = m z through the vertex, its
+ *     residuals and their sum of squares Q:
+ *         Szz = (z0*z0 + z1*z1) + z2*z2,   w = f32(1 / f64(Szz)),
+ *         m = ((c_i*z0 + c_j*z1) + c_k*z2) * w,
+ *         r_l = c_l - m*z_l,   Q = (r0*r0 + r1*r1) + r2*r2
+ *   TRIG_TEST_MSD_BASIS - the same Q evaluated in an orthonormal basis of
+ *     the plane orthogonal to z = (z0, z1, z2) (8 operations per triplet
+ *     instead of 28; in exact arithmetic the same number, in binary32 a
+ *     decision can differ from TRIG_TEST_MSD's within a few ulps of the cut):
  *       u = (z1, -z0, 0) / n01,   v = (z0 z2, z1 z2, -s01) / (n01 |z|),
  *       s01 = z0^2 + z1^2, n01 = sqrt(s01), |z| = sqrt(s01 + z2^2):
  *         a = U0*c_i + U1*c_j
@@ -44,10 +52,6 @@
  *     with U0 = f32(z1/n01), U1 = f32(-z0/n01), V0 = f32(z0 z2/d),
  *     V1 = f32(z1 z2/d), V2 = f32(-s01/d), d = n01 |z|, everything before the
  *     final rounding evaluated in binary64 in the order written.
- *   TRIG_TEST_MSD_FIT - the same fit written out:
- *         m = ((c_i*z0 + c_j*z1) + c_k*z2) * w,  w = f32(1 / f64(Szz)),
- *         Szz = (z0*z0 + z1*z1) + z2*z2 in binary32,
- *         r_l = c_l - m*z_l,   Q = (r0*r0 + r1*r1) + r2*r2
  *   For both MSD tests the plane passes iff  f32(Q / ndf) <= msd_max[c]
  *   (a triplet is rejected only if its MSD is above the threshold).
  *   TRIG_TEST_SLOPE_WINDOW - s_l = c_l / z_l (binary32 division); the plane
@@ -65,7 +69,7 @@
 extern "C" {
 #endif
 
-#define TRIG_ABI_VERSION 1u
+#define TRIG_ABI_VERSION 2u
 
 /* Return codes. */
 #define TRIG_OK 0
@@ -102,55 +106,53 @@ typedef struct {
 enum {
     TRIG_TEST_MSD = 0,
     TRIG_TEST_SLOPE_WINDOW = 1,
-    TRIG_TEST_MSD_FIT = 2
+    TRIG_TEST_MSD_BASIS = 2
 };
 
 /* Execution form and output flags (bitwise OR).  Every form computes the same
- * counts and flags bit for bit. */
+ * counts and flags bit for bit, for every test. */
 enum {
     TRIG_EXEC_PLAIN = 0u,       /* one wave per event, every triplet tested */
     TRIG_EXEC_PERSISTENT = 1u,  /* one persistent launch; alone: waves steal
                                    (event, pair-range) work units of the
                                    every-triplet loop from a global counter;
                                    with TRIG_EXEC_PRUNED: workgroups steal event
-                                   blocks.  Needs workspace */
-    TRIG_EXEC_PRUNED = 2u,      /* batched form: workgroups stage blocks of
-                                   consecutive events in LDS and complete only
-                                   pairs that provably can pass (MSD: a pair
-                                   with f32(a*a) > Qmax in a plane has Q > Qmax
-                                   for every k in binary32; window: the layer-1
-                                   window is part of the test); same counts.
-                                   Not for TRIG_TEST_MSD_FIT */
-    TRIG_EXEC_BINNED = 4u,      /* binned form for high-multiplicity events:
+                                   blocks; with TRIG_EXEC_BINNED: workgroups
+                                   steal event groups.  Needs workspace */
+    TRIG_EXEC_BINNED = 2u,      /* binned form for high-multiplicity events:
                                    one wave per event sorts layers 1 and 2
                                    into cells of a slope-proportional key in
                                    LDS and tests only hits in the cells whose
-                                   key interval can pass (MSD: |a|, |b| <=
-                                   beta; window: the slope windows), with the
-                                   interval ends rounded outwards; same
-                                   counts.  Events with more than 256 hits in
-                                   layer 1 or 2 take the pruned path.  With
-                                   TRIG_EXEC_PERSISTENT workgroups take event
-                                   groups from a counter (needs workspace).
-                                   Not for TRIG_TEST_MSD_FIT, not with
-                                   TRIG_EXEC_PRUNED or TRIG_EXEC_AUTOTUNE */
-    TRIG_EXEC_AUTOTUNE = 8u,    /* MSD and window tests: run the form that
-                                   trig_autotune recorded for this device,
-                                   test and multiplicity class
-                                   (floor(log2(mean hits per event))): the
-                                   batched form with its launch shape
+                                   key interval can pass (MSD tests: bounds on
+                                   the partial sums a and b that every passing
+                                   triplet meets; window: the slope windows),
+                                   with the interval ends rounded outwards;
+                                   same counts.  Events with more than 256
+                                   hits in layer 1 or 2 take the pruned path.
+                                   Not with TRIG_EXEC_PRUNED or
+                                   TRIG_EXEC_AUTOTUNE */
+    TRIG_EXEC_AUTOTUNE = 4u,    /* run the form that trig_autotune recorded
+                                   for this device, test and multiplicity
+                                   class (floor(log2(mean hits per event))):
+                                   the batched form with its launch shape
                                    (block_hits, block_waves, fill of
                                    block_events, block stealing on or off),
                                    or the binned form with or without
                                    stealing; without a record, the batched
                                    form with the built-in rule.  Non-zero
                                    block_* fields win over the record and
-                                   select the batched form.  MSD_FIT: the
-                                   caller's brute-force flags.  Needs the
+                                   select the batched form.  Needs the
                                    workspace of trig_workspace_bytes() for
                                    these flags */
-    TRIG_OUT_COMPACT = 16u      /* also write the ascending ids of accepted
+    TRIG_OUT_COMPACT = 8u,      /* also write the ascending ids of accepted
                                    events; needs workspace */
+    TRIG_EXEC_PRUNED = 16u      /* batched form: workgroups stage blocks of
+                                   consecutive events in LDS and complete only
+                                   pairs that provably can pass (MSD tests: a
+                                   bound on the pair's partial sum a that
+                                   every passing triplet meets; window: the
+                                   layer-1 window is part of the test); same
+                                   counts */
 };
 
 typedef struct {
@@ -226,7 +228,7 @@ int trig_select(const trig_events_csr *ev, const trig_hits *hits, const trig_par
 
 /* Result of trig_autotune (host). */
 typedef struct {
-    int32_t n_candidates;     /* launch shapes timed (0 for MSD_FIT) */
+    int32_t n_candidates;     /* launch shapes timed (0 for an empty batch) */
     int32_t mult_class;       /* multiplicity class of the batch */
     int32_t block_hits;       /* chosen batched-form shape (0 if binned) */
     int32_t block_waves;

@@ -36,6 +36,7 @@
 #include "trig.h"
 #include "trig_binned.hpp"
 #include "trig_block.hpp"
+#include "trig_bounds.hpp"
 #include "trig_device.hpp"
 
 using namespace trig;
@@ -56,7 +57,7 @@ constexpr double kRuleFill = 0.85;    // built-in rule: hits per block over the 
 template <class T>
 struct Chunk;
 template <>
-struct Chunk<MsdTest> { static constexpr int value = kChunkMsd; };
+struct Chunk<MsdBasisTest> { static constexpr int value = kChunkMsd; };
 template <>
 struct Chunk<WindowTest> { static constexpr int value = kChunkMsd; };
 template <>
@@ -377,8 +378,12 @@ __global__ __launch_bounds__(kBinWaves * kWave) __attribute__((amdgpu_waves_per_
                 if (ev.n1 <= kBinCap && ev.n2 <= kBinCap) {
                     cnt = (int32_t)wave_event_binned<B>(c, x, y, ev.o0, ev.n0, ev.o1, ev.n1, ev.o2, ev.n2, L);
                 } else {
-                    cnt = (int32_t)wave_event_pruned<typename B::Prune>(c, GlobalHits{x, y}, ev.o0, ev.n0, ev.o1,
-                                                                        ev.n1, ev.o2, ev.n2, L.a1, L.b1);
+                    using P = typename B::Prune;
+                    const GlobalHits gh{x, y};
+                    float M = 0.0f;
+                    if constexpr (P::kMag) M = layer_mag(gh, ev.o1, ev.n1);
+                    cnt = (int32_t)wave_event_pruned<P>(c, P::bounds(c, M), gh, ev.o0, ev.n0, ev.o1, ev.n1, ev.o2,
+                                                        ev.n2, L.a1, L.b1);
                     wave_lds_sync();
                 }
             }
@@ -412,60 +417,15 @@ size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-uint32_t bits_of(float f) {
-    uint32_t u;
-    std::memcpy(&u, &f, 4);
-    return u;
-}
-float float_of(uint32_t u) {
-    float f;
-    std::memcpy(&f, &u, 4);
-    return f;
-}
-
-// Largest non-negative binary32 v (bit pattern search over [0, +inf]) with
-// pred(v) true, for pred non-increasing in v and pred(0) true.
-template <class Pred>
-float largest_with(Pred pred) {
-    uint32_t lo = 0u, hi = 0x7f800000u;  // pred(lo) true
-    if (pred(float_of(hi))) return float_of(hi);
-    while (hi - lo > 1u) {  // pred(hi) false
-        const uint32_t mid = lo + (hi - lo) / 2u;
-        if (pred(float_of(mid))) lo = mid; else hi = mid;
-    }
-    return float_of(lo);
-}
-
-// Largest binary32 q with f32(q / ndf) <= t.  f32(q / ndf) is non-decreasing
-// in q, so {q >= 0 : f32(q / ndf) <= t} is exactly {0 <= q <= Qmax}.
-float fold_threshold(float t, int ndf) {
-    const float n = (float)ndf;
-    return largest_with([&](float q) {
-        volatile float d = q / n;
-        return (float)d <= t;
-    });
-}
-
-// Largest binary32 b >= 0 with f32(b * b) <= qmax (f32(b * b) is
-// non-decreasing in b >= 0).
-float pair_bound(float qmax) {
-    return largest_with([&](float b) {
-        volatile float sq = b * b;
-        return (float)sq <= qmax;
-    });
-}
-
 Consts make_consts(const trig_params* p, int n_hits) {
+    using namespace trig_host;
     Consts c;
-    const double z0 = p->z[0], z1 = p->z[1], z2 = p->z[2];
-    const double s01 = z0 * z0 + z1 * z1;
-    const double n01 = std::sqrt(s01);
-    const double d = n01 * std::sqrt(s01 + z2 * z2);
-    c.U0 = (float)(z1 / n01);
-    c.U1 = (float)(-z0 / n01);
-    c.V0 = (float)((z0 * z2) / d);
-    c.V1 = (float)((z1 * z2) / d);
-    c.V2 = (float)(-s01 / d);
+    const Basis K = basis(p->z[0], p->z[1], p->z[2]);
+    c.U0 = K.U0;
+    c.U1 = K.U1;
+    c.V0 = K.V0;
+    c.V1 = K.V1;
+    c.V2 = K.V2;
     c.z0 = p->z[0];
     c.z1 = p->z[1];
     c.z2 = p->z[2];
@@ -475,6 +435,14 @@ Consts make_consts(const trig_params* p, int n_hits) {
     c.qmax_y = fold_threshold(p->msd_max[1], p->ndf);
     c.beta_x = pair_bound(c.qmax_x);
     c.beta_y = pair_bound(c.qmax_y);
+    const FitBounds fx = fit_bounds(c.z0, c.z1, c.z2, c.qmax_x);
+    const FitBounds fy = fit_bounds(c.z0, c.z1, c.z2, c.qmax_y);
+    c.fit_a0x = fx.a0;
+    c.fit_a1x = fx.a1;
+    c.fit_a0y = fy.a0;
+    c.fit_a1y = fy.a1;
+    c.fit_b0x = fx.b0;
+    c.fit_b1x = fx.b1;
     c.pre_msd = std::max(c.beta_x, c.beta_y);
     c.pre_win = std::max(p->slope_window[0], p->slope_window[1]);
     c.win_x = p->slope_window[0];
@@ -499,14 +467,15 @@ int validate(const trig_events_csr* ev, const trig_hits* hits, const trig_params
 int validate_params(const trig_params* p, bool need_outputs) {
     if (!p) return fail(TRIG_EINVAL, "NULL params");
     if (p->abi_version != TRIG_ABI_VERSION) return fail(TRIG_EINVAL, "abi_version mismatch");
-    if (p->test != TRIG_TEST_MSD && p->test != TRIG_TEST_MSD_FIT && p->test != TRIG_TEST_SLOPE_WINDOW)
+    if (p->test != TRIG_TEST_MSD && p->test != TRIG_TEST_MSD_BASIS && p->test != TRIG_TEST_SLOPE_WINDOW)
         return fail(TRIG_EINVAL, "unknown test");
     for (int l = 0; l < 3; ++l)
         if (!std::isfinite(p->z[l]) || !(p->z[l] > 0.0f)) return fail(TRIG_EINVAL, "z must be finite and > 0");
     for (int k = 0; k < 2; ++k) {
-        if (std::isnan(p->msd_max[k]) || p->msd_max[k] < 0.0f) return fail(TRIG_EINVAL, "msd_max must be >= 0");
-        if (std::isnan(p->slope_window[k]) || p->slope_window[k] < 0.0f)
-            return fail(TRIG_EINVAL, "slope_window must be >= 0");
+        if (!std::isfinite(p->msd_max[k]) || p->msd_max[k] < 0.0f)
+            return fail(TRIG_EINVAL, "msd_max must be finite and >= 0");
+        if (!std::isfinite(p->slope_window[k]) || p->slope_window[k] < 0.0f)
+            return fail(TRIG_EINVAL, "slope_window must be finite and >= 0");
     }
     if (p->ndf < 1) return fail(TRIG_EINVAL, "ndf < 1");
     if (p->min_triplets < 0) return fail(TRIG_EINVAL, "min_triplets < 0");
@@ -523,10 +492,6 @@ int validate_params(const trig_params* p, bool need_outputs) {
     if (p->flags & ~known) return fail(TRIG_EINVAL, "unknown flag bits");
     if (need_outputs && (p->flags & TRIG_OUT_COMPACT) && (!p->out_accepted_ids || !p->out_n_accepted))
         return fail(TRIG_EINVAL, "TRIG_OUT_COMPACT needs out_accepted_ids and out_n_accepted");
-    if ((p->flags & TRIG_EXEC_PRUNED) && p->test == TRIG_TEST_MSD_FIT)
-        return fail(TRIG_EUNSUPPORTED, "pruning is not provided for TRIG_TEST_MSD_FIT");
-    if ((p->flags & TRIG_EXEC_BINNED) && p->test == TRIG_TEST_MSD_FIT)
-        return fail(TRIG_EUNSUPPORTED, "binning is not provided for TRIG_TEST_MSD_FIT");
     if ((p->flags & TRIG_EXEC_BINNED) && (p->flags & (TRIG_EXEC_PRUNED | TRIG_EXEC_AUTOTUNE)))
         return fail(TRIG_EUNSUPPORTED, "TRIG_EXEC_BINNED does not combine with TRIG_EXEC_PRUNED or TRIG_EXEC_AUTOTUNE");
     return TRIG_OK;
@@ -562,12 +527,11 @@ Layout layout(int n_events, uint32_t flags) {
 }
 
 // Flags whose workspace layout covers a call: an autotuned call may run the
-// batched form with or without block stealing (the MSD_FIT test keeps the
-// caller's brute-force flags), so it reserves the block counter.
+// batched or binned form with or without stealing, so it reserves the block
+// counter.
 uint32_t layout_flags(const trig_params* p) {
     if (!(p->flags & TRIG_EXEC_AUTOTUNE)) return p->flags;
     const uint32_t f = p->flags & ~(uint32_t)TRIG_EXEC_AUTOTUNE;
-    if (p->test == TRIG_TEST_MSD_FIT) return f;
     return f | TRIG_EXEC_PRUNED | TRIG_EXEC_PERSISTENT;
 }
 
@@ -785,14 +749,13 @@ int current_device() {
     return d;
 }
 
-// Effective parameters of a TRIG_EXEC_AUTOTUNE call for the tests that have
-// the batched and binned forms: the recorded form and shape of the batch's
-// class, else the batched form with the built-in rule.  Block fields the
-// caller set explicitly win over the record and select the batched form.
+// Effective parameters of a TRIG_EXEC_AUTOTUNE call: the recorded form and
+// shape of the batch's class, else the batched form with the built-in rule.
+// Block fields the caller set explicitly win over the record and select the
+// batched form.
 trig_params resolve_autotune(const trig_params* p, int n_events, int n_hits) {
     trig_params q = *p;
     q.flags &= ~(uint32_t)TRIG_EXEC_AUTOTUNE;
-    if (p->test == TRIG_TEST_MSD_FIT) return q;  // brute force only
     q.flags |= TRIG_EXEC_PRUNED;
     std::lock_guard<std::mutex> lock(g_tune_mu);
     auto it = g_tuned.find({current_device(), p->test, multiplicity_class(n_events, n_hits)});
@@ -873,10 +836,11 @@ int trig_select(const trig_events_csr* ev, const trig_hits* hits, const trig_par
         int r = TRIG_OK;
         switch (p->test) {
             case TRIG_TEST_MSD:
-                r = run_form<MsdTest, MsdPrune, MsdBin>(ev, hits, p, c, L, ws, out_counts, out_accept, s);
+                r = run_form<MsdFitTest, MsdFitPrune, MsdFitBin>(ev, hits, p, c, L, ws, out_counts, out_accept, s);
                 break;
-            case TRIG_TEST_MSD_FIT:  // validated: never with TRIG_EXEC_PRUNED
-                r = run_form<MsdFitTest, MsdPrune, MsdBin>(ev, hits, p, c, L, ws, out_counts, out_accept, s);
+            case TRIG_TEST_MSD_BASIS:
+                r = run_form<MsdBasisTest, MsdBasisPrune, MsdBasisBin>(ev, hits, p, c, L, ws, out_counts, out_accept,
+                                                                       s);
                 break;
             default:
                 r = run_form<WindowTest, WindowPrune, WindowBin>(ev, hits, p, c, L, ws, out_counts, out_accept, s);
@@ -926,7 +890,7 @@ int trig_autotune(const trig_events_csr* ev, const trig_hits* hits, const trig_p
     res.mult_class = multiplicity_class(n, n_hits);
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
 
-    if (p->test != TRIG_TEST_MSD_FIT && n > 0) {
+    if (n > 0) {
         hipEvent_t e0 = nullptr, e1 = nullptr;
         if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
             if (e0) (void)hipEventDestroy(e0);
@@ -1003,7 +967,7 @@ int trig_autotune(const trig_events_csr* ev, const trig_hits* hits, const trig_p
     trig_params q = *p;
     q.block_hits = q.block_waves = q.block_events = 0;
     if (int r = trig_select(ev, hits, &q, out_counts, out_accept, stream)) return r;
-    if (p->test != TRIG_TEST_MSD_FIT && n > 0) {
+    if (n > 0) {
         const trig_params eff = resolve_autotune(&q, n, n_hits);
         res.persistent = (eff.flags & TRIG_EXEC_PERSISTENT) ? 1 : 0;
         res.binned = (eff.flags & TRIG_EXEC_BINNED) ? 1 : 0;

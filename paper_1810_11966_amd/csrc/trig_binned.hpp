@@ -5,13 +5,15 @@
 // layer-1 hit is put into a cell by a key that is proportional to its slope
 // x/z, and each layer-0 hit looks only at the cells that can hold a partner:
 //
-//   MSD test: a triplet passes only if |a| <= beta in both planes (see the
-//     batched form), a = f32(u + v) with u = f32(U0 x_i), v = f32(U1 x_j).  As
-//     binary32 rounding is monotone and beta_up = next float above beta,
-//     |f32(u + v)| <= beta implies -beta_up < u + v < beta_up in real numbers,
-//     so v lies in (-u - beta_up, -u + beta_up).  The layer-1 key is v.  In
+//   MSD tests: a triplet passes only if |a| <= A in both planes and
+//     |b| <= B in the x-z plane (see the batched form; MSD_BASIS: A = B = beta,
+//     MSD: A = a0 + a1 M and B = b0 + b1 M with M the event's largest layer-1
+//     |x|, |y|), a = f32(u + v) with u = f32(U0 x_i), v = f32(U1 x_j).  As
+//     binary32 rounding is monotone and A_up >= next float above A,
+//     |f32(u + v)| <= A implies -A_up < u + v < A_up in real numbers,
+//     so v lies in (-u - A_up, -u + A_up).  The layer-1 key is v.  In
 //     the same way b = f32(p + w_k) with p = f32(V0 x_i + V1 x_j) and
-//     w_k = f32(V2 x_k) needs w_k in (-p - beta_up, -p + beta_up); the
+//     w_k = f32(V2 x_k) needs w_k in (-p - B_up, -p + B_up); the
 //     layer-2 key is w_k.
 //   window test: |f32(s_j - s_i)| < W implies |s_j - s_i| < W (W is a binary32
 //     value), so s_j lies in (s_i - W, s_i + W); the same for s_k.  Here the
@@ -192,10 +194,22 @@ __device__ __forceinline__ Bins build_bins(const Consts& c, const LayerRegs& h, 
     return build_bins_r<K, 4>(c, h, n, end, pa, pb);
 }
 
+// Bounds of one event: pair test |a_x| <= bx, |a_y| <= by (window: strict,
+// with the windows), and the half-widths r1, r2 of the layer-1 and layer-2
+// key intervals, each at least the next binary32 value above its bound.
+struct BinBounds {
+    float bx, by, r1, r2;
+};
+
 // ---------------------------------------------------------------- MSD ---
 
-struct MsdBin {
-    using Prune = MsdPrune;
+// TRIG_TEST_MSD_BASIS.
+struct MsdBasisBin {
+    using Prune = MsdBasisPrune;
+    static constexpr bool kMag = false;
+    __device__ static __forceinline__ BinBounds bounds(const Consts& c, float) {
+        return BinBounds{c.beta_x, c.beta_y, c.bin_r, c.bin_r};
+    }
     struct Key1 {  // layer 1: key U1 x, payload (x, y)
         __device__ static __forceinline__ float key(const Consts& c, float x, float) { return c.U1 * x; }
         __device__ static __forceinline__ float2 payload(const Consts&, float x, float y) {
@@ -209,10 +223,10 @@ struct MsdBin {
         }
     };
     // Passing triplets with layer-0 hit (xi, yi).
-    __device__ static uint32_t count_i(const Consts& c, float xi, float yi, const Bins& b1, const Bins& b2,
-                                       const BinLds& L) {
+    __device__ static uint32_t count_i(const Consts& c, const BinBounds& bb, float xi, float yi, const Bins& b1,
+                                       const Bins& b2, const BinLds& L) {
         const float ux = c.U0 * xi;
-        const float r = c.bin_r;
+        const float r = bb.r1;
         if (!__builtin_isfinite(ux)) return 0;
         const float lo = widen_down(-ux - r), hi = widen_up(-ux + r);
         if (hi < b1.kmin || lo > b1.kmax) return 0;
@@ -223,12 +237,12 @@ struct MsdBin {
             const float xj = L.a1[j], yj = L.b1[j];
             const float ax = c.U0 * xi + c.U1 * xj;
             const float ay = c.U0 * yi + c.U1 * yj;
-            if (!(__builtin_fabsf(ax) <= c.beta_x && __builtin_fabsf(ay) <= c.beta_y)) continue;
+            if (!(__builtin_fabsf(ax) <= bb.bx && __builtin_fabsf(ay) <= bb.by)) continue;
             const float ax2 = ax * ax, ay2 = ay * ay;
             const float bx0 = c.V0 * xi + c.V1 * xj;
             const float by0 = c.V0 * yi + c.V1 * yj;
             if (!__builtin_isfinite(bx0)) continue;
-            const float lo2 = widen_down(-bx0 - r), hi2 = widen_up(-bx0 + r);
+            const float lo2 = widen_down(-bx0 - bb.r2), hi2 = widen_up(-bx0 + bb.r2);
             if (hi2 < b2.kmin || lo2 > b2.kmax) continue;
             int k0, k1;
             b2.range(L.end2, lo2, hi2, k0, k1);
@@ -244,10 +258,76 @@ struct MsdBin {
     }
 };
 
+// TRIG_TEST_MSD: cells and pair test from the written-out fit's bounds
+// (a0 + a1 M, b0 + b1 M), candidates completed with the fit written out.
+// A pair whose b partial is infinite has no passing triplet: with
+// M = |x_j| (finite for a hit in a cell) the bound on |b| is finite.
+struct MsdFitBin {
+    using Prune = MsdFitPrune;
+    static constexpr bool kMag = true;
+    __device__ static __forceinline__ BinBounds bounds(const Consts& c, float M) {
+        // 1 + 2^-20: fl(A (1 + 2^-20)) >= A (1 + 2^-23), above the next
+        // binary32 value after any A >= 2^-126 (the bounds are normal)
+        constexpr float kUp = 1.00000095367431640625f;
+        const float bx = c.fit_a0x + c.fit_a1x * M;
+        const float by = c.fit_a0y + c.fit_a1y * M;
+        const float B = c.fit_b0x + c.fit_b1x * M;
+        return BinBounds{bx, by, bx * kUp, B * kUp};
+    }
+    struct Key1 {  // layer 1: key U1 x, payload (x, y)
+        __device__ static __forceinline__ float key(const Consts& c, float x, float) { return c.U1 * x; }
+        __device__ static __forceinline__ float2 payload(const Consts&, float x, float y) {
+            return make_float2(x, y);
+        }
+    };
+    struct Key2 {  // layer 2: key V2 x, payload (x, y)
+        __device__ static __forceinline__ float key(const Consts& c, float x, float) { return c.V2 * x; }
+        __device__ static __forceinline__ float2 payload(const Consts&, float x, float y) {
+            return make_float2(x, y);
+        }
+    };
+    __device__ static uint32_t count_i(const Consts& c, const BinBounds& bb, float xi, float yi, const Bins& b1,
+                                       const Bins& b2, const BinLds& L) {
+        const float ux = c.U0 * xi;
+        if (!__builtin_isfinite(ux)) return 0;  // x_i not finite: the fit fails
+        const float lo = widen_down(-ux - bb.r1), hi = widen_up(-ux + bb.r1);
+        if (hi < b1.kmin || lo > b1.kmax) return 0;
+        int j0, j1;
+        b1.range(L.end1, lo, hi, j0, j1);
+        const float pxi = xi * c.z0, pyi = yi * c.z0;
+        uint32_t cnt = 0;
+        for (int j = j0; j < j1; ++j) {
+            const float xj = L.a1[j], yj = L.b1[j];
+            const float ax = c.U0 * xi + c.U1 * xj;
+            const float ay = c.U0 * yi + c.U1 * yj;
+            if (!(__builtin_fabsf(ax) <= bb.bx && __builtin_fabsf(ay) <= bb.by)) continue;
+            const float bx0 = c.V0 * xi + c.V1 * xj;
+            if (!__builtin_isfinite(bx0)) continue;
+            const float lo2 = widen_down(-bx0 - bb.r2), hi2 = widen_up(-bx0 + bb.r2);
+            if (hi2 < b2.kmin || lo2 > b2.kmax) continue;
+            int k0, k1;
+            b2.range(L.end2, lo2, hi2, k0, k1);
+            const float sx01 = pxi + xj * c.z1;
+            const float sy01 = pyi + yj * c.z1;
+            for (int k = k0; k < k1; ++k) {
+                const float xk = L.a2[k], yk = L.b2[k];
+                const float qx = MsdFitTest::plane_q(c, xi, xj, sx01, xk, xk * c.z2);
+                const float qy = MsdFitTest::plane_q(c, yi, yj, sy01, yk, yk * c.z2);
+                cnt += (uint32_t)((qx <= c.qmax_x) & (qy <= c.qmax_y));
+            }
+        }
+        return cnt;
+    }
+};
+
 // ------------------------------------------------------------- window ---
 
 struct WindowBin {
     using Prune = WindowPrune;
+    static constexpr bool kMag = false;
+    __device__ static __forceinline__ BinBounds bounds(const Consts& c, float) {
+        return BinBounds{c.win_x, c.win_y, c.bin_r, c.bin_r};
+    }
     struct Key1 {  // layer 1: slopes (x / z1, y / z1), key the x slope
         __device__ static __forceinline__ float key(const Consts& c, float x, float) { return x / c.z1; }
         __device__ static __forceinline__ float2 payload(const Consts& c, float x, float y) {
@@ -260,11 +340,11 @@ struct WindowBin {
             return make_float2(x / c.z2, y / c.z2);
         }
     };
-    __device__ static uint32_t count_i(const Consts& c, float xi, float yi, const Bins& b1, const Bins& b2,
-                                       const BinLds& L) {
+    __device__ static uint32_t count_i(const Consts& c, const BinBounds& bb, float xi, float yi, const Bins& b1,
+                                       const Bins& b2, const BinLds& L) {
         const float sxi = xi / c.z0, syi = yi / c.z0;
         if (!__builtin_isfinite(sxi)) return 0;
-        const float lo = widen_down(sxi - c.bin_r), hi = widen_up(sxi + c.bin_r);
+        const float lo = widen_down(sxi - bb.r1), hi = widen_up(sxi + bb.r1);
         uint32_t nj = 0, nk = 0;
         if (!(hi < b1.kmin || lo > b1.kmax)) {
             int j0, j1;
@@ -297,6 +377,15 @@ __device__ uint32_t wave_event_binned(const Consts& c, const float* __restrict__
     h1.load(x, y, o1, n1);
     h2.load(x, y, o2, n2);
     float xi = x[o0 + min(lane, n0 - 1)], yi = y[o0 + min(lane, n0 - 1)];
+    float M = 0.0f;  // largest layer-1 |x|, |y| (rounds past the layer hold 0 or a layer-1 hit)
+    if constexpr (B::kMag) {
+        float m = 0.0f;
+#pragma unroll
+        for (int r = 0; r < kBinRounds; ++r)
+            if (r * kWave < n1) m = mag4(m, h1.x[r], h1.y[r], 0.0f, 0.0f);
+        M = wave_max_f(m);
+    }
+    const BinBounds bb = B::bounds(c, M);
     const Bins b1 = build_bins<typename B::Key1>(c, h1, n1, L.end1, L.a1, L.b1);
     const Bins b2 = build_bins<typename B::Key2>(c, h2, n2, L.end2, L.a2, L.b2);
     uint32_t cnt = 0;
@@ -307,7 +396,7 @@ __device__ uint32_t wave_event_binned(const Consts& c, const float* __restrict__
             xn = x[o0 + in];
             yn = y[o0 + in];
         }
-        if (i0 + lane < n0) cnt += B::count_i(c, xi, yi, b1, b2, L);
+        if (i0 + lane < n0) cnt += B::count_i(c, bb, xi, yi, b1, b2, L);
         xi = xn;
         yi = yn;
     }

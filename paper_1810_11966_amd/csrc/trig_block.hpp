@@ -6,16 +6,21 @@
 // brute-force triplet loop (paper Sec. 3.2 steps 1-3), but triplets are only
 // completed for pairs (i, j) that can still pass:
 //
-//   MSD test:  Q = f32(A + f32(b*b)) >= A = f32(a*a) in binary32 (rounding is
+//   MSD test (the fit written out): a = f32(U0*c_i + U1*c_j) depends on
+//              (i, j) only, and a triplet that passes a plane has
+//              |a| <= a0 + a1 M for any M >= |c_j| (csrc/trig_bounds.hpp: a
+//              rigorous bound on the fit's binary32 rounding).  M is the
+//              largest |x|, |y| among the staged hits (per block, or per event
+//              for events read from HBM).
+//   MSD_BASIS: Q = f32(A + f32(b*b)) >= A = f32(a*a) in binary32 (rounding is
 //              monotone and b*b >= 0), so a triplet can pass only if
 //              f32(a*a) <= Qmax in both planes, i.e. |a| <= beta with beta the
 //              largest binary32 value whose rounded square is <= Qmax
-//              (f32(a*a) is non-decreasing in |a|).  a = f32(U0*c_i + U1*c_j)
-//              depends on (i, j) only.
+//              (f32(a*a) is non-decreasing in |a|).
 //   window:    the layer-1 window |s_j - s_i| < W is itself part of the test.
 //
-// Both conditions are exact consequences of the binary32 test, so pruning
-// never changes a count.  Surviving pairs (rare: a is the distance of hit j
+// All three conditions are exact consequences of the binary32 test, so
+// pruning never changes a count.  Surviving pairs (rare: a is the distance of hit j
 // from the line through the vertex and hit i, in cm) are completed against
 // every layer-2 hit with the full binary32 test, lanes over k.
 //
@@ -84,7 +89,31 @@ __device__ __forceinline__ float2 nan2() {
     return make_float2(n, n);
 }
 
-struct MsdPrune {
+// Largest |x|, |y| of hits [o, o + n) (NaN ignored, infinities kept), by a
+// whole wave; the same value on every lane.
+template <class H>
+__device__ float layer_mag(const H& hits, int o, int n) {
+    float m = 0.0f;
+    for (int t = (int)lane_id(); t < n; t += kWave) {
+        const float2 h = hits.at(o + t);
+        m = __builtin_fmaxf(m, __builtin_fmaxf(__builtin_fabsf(h.x), __builtin_fabsf(h.y)));
+    }
+    return wave_max_f(m);
+}
+
+// Pair test bounds of a block or event: the exact pair test is
+// |a_x| <= bx and |a_y| <= by (window: strict), and the prefilter score of a
+// pair that passes it is at most pre.
+struct PairBounds {
+    float bx, by, pre;
+};
+
+// TRIG_TEST_MSD_BASIS.
+struct MsdBasisPrune {
+    static constexpr bool kMag = false;  // bounds do not depend on M
+    __device__ static __forceinline__ PairBounds bounds(const Consts& c, float) {
+        return PairBounds{c.beta_x, c.beta_y, c.pre_msd};
+    }
     __device__ static __forceinline__ float2 layer0(const Consts& c, float2 h) {
         return make_float2(c.U0 * h.x, c.U0 * h.y);
     }
@@ -96,21 +125,20 @@ struct MsdPrune {
         const float u = select_uniform(l, c.U1, c.U0);
         return make_float2(u * h.x, u * h.y);
     }
-    // Lanes whose pair can still pass: |f32(P + Q)| <= beta in both planes.
-    __device__ static __forceinline__ uint64_t pair_mask(const Consts& c, float2 p, float2 q) {
+    // Lanes whose pair can still pass: |f32(P + Q)| <= bound in both planes.
+    __device__ static __forceinline__ uint64_t pair_mask(const PairBounds& b, float2 p, float2 q) {
         const float ax = p.x + q.x;
         const float ay = p.y + q.y;
-        return lanes(__builtin_fabsf(ax) <= c.beta_x) & lanes(__builtin_fabsf(ay) <= c.beta_y);
+        return lanes(__builtin_fabsf(ax) <= b.bx) & lanes(__builtin_fabsf(ay) <= b.by);
     }
-    // Prefilter score: pair_mask's lane set is within {score <= bound()}
-    // (|a_x| <= beta_x and |a_y| <= beta_y imply max(|a_x|, |a_y|) <= the
-    // larger beta; same binary32 a as the exact test, no rounding of its own).
-    __device__ static __forceinline__ float score(const Consts&, float2 p, float2 q) {
+    // Prefilter score: pair_mask's lane set is within {score <= b.pre}
+    // (|a_x| <= bx and |a_y| <= by imply max(|a_x|, |a_y|) <= max(bx, by);
+    // same binary32 a as the exact test, no rounding of its own).
+    __device__ static __forceinline__ float score(float2 p, float2 q) {
         const float ax = p.x + q.x;
         const float ay = p.y + q.y;
         return __builtin_fmaxf(__builtin_fabsf(ax), __builtin_fabsf(ay));
     }
-    __device__ static __forceinline__ float bound(const Consts& c) { return c.pre_msd; }
     // Passing triplets of the surviving pair (hi, hj) over layer-2 hits
     // [o2, o2 + n2): lanes over k, the binary32 test of include/trig.h.
     template <class H>
@@ -139,7 +167,51 @@ struct MsdPrune {
     }
 };
 
+// TRIG_TEST_MSD: the basis-form partials a prune pairs with the bounds of
+// the written-out fit (a0 + a1 M), and survivors are completed with the fit
+// written out.
+struct MsdFitPrune {
+    static constexpr bool kMag = true;  // bounds grow with M >= |c_j|
+    __device__ static __forceinline__ PairBounds bounds(const Consts& c, float M) {
+        const float bx = c.fit_a0x + c.fit_a1x * M;
+        const float by = c.fit_a0y + c.fit_a1y * M;
+        return PairBounds{bx, by, __builtin_fmaxf(bx, by)};
+    }
+    __device__ static __forceinline__ float2 layer0(const Consts& c, float2 h) {
+        return MsdBasisPrune::layer0(c, h);
+    }
+    __device__ static __forceinline__ float2 layer1(const Consts& c, float2 h) {
+        return MsdBasisPrune::layer1(c, h);
+    }
+    __device__ static __forceinline__ float2 layer(const Consts& c, float2 h, int l) {
+        return MsdBasisPrune::layer(c, h, l);
+    }
+    __device__ static __forceinline__ uint64_t pair_mask(const PairBounds& b, float2 p, float2 q) {
+        return MsdBasisPrune::pair_mask(b, p, q);
+    }
+    __device__ static __forceinline__ float score(float2 p, float2 q) { return MsdBasisPrune::score(p, q); }
+    template <class H>
+    __device__ static uint32_t complete(const Consts& c, const H& hits, int hi, int hj, int o2, int n2) {
+        const float2 ci = hits.at(hi), cj = hits.at(hj);
+        const float sx01 = ci.x * c.z0 + cj.x * c.z1;
+        const float sy01 = ci.y * c.z0 + cj.y * c.z1;
+        uint32_t cnt = 0;
+        for (int k0 = 0; k0 < n2; k0 += kWave) {
+            const int k = k0 + (int)lane_id();
+            const float2 ck = k < n2 ? hits.at(o2 + k) : nan2();
+            const float qx = MsdFitTest::plane_q(c, ci.x, cj.x, sx01, ck.x, ck.x * c.z2);
+            const float qy = MsdFitTest::plane_q(c, ci.y, cj.y, sy01, ck.y, ck.y * c.z2);
+            cnt += (uint32_t)__builtin_popcountll(lanes(qx <= c.qmax_x) & lanes(qy <= c.qmax_y));
+        }
+        return cnt;
+    }
+};
+
 struct WindowPrune {
+    static constexpr bool kMag = false;
+    __device__ static __forceinline__ PairBounds bounds(const Consts& c, float) {
+        return PairBounds{c.win_x, c.win_y, c.pre_win};
+    }
     __device__ static __forceinline__ float2 layer0(const Consts& c, float2 h) {
         return make_float2(h.x / c.z0, h.y / c.z0);
     }
@@ -150,14 +222,13 @@ struct WindowPrune {
         const float z = select_uniform(l, c.z1, c.z0);
         return make_float2(h.x / z, h.y / z);
     }
-    __device__ static __forceinline__ uint64_t pair_mask(const Consts& c, float2 p, float2 q) {
-        return lanes(__builtin_fabsf(q.x - p.x) < c.win_x) & lanes(__builtin_fabsf(q.y - p.y) < c.win_y);
-    }
-    __device__ static __forceinline__ float score(const Consts&, float2 p, float2 q) {
-        return __builtin_fmaxf(__builtin_fabsf(q.x - p.x), __builtin_fabsf(q.y - p.y));
+    __device__ static __forceinline__ uint64_t pair_mask(const PairBounds& b, float2 p, float2 q) {
+        return lanes(__builtin_fabsf(q.x - p.x) < b.bx) & lanes(__builtin_fabsf(q.y - p.y) < b.by);
     }
     // |d_x| < W_x and |d_y| < W_y imply max(|d_x|, |d_y|) <= the larger window.
-    __device__ static __forceinline__ float bound(const Consts& c) { return c.pre_win; }
+    __device__ static __forceinline__ float score(float2 p, float2 q) {
+        return __builtin_fmaxf(__builtin_fabsf(q.x - p.x), __builtin_fabsf(q.y - p.y));
+    }
     template <class H>
     __device__ static uint32_t complete(const Consts& c, const H& hits, int hi, int /*hj*/, int o2, int n2) {
         const float2 ci = hits.at(hi);
@@ -187,8 +258,8 @@ struct WindowPrune {
 // multiple of 4, so one 16-byte LDS read per coordinate serves four pairs.
 // Buffer entries past the event's layer-0 hits hold NaN and fail every test.
 template <class P, class H>
-__device__ uint32_t wave_event_pruned(const Consts& c, const H& hits, int o0, int n0, int o1, int n1,
-                                      int o2, int n2, float* __restrict__ px, float* __restrict__ py) {
+__device__ uint32_t wave_event_pruned(const Consts& c, const PairBounds& pb, const H& hits, int o0, int n0, int o1,
+                                      int n1, int o2, int n2, float* __restrict__ px, float* __restrict__ py) {
     const int lane = (int)lane_id();
     const int R = uniform_i(n1 <= kWave / 2 ? min(div_small(kWave, n1), kPBuf / 4) : 1);
     const int chunk = uniform_i(div_small(kPBuf, 4 * R) * 4 * R);  // a positive multiple of 4R
@@ -224,22 +295,22 @@ __device__ uint32_t wave_event_pruned(const Consts& c, const H& hits, int o0, in
             };
             const float4* ppx = reinterpret_cast<const float4*>(px + g * T);
             const float4* ppy = reinterpret_cast<const float4*>(py + g * T);
-            const float bnd = P::bound(c);
+            const float bnd = pb.pre;
             for (int t = 0; t < T; t += 4) {
                 const float4 vx = ppx[t >> 2], vy = ppy[t >> 2];
                 // Prefilter on the vector unit: does the smallest of the four
                 // pairs' scores reach the bound?  (fmin drops NaN scores; all
                 // NaN gives NaN, which fails.)
-                const float s0 = P::score(c, make_float2(vx.x, vy.x), q);
-                const float s1 = P::score(c, make_float2(vx.y, vy.y), q);
-                const float s2 = P::score(c, make_float2(vx.z, vy.z), q);
-                const float s3 = P::score(c, make_float2(vx.w, vy.w), q);
+                const float s0 = P::score(make_float2(vx.x, vy.x), q);
+                const float s1 = P::score(make_float2(vx.y, vy.y), q);
+                const float s2 = P::score(make_float2(vx.z, vy.z), q);
+                const float s3 = P::score(make_float2(vx.w, vy.w), q);
                 const float smin = __builtin_fminf(__builtin_fminf(s0, s1), __builtin_fminf(s2, s3));
                 if (wave_any(smin <= bnd)) {
-                    finish(P::pair_mask(c, make_float2(vx.x, vy.x), q), t);
-                    finish(P::pair_mask(c, make_float2(vx.y, vy.y), q), t + 1);
-                    finish(P::pair_mask(c, make_float2(vx.z, vy.z), q), t + 2);
-                    finish(P::pair_mask(c, make_float2(vx.w, vy.w), q), t + 3);
+                    finish(P::pair_mask(pb, make_float2(vx.x, vy.x), q), t);
+                    finish(P::pair_mask(pb, make_float2(vx.y, vy.y), q), t + 1);
+                    finish(P::pair_mask(pb, make_float2(vx.z, vy.z), q), t + 2);
+                    finish(P::pair_mask(pb, make_float2(vx.w, vy.w), q), t + 3);
                 }
             }
             wave_lds_sync();
@@ -282,13 +353,12 @@ __device__ __forceinline__ void fast_setup(const Consts& c, const H& hits, int o
 // m folded with the prefilter scores of the four pairs (g T + t .. g T + t +
 // 3, j): fmin drops NaN scores; all NaN leaves m, and NaN fails every bound.
 template <class P>
-__device__ __forceinline__ float fast_fold(const Consts& c, const float4* ppx, const float4* ppy, int t, float2 q,
-                                           float m) {
+__device__ __forceinline__ float fast_fold(const float4* ppx, const float4* ppy, int t, float2 q, float m) {
     const float4 vx = ppx[t >> 2], vy = ppy[t >> 2];
-    const float s0 = P::score(c, make_float2(vx.x, vy.x), q);
-    const float s1 = P::score(c, make_float2(vx.y, vy.y), q);
-    const float s2 = P::score(c, make_float2(vx.z, vy.z), q);
-    const float s3 = P::score(c, make_float2(vx.w, vy.w), q);
+    const float s0 = P::score(make_float2(vx.x, vy.x), q);
+    const float s1 = P::score(make_float2(vx.y, vy.y), q);
+    const float s2 = P::score(make_float2(vx.z, vy.z), q);
+    const float s3 = P::score(make_float2(vx.w, vy.w), q);
     return __builtin_fminf(__builtin_fminf(__builtin_fminf(__builtin_fminf(m, s0), s1), s2), s3);
 }
 
@@ -296,8 +366,8 @@ __device__ __forceinline__ float fast_fold(const Consts& c, const float4* ppx, c
 // prefilter score reached the bound): the exact pair test per pair, then the
 // surviving pairs completed against layer 2 (layer-0 hit first).
 template <class P, class H>
-__device__ uint32_t fast_exact(const Consts& c, const H& hits, int oB, int oL, int S, int o2, int n2, int T, int g,
-                               int j, float2 q, const float* px, const float* py) {
+__device__ uint32_t fast_exact(const Consts& c, const PairBounds& pb, const H& hits, int oB, int oL, int S, int o2,
+                               int n2, int T, int g, int j, float2 q, const float* px, const float* py) {
     uint32_t cnt = 0;
     auto finish = [&](uint64_t m, int t) {
         while (m) {
@@ -312,10 +382,10 @@ __device__ uint32_t fast_exact(const Consts& c, const H& hits, int oB, int oL, i
     const float4* ppy = reinterpret_cast<const float4*>(py + g * T);
     for (int t = 0; t < T; t += 4) {
         const float4 vx = ppx[t >> 2], vy = ppy[t >> 2];
-        finish(P::pair_mask(c, make_float2(vx.x, vy.x), q), t);
-        finish(P::pair_mask(c, make_float2(vx.y, vy.y), q), t + 1);
-        finish(P::pair_mask(c, make_float2(vx.z, vy.z), q), t + 2);
-        finish(P::pair_mask(c, make_float2(vx.w, vy.w), q), t + 3);
+        finish(P::pair_mask(pb, make_float2(vx.x, vy.x), q), t);
+        finish(P::pair_mask(pb, make_float2(vx.y, vy.y), q), t + 1);
+        finish(P::pair_mask(pb, make_float2(vx.z, vy.z), q), t + 2);
+        finish(P::pair_mask(pb, make_float2(vx.w, vy.w), q), t + 3);
     }
     return cnt;
 }
@@ -326,8 +396,9 @@ __device__ uint32_t fast_exact(const Consts& c, const H& hits, int oB, int oL, i
 // once, and the prefilter minimum taken over the whole event before one
 // vote.  R, T and S come from the per-event descriptor (event_layout).
 template <class P, class H>
-__device__ uint32_t wave_event_fast(const Consts& c, const H& hits, int o0, int n0, int o1, int n1, int o2,
-                                    int n2, int R, int T, int S, float* __restrict__ px, float* __restrict__ py) {
+__device__ uint32_t wave_event_fast(const Consts& c, const PairBounds& pb, const H& hits, int o0, int n0, int o1,
+                                    int n1, int o2, int n2, int R, int T, int S, float* __restrict__ px,
+                                    float* __restrict__ py) {
     const int oB = S ? o1 : o0, nB = S ? n1 : n0;
     const int oL = S ? o0 : o1, nL = S ? n0 : n1;
     int g, j;
@@ -338,10 +409,10 @@ __device__ uint32_t wave_event_fast(const Consts& c, const H& hits, int o0, int 
     const float4* ppy = reinterpret_cast<const float4*>(py + g * T);
     float m = __builtin_nanf("");
     int t = 0;
-    for (; t + 8 <= T; t += 8) m = fast_fold<P>(c, ppx, ppy, t + 4, q, fast_fold<P>(c, ppx, ppy, t, q, m));
-    if (t < T) m = fast_fold<P>(c, ppx, ppy, t, q, m);
+    for (; t + 8 <= T; t += 8) m = fast_fold<P>(ppx, ppy, t + 4, q, fast_fold<P>(ppx, ppy, t, q, m));
+    if (t < T) m = fast_fold<P>(ppx, ppy, t, q, m);
     uint32_t cnt = 0;
-    if (wave_any(m <= P::bound(c))) cnt = fast_exact<P>(c, hits, oB, oL, S, o2, n2, T, g, j, q, px, py);
+    if (wave_any(m <= pb.pre)) cnt = fast_exact<P>(c, pb, hits, oB, oL, S, o2, n2, T, g, j, q, px, py);
     wave_lds_sync();
     return cnt;
 }
@@ -383,7 +454,10 @@ __device__ void wave_event(const Consts& c, const H& hits, int h_base, int o0, i
     if (n2 > 0 && (n01 > (int64_t)INT32_MAX || n01 * n2 > (int64_t)INT32_MAX)) {
         cnt = -2;
     } else if (n0 > 0 && n1 > 0 && n2 > 0) {
-        cnt = (int32_t)wave_event_pruned<P>(c, hits, o0 - h_base, n0, o1 - h_base, n1, o2 - h_base, n2, px, py);
+        float M = 0.0f;
+        if constexpr (P::kMag) M = layer_mag(hits, o1 - h_base, n1);
+        cnt = (int32_t)wave_event_pruned<P>(c, P::bounds(c, M), hits, o0 - h_base, n0, o1 - h_base, n1, o2 - h_base,
+                                            n2, px, py);
     }
     if (lane_id() == 0) {
         counts[e] = cnt;
@@ -401,13 +475,22 @@ __device__ void wave_event(const Consts& c, const H& hits, int h_base, int o0, i
 // The one float4 group that would cross n_hits is copied element by element
 // by thread 0.  Needs x and y 16-byte aligned (checked by the host; `vec`
 // false otherwise: plain 4-byte loads).
+// Largest |x|, |y| of a staged group (NaN ignored, infinities kept).
+__device__ __forceinline__ float mag4(float m, float a, float b, float c, float d) {
+    return __builtin_fmaxf(__builtin_fmaxf(m, __builtin_fmaxf(__builtin_fabsf(a), __builtin_fabsf(b))),
+                           __builtin_fmaxf(__builtin_fabsf(c), __builtin_fabsf(d)));
+}
+
+// Returns the largest |x|, |y| among the hits this thread staged (and a few
+// neighbours of the range: only an upper bound is needed).
 template <int HB, int NT>
-__device__ __forceinline__ void stage_hits(const float* __restrict__ x, const float* __restrict__ y,
-                                           int base, int nh, int n_hits, bool vec, float* xs, float* ys) {
+__device__ __forceinline__ float stage_hits(const float* __restrict__ x, const float* __restrict__ y,
+                                            int base, int nh, int n_hits, bool vec, float* xs, float* ys) {
     constexpr int Q = (HB + 6) / 4 / NT + 1;  // float4 groups per thread, upper bound
     const int a0 = base & ~3;
     const int nq = (base + nh - a0 + 3) >> 2;             // float4 groups to copy
     const int t = (int)threadIdx.x;
+    float mag = 0.0f;
     if (vec) {
         const int nq_full = min(nq, (n_hits - a0) >> 2);   // groups entirely below n_hits
         if (nq_full > 0) {
@@ -434,20 +517,25 @@ __device__ __forceinline__ void stage_hits(const float* __restrict__ x, const fl
                     reinterpret_cast<float4*>(xs)[q] = vx[k];
                     reinterpret_cast<float4*>(ys)[q] = vy[k];
                 }
+                mag = mag4(mag4(mag, vx[k].x, vx[k].y, vx[k].z, vx[k].w), vy[k].x, vy[k].y, vy[k].z, vy[k].w);
             }
         }
         if (t == 0 && nq_full < nq) {
             for (int g = a0 + 4 * nq_full; g < base + nh; ++g) {
                 xs[g - a0] = x[g];
                 ys[g - a0] = y[g];
+                mag = mag4(mag, x[g], y[g], 0.0f, 0.0f);
             }
         }
     } else {
         for (int h = t; h < nh; h += NT) {
-            xs[base - a0 + h] = x[base + h];
-            ys[base - a0 + h] = y[base + h];
+            const float hx = x[base + h], hy = y[base + h];
+            xs[base - a0 + h] = hx;
+            ys[base - a0 + h] = hy;
+            mag = mag4(mag, hx, hy, 0.0f, 0.0f);
         }
     }
+    return mag;
 }
 
 // LDS of the block kernels.
@@ -464,8 +552,24 @@ struct BlockLds {
     uint32_t da[kMaxEB], db[kMaxEB], dc[kMaxEB];
     int32_t soff[3 * kMaxEB + 1];
     int32_t sres[kMaxEB];
+    float wmag[NW];  // per wave: largest |x|, |y| it staged (TRIG_TEST_MSD bounds)
     int s_block, s_next, s_bad;
 };
+
+// Each wave's largest staged |x|, |y| into L.wmag (whole waves; read after
+// the next barrier by block_mag).
+template <int HB, int NW>
+__device__ __forceinline__ void publish_mag(BlockLds<HB, NW>& L, float m) {
+    const float wm = wave_max_f(m);
+    if (lane_id() == 0) L.wmag[threadIdx.x / kWave] = wm;
+}
+template <int HB, int NW>
+__device__ __forceinline__ float block_mag(const BlockLds<HB, NW>& L) {
+    float m = 0.0f;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) m = __builtin_fmaxf(m, L.wmag[w]);
+    return m;
+}
 
 // CSR checks of the block's events (offsets in L.soff); malformed events get
 // -1 here.  Returns (workgroup-uniform) whether any event was malformed.
@@ -561,6 +665,9 @@ __device__ void block_count(BlockLds<HB, NW>& L, const Consts& c, int e_first, i
     float* px = L.pbuf_x[w];
     float* py = L.pbuf_y[w];
     const LdsHits lh{L.stage_x, L.stage_y};
+    float M = 0.0f;
+    if constexpr (P::kMag) M = block_mag(L);
+    const PairBounds pb = P::bounds(c, M);
     for (int te = w; te < nsub; te += NW) {
         const uint32_t da = (uint32_t)uniform_i((int)L.da[te]);
         const uint32_t db = (uint32_t)uniform_i((int)L.db[te]);
@@ -571,8 +678,8 @@ __device__ void block_count(BlockLds<HB, NW>& L, const Consts& c, int e_first, i
         const int o1 = (int)(db & kF), n1 = (int)((db >> 13) & kF), T = (int)(db >> 26) * 4;
         const int o2 = (int)(dc & kF), n2 = (int)((dc >> 13) & kF);
         if (R == 0) continue;  // decided in the descriptor pass
-        const uint32_t cnt = T > 0 ? wave_event_fast<P>(c, lh, o0, n0, o1, n1, o2, n2, R, T, S, px, py)
-                                   : wave_event_pruned<P>(c, lh, o0, n0, o1, n1, o2, n2, px, py);
+        const uint32_t cnt = T > 0 ? wave_event_fast<P>(c, pb, lh, o0, n0, o1, n1, o2, n2, R, T, S, px, py)
+                                   : wave_event_pruned<P>(c, pb, lh, o0, n0, o1, n1, o2, n2, px, py);
         L.sres[te] = (int32_t)cnt;  // uniform: every lane stores the same value
     }
     __syncthreads();
@@ -632,7 +739,8 @@ __device__ void block_general(BlockLds<HB, NW>& L, const Consts& c, const float*
         }
         const int end = cur + nfit;
         const int nh = L.soff[3 * end] - base;
-        stage_hits<HB, NT>(x, y, base, nh, c.n_hits, vec, L.stage_x, L.stage_y);
+        const float mag = stage_hits<HB, NT>(x, y, base, nh, c.n_hits, vec, L.stage_x, L.stage_y);
+        if constexpr (P::kMag) publish_mag(L, mag);
         block_descriptors(L, cur, nfit, base & ~3);
         block_count<P>(L, c, e0 + cur, nfit, counts, accept, status);
         cur = end;
@@ -659,19 +767,21 @@ struct HitGroups {
         vy = *reinterpret_cast<const f32x4*>(y + a0 + 4 * q);
         rest.load(x, y, a0, nq_full);
     }
-    __device__ __forceinline__ void store(int nq_full, float* xs, float* ys) const {
+    // Returns the largest |x|, |y| of the groups (and m).
+    __device__ __forceinline__ float store(int nq_full, float* xs, float* ys, float m) const {
         const int q = (int)threadIdx.x + (K - 1) * NT;
         if (q < nq_full) {
             reinterpret_cast<f32x4*>(xs)[q] = vx;
             reinterpret_cast<f32x4*>(ys)[q] = vy;
         }
-        rest.store(nq_full, xs, ys);
+        m = mag4(mag4(m, vx.x, vx.y, vx.z, vx.w), vy.x, vy.y, vy.z, vy.w);
+        return rest.store(nq_full, xs, ys, m);
     }
 };
 template <int NT>
 struct HitGroups<0, NT> {
     __device__ __forceinline__ void load(const float*, const float*, int, int) {}
-    __device__ __forceinline__ void store(int, float*, float*) const {}
+    __device__ __forceinline__ float store(int, float*, float*, float m) const { return m; }
 };
 
 template <int HB, int NT>
@@ -691,15 +801,19 @@ struct HitPrefetch {
         nq_full = min(nq, (n_hits - a0) >> 2);
         if (nq_full > 0) g.load(x, y, a0, nq_full);
     }
-    __device__ __forceinline__ void store(const float* __restrict__ x, const float* __restrict__ y, int base,
-                                          int nh, float* xs, float* ys) const {
+    // Stores the block's hits; returns the largest |x|, |y| this thread
+    // stored (the groups of a block with nq_full <= 0 are not loaded: 0).
+    __device__ __forceinline__ float store(const float* __restrict__ x, const float* __restrict__ y, int base,
+                                           int nh, float* xs, float* ys) const {
         const int a0 = base & ~3;
-        g.store(nq_full, xs, ys);
+        float m = nq_full > 0 ? g.store(nq_full, xs, ys, 0.0f) : 0.0f;
         if (threadIdx.x == 0)
             for (int h = a0 + 4 * max(nq_full, 0); h < base + nh; ++h) {
                 xs[h - a0] = x[h];
                 ys[h - a0] = y[h];
+                m = mag4(m, x[h], y[h], 0.0f, 0.0f);
             }
+        return m;
     }
 };
 
@@ -731,7 +845,10 @@ __global__ __launch_bounds__(NW * kWave) void k_block(const int32_t* __restrict_
     Prefetch pf;
     if (whole) pf.issue(x, y, base, end - base, c.n_hits);
     block_check_describe(L, c, e0, ne, base & ~3, counts, accept, status);
-    if (whole) pf.store(x, y, base, end - base, L.stage_x, L.stage_y);
+    if (whole) {
+        const float mag = pf.store(x, y, base, end - base, L.stage_x, L.stage_y);
+        if constexpr (P::kMag) publish_mag(L, mag);
+    }
     __syncthreads();
     const bool bad = uniform_i(L.s_bad) != 0;
     if (whole && !bad)
@@ -808,7 +925,8 @@ __global__ __launch_bounds__(NW * kWave) void k_block_pipe(const int32_t* __rest
         if (regular) {
             const int base = L.soff[0];
             const int nh = L.soff[3 * ne] - base;
-            pf.store(x, y, base, nh, L.stage_x, L.stage_y);
+            const float mag = pf.store(x, y, base, nh, L.stage_x, L.stage_y);
+            if constexpr (P::kMag) publish_mag(L, mag);
             block_descriptors(L, 0, ne, base & ~3);
         } else {
             block_general<P>(L, c, x, y, e0, ne, bad, true, counts, accept, status);

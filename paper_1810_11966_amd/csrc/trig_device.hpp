@@ -17,24 +17,33 @@ namespace trig {
 
 constexpr int kWave = 64;
 
-// Everything a kernel needs from the parameters, derived on the host.
+// Everything a kernel needs from the parameters, derived on the host
+// (csrc/trig_bounds.hpp holds the derivations).
 struct Consts {
-    // TRIG_TEST_MSD: orthonormal basis of the plane orthogonal to (z0, z1, z2)
+    // Orthonormal basis of the plane orthogonal to (z0, z1, z2): the
+    // TRIG_TEST_MSD_BASIS evaluation, and the partial sums a, b that the
+    // pruned and binned forms of both MSD tests look at
     float U0, U1, V0, V1, V2;
-    // TRIG_TEST_MSD_FIT: layer positions and w = 1 / sum z^2
+    // TRIG_TEST_MSD (the fit written out): layer positions and w = 1 / sum z^2
     float z0, z1, z2, w;
     // MSD tests: largest binary32 Q with f32(Q / ndf) <= msd_max, per plane
     float qmax_x, qmax_y;
-    // MSD pair bound: largest binary32 b >= 0 with f32(b * b) <= qmax, per plane
+    // TRIG_TEST_MSD_BASIS pair bound: largest binary32 b >= 0 with
+    // f32(b * b) <= qmax, per plane
     float beta_x, beta_y;
+    // TRIG_TEST_MSD: a triplet that passes a plane has |a| <= a0 + a1 M and
+    // |b| <= b0 + b1 M (device evaluation order, M >= |c1| the plane's
+    // layer-1 coordinate), per plane for a, x-z plane for b
+    float fit_a0x, fit_a1x, fit_a0y, fit_a1y, fit_b0x, fit_b1x;
     // Pair prefilter of the batched form: (|u| <= bx and |v| <= by) implies
-    // max(|u|, |v|) <= max(bx, by).  MSD: the larger beta; window: the larger
-    // window.
+    // max(|u|, |v|) <= max(bx, by).  MSD_BASIS: the larger beta; window: the
+    // larger window.
     float pre_msd, pre_win;
     // TRIG_TEST_SLOPE_WINDOW
     float win_x, win_y;
-    // Binned form: half-width of the key interval around a hit's centre
-    // (MSD: the binary32 value above beta_x; window: win_x).
+    // Binned form, MSD_BASIS and window: half-width of the key interval
+    // around a hit's centre (MSD_BASIS: the binary32 value above beta_x;
+    // window: win_x).
     float bin_r;
     int32_t min_triplets;
     int32_t n_hits;
@@ -151,7 +160,8 @@ __device__ __forceinline__ uint64_t lanes(bool cmp) { return __builtin_amdgcn_ba
 // Staged padding and invalid pairs are NaN, which fails every comparison.
 // ----------------------------------------------------------------------------
 
-struct MsdTest {
+// TRIG_TEST_MSD_BASIS: Q = a^2 + b^2 in the basis (u, v).
+struct MsdBasisTest {
     static constexpr int HF = 2;
     struct Pair {
         float ax2, bx0, ay2, by0;
@@ -188,6 +198,8 @@ struct MsdTest {
     }
 };
 
+// TRIG_TEST_MSD: the fit through the vertex written out (slope, residuals,
+// their sum of squares), the paper's definition of the test.
 struct MsdFitTest {
     static constexpr int HF = 4;
     struct Pair {

@@ -27,15 +27,15 @@ from typing import Optional
 PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libtrig.so")
 
-TRIG_ABI_VERSION = 1
+TRIG_ABI_VERSION = 2
 TRIG_OK, TRIG_EINVAL, TRIG_EWORKSPACE, TRIG_EHIP, TRIG_EUNSUPPORTED = 0, -1, -2, -3, -4
 TRIG_COUNT_MALFORMED, TRIG_COUNT_OVERFLOW = -1, -2
 TRIG_STATUS_MALFORMED, TRIG_STATUS_OVERFLOW = 1, 2
-TRIG_TEST_MSD, TRIG_TEST_SLOPE_WINDOW, TRIG_TEST_MSD_FIT = 0, 1, 2
-TRIG_EXEC_PLAIN, TRIG_EXEC_PERSISTENT, TRIG_EXEC_PRUNED = 0, 1, 2
-TRIG_EXEC_BINNED, TRIG_EXEC_AUTOTUNE, TRIG_OUT_COMPACT = 4, 8, 16
+TRIG_TEST_MSD, TRIG_TEST_SLOPE_WINDOW, TRIG_TEST_MSD_BASIS = 0, 1, 2
+TRIG_EXEC_PLAIN, TRIG_EXEC_PERSISTENT, TRIG_EXEC_BINNED = 0, 1, 2
+TRIG_EXEC_AUTOTUNE, TRIG_OUT_COMPACT, TRIG_EXEC_PRUNED = 4, 8, 16
 
-TESTS = {"msd": TRIG_TEST_MSD, "window": TRIG_TEST_SLOPE_WINDOW, "msd_fit": TRIG_TEST_MSD_FIT}
+TESTS = {"msd": TRIG_TEST_MSD, "window": TRIG_TEST_SLOPE_WINDOW, "msd_basis": TRIG_TEST_MSD_BASIS}
 FORMS = {
     "plain": TRIG_EXEC_PLAIN,
     "pruned": TRIG_EXEC_PRUNED,

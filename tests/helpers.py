@@ -41,7 +41,7 @@ def near_threshold_triplets(n, seed, plane_T=0.03, ndf=2, rel=1e-3, z=(400.0, 41
     return c[:, 0], c[:, 1], c[:, 2]
 
 
-def near_threshold_events(n_events, per_layer, seed, z=(400.0, 410.0, 420.0), rel=2e-3):
+def near_threshold_events(n_events, per_layer, seed, z=(400.0, 410.0, 420.0), rel=2e-3, slope_max=0.45):
     """Events whose hits form many triplets near the MSD threshold in both
     planes: each event holds ``per_layer`` near-threshold tracks, hits of the
     same track in the same slot of each layer."""
@@ -49,8 +49,8 @@ def near_threshold_events(n_events, per_layer, seed, z=(400.0, 410.0, 420.0), re
     xs, ys, off = [], [], [0]
     for e in range(n_events):
         n = per_layer
-        xi, xj, xk = near_threshold_triplets(n, seed * 1000 + 2 * e, 0.03, 2, rel, z)
-        yi, yj, yk = near_threshold_triplets(n, seed * 1000 + 2 * e + 1, 0.025, 2, rel, z)
+        xi, xj, xk = near_threshold_triplets(n, seed * 1000 + 2 * e, 0.03, 2, rel, z, slope_max)
+        yi, yj, yk = near_threshold_triplets(n, seed * 1000 + 2 * e + 1, 0.025, 2, rel, z, slope_max)
         for cx, cy in ((xi, yi), (xj, yj), (xk, yk)):
             perm = rng.permutation(n)
             xs.append(cx[perm]); ys.append(cy[perm])
@@ -78,7 +78,7 @@ def ragged_sizes_set(sizes, seed, with_tracks=True, spread=200.0):
     return synth.from_layers(events)
 
 
-def pair_boundary_events(n_events, per_layer, seed, rel=1e-6, z=(400.0, 410.0, 420.0)):
+def pair_boundary_events(n_events, per_layer, seed, rel=1e-6, z=(400.0, 410.0, 420.0), slope_max=0.4):
     """Events whose tracks are displaced along u = (z1, -z0, 0)/|(z0, z1)|,
     the direction that changes only the layer-0/1 part a of the residual, by
     |a| within a relative ``rel`` of sqrt(ndf*T) (ndf 2): triplets sit right at
@@ -91,7 +91,7 @@ def pair_boundary_events(n_events, per_layer, seed, rel=1e-6, z=(400.0, 410.0, 4
         n = per_layer
         cx, cy = [], []
         for T, store in ((0.03, cx), (0.025, cy)):
-            m = rng.uniform(-0.4, 0.4, n)
+            m = rng.uniform(-slope_max, slope_max, n)
             r = np.sqrt(2 * T) * (1.0 + rng.uniform(-rel, rel, n)) * rng.choice([-1.0, 1.0], n)
             c = m[:, None] * z[None, :] + r[:, None] * u[None, :]
             store.append(c.astype(np.float32))
@@ -104,7 +104,7 @@ def pair_boundary_events(n_events, per_layer, seed, rel=1e-6, z=(400.0, 410.0, 4
                           np.zeros(n_events, np.int8))
 
 
-def k_boundary_events(n_events, per_layer, seed, rel=1e-6, z=(400.0, 410.0, 420.0)):
+def k_boundary_events(n_events, per_layer, seed, rel=1e-6, z=(400.0, 410.0, 420.0), slope_max=0.4):
     """Events whose tracks are displaced along the unit vector orthogonal to
     z and to (z1, -z0, 0): only the layer-2 part b of the residual changes, by
     |b| within a relative ``rel`` of sqrt(ndf*T) (ndf 2), so triplets sit
@@ -120,7 +120,7 @@ def k_boundary_events(n_events, per_layer, seed, rel=1e-6, z=(400.0, 410.0, 420.
         n = per_layer
         cs = []
         for T in (0.03, 0.025):
-            m = rng.uniform(-0.4, 0.4, n)
+            m = rng.uniform(-slope_max, slope_max, n)
             r = np.sqrt(2 * T) * (1.0 + rng.uniform(-rel, rel, n)) * rng.choice([-1.0, 1.0], n)
             cs.append((m[:, None] * z[None, :] + r[:, None] * v[None, :]).astype(np.float32))
         for l in range(3):

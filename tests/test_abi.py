@@ -83,12 +83,14 @@ def _call(p, n_events=4, n_hits=12, offsets=0x1000, x=0x2000, y=0x3000, counts=0
 
 
 @pytest.mark.parametrize("mutate,code", [
-    (lambda p: setattr(p, "abi_version", 2), trig.TRIG_EINVAL),
+    (lambda p: setattr(p, "abi_version", 1), trig.TRIG_EINVAL),
     (lambda p: setattr(p, "test", 7), trig.TRIG_EINVAL),
     (lambda p: p.z.__setitem__(1, 0.0), trig.TRIG_EINVAL),
     (lambda p: p.z.__setitem__(2, float("inf")), trig.TRIG_EINVAL),
     (lambda p: p.msd_max.__setitem__(0, -1.0), trig.TRIG_EINVAL),
     (lambda p: p.msd_max.__setitem__(1, float("nan")), trig.TRIG_EINVAL),
+    (lambda p: p.msd_max.__setitem__(0, float("inf")), trig.TRIG_EINVAL),
+    (lambda p: p.slope_window.__setitem__(1, float("inf")), trig.TRIG_EINVAL),
     (lambda p: p.slope_window.__setitem__(0, -0.1), trig.TRIG_EINVAL),
     (lambda p: setattr(p, "ndf", 0), trig.TRIG_EINVAL),
     (lambda p: setattr(p, "min_triplets", -1), trig.TRIG_EINVAL),
@@ -97,10 +99,6 @@ def _call(p, n_events=4, n_hits=12, offsets=0x1000, x=0x2000, y=0x3000, counts=0
     (lambda p: setattr(p, "flags", 1 << 20), trig.TRIG_EINVAL),
     (lambda p: setattr(p, "flags", trig.TRIG_OUT_COMPACT), trig.TRIG_EINVAL),  # no id buffers
     (lambda p: setattr(p, "flags", trig.TRIG_EXEC_PERSISTENT), trig.TRIG_EWORKSPACE),
-    (lambda p: (setattr(p, "test", trig.TRIG_TEST_MSD_FIT), setattr(p, "flags", trig.TRIG_EXEC_PRUNED)),
-     trig.TRIG_EUNSUPPORTED),
-    (lambda p: (setattr(p, "test", trig.TRIG_TEST_MSD_FIT), setattr(p, "flags", trig.TRIG_EXEC_BINNED)),
-     trig.TRIG_EUNSUPPORTED),
     (lambda p: setattr(p, "flags", trig.TRIG_EXEC_BINNED | trig.TRIG_EXEC_PRUNED), trig.TRIG_EUNSUPPORTED),
     (lambda p: setattr(p, "flags", trig.TRIG_EXEC_BINNED | trig.TRIG_EXEC_AUTOTUNE), trig.TRIG_EUNSUPPORTED),
     (lambda p: setattr(p, "flags", trig.TRIG_EXEC_BINNED | trig.TRIG_EXEC_PERSISTENT), trig.TRIG_EWORKSPACE),
@@ -187,8 +185,8 @@ def kernel_bodies(isa_text):
 
 def test_msd_kernels_have_no_fma_or_packed_fp32(isa):
     bodies = kernel_bodies(isa)
-    msd = {k: v for k, v in bodies.items() if re.search(r"Msd(Test|FitTest|Prune|Bin)", k)}
-    assert len(msd) >= 8
+    msd = {k: v for k, v in bodies.items() if re.search(r"Msd(BasisTest|FitTest|BasisPrune|FitPrune|BasisBin|FitBin)", k)}
+    assert len(msd) >= 16
     for name, body in msd.items():
         bad = re.findall(r"\b(v_fma\w*|v_fmac\w*|v_mac_f32\w*|v_mad_f32\w*|v_mad_legacy\w*|"
                          r"v_pk_(?:add|mul|fma)_f32\w*)", body)
@@ -221,7 +219,7 @@ def test_kernel_resources(isa):
     for name, d in desc.items():
         assert d["private_segment_fixed_size"] == 0, name
     binned = {k: v for k, v in desc.items() if "k_binned" in k}
-    assert len(binned) == 2
+    assert len(binned) == 3
     for name, d in binned.items():
         assert d["next_free_vgpr"] <= 80, (name, d["next_free_vgpr"])
 
@@ -235,8 +233,8 @@ def test_autotune_argument_checks(lib):
     p = trig.make_params(flags=trig.TRIG_EXEC_AUTOTUNE)
     assert trig.trig_workspace_bytes(100, p) >= 256  # block counter for stealing
     assert _call(p) == trig.TRIG_EWORKSPACE
-    fit = trig.make_params(test="msd_fit", flags=trig.TRIG_EXEC_AUTOTUNE)
-    assert trig.trig_workspace_bytes(100, fit) == 0  # brute force, no stealing
+    fit = trig.make_params(test="msd_basis", flags=trig.TRIG_EXEC_AUTOTUNE)
+    assert trig.trig_workspace_bytes(100, fit) >= 256
     ev = trig.TrigEventsCsr(1, 0x1000)
     hits = trig.TrigHits(0, None, None)
     plain = trig.make_params()

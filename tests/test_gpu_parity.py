@@ -13,13 +13,12 @@ from tests import helpers
 
 pytestmark = pytest.mark.gpu
 
-TESTS = ("msd", "msd_fit", "window")
+TESTS = ("msd", "msd_basis", "window")
 FORMS = ("plain", "persistent", "pruned", "persistent_pruned", "binned", "persistent_binned", "auto")
-EXACT_ONLY = ("pruned", "binned")  # forms without the MSD_FIT test
 
 
 def forms_for(test):
-    return [f for f in FORMS if not (test == "msd_fit" and any(t in f for t in EXACT_ONLY))]
+    return list(FORMS)
 
 
 @pytest.fixture(scope="module")
@@ -99,9 +98,7 @@ def test_golden_cases(gpu, form):
             kw["ndf"] = cfg["ndf"]
         if "window" in cfg:
             kw["slope_window"] = cfg["window"]
-        for t in ([test] if test == "window" else ["msd", "msd_fit"]):
-            if t == "msd_fit" and any(x in form for x in EXACT_ONLY):
-                continue
+        for t in ([test] if test == "window" else ["msd", "msd_basis"]):
             print(f"[golden] {case['name']} {t} {form}", flush=True)
             got = run_gpu(gpu, s, t, form, **kw)
             assert got["counts"][0] == case["expected_count"], (case["name"], t, form)
@@ -130,11 +127,12 @@ def test_pair_prune_boundary(gpu):
     pair pruning of the batched form must keep every pair that can pass."""
     s = synth.concat([helpers.pair_boundary_events(300, 6, seed=1, rel=1e-6),
                       helpers.pair_boundary_events(300, 6, seed=2, rel=3e-8)])
-    for form in FORMS:
-        c = assert_parity(gpu, s, "msd", form, "pair boundary")
-    assert c.sum() > 0
-    for form in ("plain", "persistent_pruned"):
-        assert_parity(gpu, s, "msd", form, "pair boundary ndf3", ndf=3, msd_max=(0.02, 0.016666668))
+    for test in ("msd", "msd_basis"):
+        for form in FORMS:
+            c = assert_parity(gpu, s, test, form, "pair boundary")
+        assert c.sum() > 0
+        for form in ("plain", "persistent_pruned"):
+            assert_parity(gpu, s, test, form, "pair boundary ndf3", ndf=3, msd_max=(0.02, 0.016666668))
 
 
 def test_block_shapes_and_large_events(gpu):
@@ -179,7 +177,7 @@ def test_near_threshold_other_ndf_and_thresholds(gpu):
                {"msd_max": (0.0300001, 0.0249999)}, {"min_triplets": 0}, {"min_triplets": 5}):
         for form in ("plain", "persistent_pruned"):
             assert_parity(gpu, s, "msd", form, f"ndf/threshold {kw}", **kw)
-        assert_parity(gpu, s, "msd_fit", "persistent", f"ndf/threshold {kw}", **kw)
+        assert_parity(gpu, s, "msd_basis", "persistent_pruned", f"ndf/threshold {kw}", **kw)
 
 
 def test_other_geometry(gpu):
@@ -254,13 +252,36 @@ def test_binned_key_interval_edges(gpu):
     win = synth.concat([helpers.window_boundary_events(200, 6, seed=9, rel=1e-6),
                         helpers.window_boundary_events(200, 6, seed=10, rel=3e-8)])
     for form in ("plain", "binned", "persistent_binned", "pruned"):
-        c1 = assert_parity(gpu, pair, "msd", form, "layer-1 key edge")
-        c2 = assert_parity(gpu, kb, "msd", form, "layer-2 key edge")
+        for test in ("msd", "msd_basis"):
+            c1 = assert_parity(gpu, pair, test, form, "layer-1 key edge")
+            c2 = assert_parity(gpu, kb, test, form, "layer-2 key edge")
         c3 = assert_parity(gpu, win, "window", form, "window edge")
     assert c1.sum() > 0 and c2.sum() > 0 and c3.sum() > 0
     for form in ("plain", "binned"):
-        assert_parity(gpu, kb, "msd", form, "layer-2 key edge ndf3", ndf=3, msd_max=(0.02, 0.016666668))
+        for test in ("msd", "msd_basis"):
+            assert_parity(gpu, kb, test, form, "layer-2 key edge ndf3", ndf=3, msd_max=(0.02, 0.016666668))
         assert_parity(gpu, win, "window", form, "window edge W=0.0049999", slope_window=(0.0049999, 0.0050001))
+
+
+def test_written_out_fit_far_from_axis(gpu):
+    """Tracks with slopes up to 25 and 1000 (coordinates up to ~1e4 and
+    ~4e5 cm) displaced near the cut: there the written-out fit's own rounding
+    moves Q by up to ~1e-3 of the cut, its decisions differ from the basis
+    form's for hundreds of triplets, and the pruned and binned forms' bounds
+    on a and b (which grow with the coordinates) must still keep every
+    triplet that passes."""
+    sets = []
+    for k, sm in enumerate((25.0, 1000.0)):
+        sets += [helpers.near_threshold_events(150, 8, seed=40 + k, rel=1e-3, slope_max=sm),
+                 helpers.pair_boundary_events(150, 6, seed=50 + k, rel=1e-3, slope_max=sm),
+                 helpers.k_boundary_events(150, 6, seed=60 + k, rel=1e-3, slope_max=sm)]
+    s = synth.concat(sets)
+    for test in ("msd", "msd_basis"):
+        for form in FORMS:
+            c = assert_parity(gpu, s, test, form, "far from the axis")
+        assert c.sum() > 0
+    for form in ("pruned", "binned"):
+        assert_parity(gpu, s, "msd", form, "far from the axis ndf3", ndf=3, msd_max=(0.02, 0.016666668))
 
 
 def test_special_coordinate_values(gpu):
@@ -345,38 +366,75 @@ def test_medium_1m_full_size_sampled(gpu):
     assert np.array_equal(w["counts"][:6000], c)
 
 
-@pytest.mark.parametrize("name", ["dense_100k", "mixture_4m"])
-def test_dense_and_mixture_full_size_sampled(gpu, name):
-    """The 100k-event high-multiplicity and the 4M-event mixture workloads at
-    full size, autotuned as the benchmark runs them (trig_autotune on the
-    batch, then TRIG_EXEC_AUTOTUNE calls): the autotuned result equals every
-    exact form's on all events, and the oracle checks three ranges of events
-    one by one."""
+_FULL = {}
+# Oracle ranges of the full-size checks: every event of the 100k-event
+# high-multiplicity workload (four ranges of 25k) and 250k events of the
+# 4M-event mixture (five ranges of 50k spread over the batch).
+FULL_RANGES = [("dense_100k", k * 25_000, 25_000) for k in range(4)] + \
+              [("mixture_4m", first, 50_000) for first in (0, 1_000_000, 2_000_000, 3_000_000, 3_950_000)]
+
+
+def full_size_results(torch, name):
+    """The 100k-event high-multiplicity or the 4M-event mixture workload at
+    full size: autotuned as the benchmark runs it (trig_autotune on the batch,
+    then TRIG_EXEC_AUTOTUNE calls), and every other form, brute force
+    included, on the same device buffers.  Computed once per module."""
+    if name in _FULL:
+        return _FULL[name]
     from paper_1810_11966_amd import trig
     s = synth.make_event_set(synth.WORKLOADS[name])
     print(f"[full] {name} generated events={s.n_events} hits={s.n_hits}", flush=True)
-    off, x, y = to_dev(gpu, s)
+    off, x, y = to_dev(torch, s)
     trig.trig_autotune_reset()
     r, info = trig.autotune(off, x, y, test="msd", reps=1, compact=True, want_status=True)
-    gpu.cuda.synchronize()
+    torch.cuda.synchronize()
     print(f"[full] {name} autotuned binned={info.binned} persistent={info.persistent} "
           f"shape={info.block_hits},{info.block_waves},{info.block_events}", flush=True)
-    auto = run_gpu(gpu, s, "msd", "auto")
-    assert np.array_equal(r.counts.cpu().numpy(), auto["counts"])
-    for form in ("pruned", "persistent_pruned", "binned", "persistent_binned"):
+    tuned = r.counts.cpu().numpy()
+    del r
+    res = {}
+    for form in FORMS:
         print(f"[full] {name} form={form}", flush=True)
-        got = run_gpu(gpu, s, "msd", form)
-        assert np.array_equal(got["counts"], auto["counts"]), form
-        assert np.array_equal(got["ids"], auto["ids"]), form
-    assert np.array_equal(auto["ids"], np.flatnonzero(auto["accept"]))
-    assert auto["status"] == 0 and auto["ids"].size > 0
-    size = 300 if name == "dense_100k" else 5000
-    for first in (0, s.n_events // 2, s.n_events - size):
-        sub = s.subset(first, size)
-        c, a, _, _ = R.select_set(sub, n_threads=THREADS)
-        assert np.array_equal(auto["counts"][first:first + size], c), (name, first)
-        assert np.array_equal(auto["accept"][first:first + size], a), (name, first)
+        g = trig.select(off, x, y, test="msd", form=form, compact=True, want_status=True)
+        torch.cuda.synchronize()
+        n = int(g.n_accepted.cpu().numpy()[0])
+        res[form] = {"counts": g.counts.cpu().numpy(), "accept": g.accept.cpu().numpy(),
+                     "ids": g.ids.cpu().numpy()[:n], "status": int(g.status.cpu().numpy()[0])}
+        del g
+    del off, x, y
+    torch.cuda.empty_cache()
     trig.trig_autotune_reset()
+    _FULL[name] = (s, tuned, res)
+    return _FULL[name]
+
+
+@pytest.mark.parametrize("name", ["dense_100k", "mixture_4m"])
+def test_dense_and_mixture_full_size_all_forms(gpu, name):
+    """At full size, every form equals GPU brute force (the plain one-wave-
+    per-event kernel) on every event: counts, flags and accepted ids; the
+    autotuned record's result too."""
+    s, tuned, res = full_size_results(gpu, name)
+    base = res["plain"]
+    assert base["status"] == 0 and base["ids"].size > 0
+    assert np.array_equal(base["ids"], np.flatnonzero(base["accept"]))
+    assert np.array_equal(tuned, base["counts"])
+    for form, r in res.items():
+        assert np.array_equal(r["counts"], base["counts"]), form
+        assert np.array_equal(r["accept"], base["accept"]), form
+        assert np.array_equal(r["ids"], base["ids"]), form
+
+
+@pytest.mark.parametrize("name,first,size", FULL_RANGES)
+def test_dense_and_mixture_full_size_oracle(gpu, name, first, size):
+    """The full-size GPU results against the oracle, event by event, over
+    the ranges above (all 100k high-multiplicity events; 250k mixture events)."""
+    s, tuned, res = full_size_results(gpu, name)
+    sub = s.subset(first, size)
+    print(f"[full] {name} oracle events [{first}, {first + size})", flush=True)
+    c, a, _, _ = R.select_set(sub, n_threads=THREADS)
+    for form in ("auto", "plain"):
+        assert np.array_equal(res[form]["counts"][first:first + size], c), (name, form, first)
+        assert np.array_equal(res[form]["accept"][first:first + size], a), (name, form, first)
 
 
 def test_compaction_both_launch_paths(gpu):
@@ -417,20 +475,16 @@ def test_autotune_records_and_matches_oracle(gpu, test):
     assert np.array_equal(r.accept.cpu().numpy(), a)
     n = int(r.n_accepted.cpu().numpy()[0])
     assert np.array_equal(r.ids.cpu().numpy()[:n], R.accepted_ids(a))
-    if test == "msd_fit":
-        assert info.n_candidates == 0
+    assert info.n_candidates == 1 + 3 * 2 * 4 * 2 + 2
+    assert 0 < info.ms_best <= info.ms_rule
+    if info.binned:
+        assert info.block_hits == 0
     else:
-        assert info.n_candidates == 1 + 3 * 2 * 4 * 2 + 2
-        assert 0 < info.ms_best <= info.ms_rule
-        if info.binned:
-            assert info.block_hits == 0
-        else:
-            assert info.block_hits in (1024, 2048, 4096) and info.block_waves in (1, 2, 4)
-            assert 1 <= info.block_events <= 128
+        assert info.block_hits in (1024, 2048, 4096) and info.block_waves in (1, 2, 4)
+        assert 1 <= info.block_events <= 128
     # later autotuned calls use the record; explicit block fields still win
     assert_parity(gpu, s, test, "auto", "autotuned")
-    if test != "msd_fit":
-        assert_parity(gpu, s, test, "auto", "autotuned+explicit", block_hits=1024, block_waves=1,
-                      block_events=3)
+    assert_parity(gpu, s, test, "auto", "autotuned+explicit", block_hits=1024, block_waves=1,
+                  block_events=3)
     trig.trig_autotune_reset()
     assert_parity(gpu, s, test, "auto", "rule after reset")

@@ -386,3 +386,14 @@ def test_evaluation_orders_can_disagree(oracle_lib):
     # an event whose counts differ has disagreeing triplets
     assert ((c_fit != c_basis) <= (d > 0)).all()
     assert (np.abs(c_fit.astype(np.int64) - c_basis) <= d).all()
+
+
+def test_evaluation_orders_disagree_far_from_axis(oracle_lib):
+    """Far from the axis (slopes up to 25 and 1000, coordinates up to ~4e5 cm)
+    the written-out fit's rounding moves Q by up to ~1e-3 of the cut: hundreds
+    of near-cut triplets are decided differently by the two orders, so the GPU
+    parity sets built this way tell the two tests apart."""
+    for k, sm in enumerate((25.0, 1000.0)):
+        s = helpers.near_threshold_events(150, 8, seed=40 + k, rel=1e-3, slope_max=sm)
+        d = R.msd_disagreements(s.offsets, s.x, s.y, n_threads=4)
+        assert d.sum() > 100, (sm, int(d.sum()))
