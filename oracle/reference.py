@@ -20,6 +20,8 @@ Contents
   * ``fp32_fit_error_bound``     a rigorous bound on |Q_fp32 - Q_exact| for the
                                  default (fit written out) evaluation.
   * ``fp32_error_bound``         the same for the basis-form evaluation.
+  * ``disjoint_accept``          two-particle acceptance: two passing triplets
+                                 with no hit in common (Sec. 3.1).
   * ``accepted_ids``             ascending ids of accepted events.
   * ``filter_stations``          trigger-station filtering, the step before the
                                  selection: per event the hits of the three
@@ -127,6 +129,11 @@ def _load():
         lib.trig_ref_msd_disagreements.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p,
                                                    ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                                    ctypes.POINTER(_Cfg), ctypes.c_void_p]
+        lib.trig_ref_disjoint.restype = ctypes.c_int64
+        lib.trig_ref_disjoint.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Cfg), ctypes.c_void_p]
+        lib.oracle_has_disjoint_pair.restype = ctypes.c_int32
+        lib.oracle_has_disjoint_pair.argtypes = [ctypes.c_int64, ctypes.c_void_p]
         lib.oracle_triplet_msd.restype = ctypes.c_float
         lib.oracle_triplet_msd.argtypes = [ctypes.POINTER(_Cfg), ctypes.c_float,
                                            ctypes.c_float, ctypes.c_float]
@@ -193,6 +200,43 @@ def msd_disagreements(offsets, x, y, cfg: OracleConfig = OracleConfig(), n_threa
     with ThreadPoolExecutor(n_threads) as ex:
         list(ex.map(run, range(len(bounds) - 1)))
     return out
+
+
+def disjoint_accept(offsets, x, y, cfg: OracleConfig = OracleConfig(), n_threads: int = 1):
+    """Two-particle acceptance per event (uint8[E]): 1 if two of the event's
+    passing triplets have no hit in common (the trigger signature of Sec. 3.1,
+    two particles pointing back to the target), else 0.  The passing triplets
+    are listed and every pair compared (trig_ref_disjoint)."""
+    from concurrent.futures import ThreadPoolExecutor
+    lib = _load()
+    off = np.ascontiguousarray(offsets, dtype=np.int32)
+    xs = np.ascontiguousarray(x, dtype=np.float32)
+    ys = np.ascontiguousarray(y, dtype=np.float32)
+    n_ev = (len(off) - 1) // 3
+    out = np.zeros(n_ev, np.uint8)
+    c = _to_c(cfg)
+    n_threads = max(1, int(n_threads))
+    bounds = np.linspace(0, n_ev, 4 * n_threads + 1).astype(np.int64)
+
+    def run(k):
+        e0, e1 = int(bounds[k]), int(bounds[k + 1])
+        if e1 > e0:
+            part = out[e0:e1]
+            r = lib.trig_ref_disjoint(e0, e1, _ptr(off), len(xs), _ptr(xs), _ptr(ys), ctypes.byref(c),
+                                      part.ctypes.data_as(ctypes.c_void_p))
+            if r < 0:
+                raise ValueError("trig_ref_disjoint rejected its arguments")
+
+    with ThreadPoolExecutor(n_threads) as ex:
+        list(ex.map(run, range(len(bounds) - 1)))
+    return out
+
+
+def has_disjoint_pair(triplets) -> bool:
+    """Whether a list of (i, j, k) hit-index triplets holds two with no hit
+    in common (the oracle's pair comparison)."""
+    t = np.ascontiguousarray(np.asarray(triplets, dtype=np.int64).reshape(-1, 3))
+    return bool(_load().oracle_has_disjoint_pair(len(t), t.ctypes.data_as(ctypes.c_void_p)))
 
 
 def triplet_msd_c(cfg: OracleConfig, ci: float, cj: float, ck: float) -> float:

@@ -285,3 +285,76 @@ int64_t trig_ref_msd_disagreements(int64_t e0, int64_t e1, const int32_t *off, i
     }
     return total;
 }
+
+/* Whether triplets t and u (hit indices i, j, k in layers 0, 1, 2) have no
+ * hit in common. */
+static int no_common_hit(const int64_t *t, const int64_t *u) {
+    return t[0] != u[0] && t[1] != u[1] && t[2] != u[2];
+}
+
+/* 1 if the list of n triplets (3 hit indices each) holds two with no hit in
+ * common, else 0: every pair is compared.  For pin tests as well. */
+int32_t oracle_has_disjoint_pair(int64_t n, const int64_t *trip) {
+    for (int64_t a = 0; a < n; ++a)
+        for (int64_t b = a + 1; b < n; ++b)
+            if (no_common_hit(trip + 3 * a, trip + 3 * b)) return 1;
+    return 0;
+}
+
+/* Two-particle acceptance (the trigger signature of Sec. 3.1: two particles
+ * in the trigger station pointing back to the target): for events [e0, e1),
+ * out[e - e0] = 1 if the event's passing triplets (the test of cfg, as in
+ * trig_select_ref) include two with no hit in common, else 0; malformed
+ * events and events whose triplet count int32 cannot hold get 0.  The
+ * passing triplets are listed, then every pair of them compared.  Returns
+ * the number of accepted events, or -1 on bad arguments or memory.  One
+ * thread; callers split the event range. */
+int64_t trig_ref_disjoint(int64_t e0, int64_t e1, const int32_t *off, int32_t n_hits, const float *x,
+                          const float *y, const oracle_cfg *cfg, uint8_t *out) {
+    if (e0 < 0 || e1 < e0 || (e1 > e0 && (!off || !out)) || !cfg) return -1;
+    oracle_consts k;
+    make_consts(cfg, &k);
+    const float ndf = (float)cfg->ndf;
+    int64_t cap = 0, accepted = 0;
+    int64_t *trip = NULL;
+    for (int64_t e = e0; e < e1; ++e) {
+        int64_t o0 = off[3 * e], o1 = off[3 * e + 1], o2 = off[3 * e + 2], o3 = off[3 * e + 3];
+        int ok = 0 <= o0 && o0 <= o1 && o1 <= o2 && o2 <= o3 && o3 <= n_hits;
+        if (ok && (o3 - o2) > 0 && (o1 - o0) * (o2 - o1) > (int64_t)INT32_MAX / (o3 - o2)) ok = 0;
+        int64_t n = 0;
+        if (ok)
+            for (int64_t i = o0; i < o1; ++i)
+                for (int64_t j = o1; j < o2; ++j)
+                    for (int64_t kk = o2; kk < o3; ++kk) {
+                        int pass;
+                        if (cfg->test == OR_TEST_WINDOW) {
+                            pass = plane_window(x[i], x[j], x[kk], &k, cfg->window[0]) &&
+                                   plane_window(y[i], y[j], y[kk], &k, cfg->window[1]);
+                        } else if (cfg->test == OR_TEST_MSD_BASIS) {
+                            pass = plane_msd(x[i], x[j], x[kk], &k, cfg->msd_max[0], ndf) &&
+                                   plane_msd(y[i], y[j], y[kk], &k, cfg->msd_max[1], ndf);
+                        } else {
+                            pass = plane_fit(x[i], x[j], x[kk], &k, cfg->msd_max[0], ndf) &&
+                                   plane_fit(y[i], y[j], y[kk], &k, cfg->msd_max[1], ndf);
+                        }
+                        if (!pass) continue;
+                        if (n == cap) {
+                            cap = cap ? 2 * cap : 64;
+                            int64_t *grown = (int64_t *)realloc(trip, (size_t)cap * 3 * sizeof(int64_t));
+                            if (!grown) {
+                                free(trip);
+                                return -1;
+                            }
+                            trip = grown;
+                        }
+                        trip[3 * n] = i;
+                        trip[3 * n + 1] = j;
+                        trip[3 * n + 2] = kk;
+                        ++n;
+                    }
+        out[e - e0] = (uint8_t)oracle_has_disjoint_pair(n, trip);
+        accepted += out[e - e0];
+    }
+    free(trip);
+    return accepted;
+}

@@ -397,3 +397,76 @@ def test_evaluation_orders_disagree_far_from_axis(oracle_lib):
         s = helpers.near_threshold_events(150, 8, seed=40 + k, rel=1e-3, slope_max=sm)
         d = R.msd_disagreements(s.offsets, s.x, s.y, n_threads=4)
         assert d.sum() > 100, (sm, int(d.sum()))
+
+
+# ------------------------------------------ two-particle (disjoint) acceptance ---
+
+def _track(m, z=(400.0, 410.0, 420.0), dx=(0.0, 0.0, 0.0)):
+    """Hits of a straight line through the vertex with slopes m = (mx, my),
+    one per layer, x displaced by dx per layer (cm)."""
+    return [(float(np.float32(m[0] * zl + d)), float(np.float32(m[1] * zl))) for zl, d in zip(z, dx)]
+
+
+def test_disjoint_pair_definition_on_index_lists(oracle_lib):
+    """Hand-built triplet lists (hit indices per layer): two triplets count as
+    two particles only if they differ in every layer's hit."""
+    cases = [
+        ([], False),
+        ([(0, 0, 0)], False),
+        ([(0, 0, 0), (1, 1, 1)], True),
+        ([(0, 0, 0), (0, 1, 1)], False),                       # shared layer-0 hit
+        ([(0, 0, 0), (1, 0, 1)], False),                       # shared layer-1 hit
+        ([(0, 0, 0), (1, 1, 0)], False),                       # shared layer-2 hit
+        ([(0, 0, 0), (0, 1, 1), (1, 0, 1)], False),            # pairwise sharing, no common hit
+        ([(0, 0, 0), (0, 1, 1), (1, 0, 1), (1, 1, 0)], False),
+        ([(0, 0, 0), (0, 1, 1), (1, 0, 1), (1, 1, 0), (1, 1, 1)], True),
+        ([(5, 7, 9)] * 3 + [(6, 8, 10)], True),
+    ]
+    for trips, want in cases:
+        assert R.has_disjoint_pair(trips) == want, trips
+
+
+def test_disjoint_acceptance_hand_built_events(oracle_lib):
+    """Events with known passing triplets (exact vertex tracks, cross
+    combinations far off any line): the count mode and the two-particle mode
+    differ exactly where the passing triplets share a hit."""
+    a, b = (0.1, 0.05), (-0.2, 0.15)
+    ta, tb = _track(a), _track(b)
+    near = _track(a, dx=(0.0, 0.0, 0.05))  # 0.05 cm off the line in layer 2: still passes
+    events = {
+        "one track": ([[ta[0]], [ta[1]], [ta[2]]], 1, 0),
+        "two tracks": ([[ta[0], tb[0]], [tb[1], ta[1]], [ta[2], tb[2]]], 2, 1),
+        "track and a near layer-2 hit": ([[ta[0]], [ta[1]], [ta[2], near[2]]], 2, 0),
+        "track, hits duplicated": ([[ta[0]] * 2, [ta[1]] * 2, [ta[2]] * 2], 8, 1),
+        "track, layer 0 duplicated": ([[ta[0]] * 2, [ta[1]], [ta[2]]], 2, 0),
+        "two near hits in layers 0 and 2 around one layer-1 hit":
+            ([[ta[0], _track(a, dx=(0.04, 0, 0))[0]], [ta[1]], [ta[2], near[2]]], 4, 0),
+        "two tracks, one duplicated": ([[ta[0], tb[0], tb[0]], [tb[1], ta[1], tb[1]], [ta[2], tb[2]]], 5, 1),
+    }
+    s = synth.from_layers([v[0] for v in events.values()])
+    c, acc, _, _ = R.select_set(s)
+    d = R.disjoint_accept(s.offsets, s.x, s.y)
+    for k, (name, (_, want_c, want_d)) in enumerate(events.items()):
+        assert c[k] == want_c, (name, c[k])
+        assert d[k] == want_d, (name, d[k])
+    assert (d <= acc).all()  # two particles need at least two triplets
+
+
+@pytest.mark.parametrize("test", ["msd", "msd_basis", "window"])
+def test_disjoint_acceptance_invariants(oracle_lib, test):
+    """On events with many passing triplets (sigma = 0 pairs, hits
+    duplicated): two-particle acceptance implies two passing triplets, does
+    not depend on the order of the hits within a layer, and equals the count
+    mode on events whose passing triplets are two exact tracks."""
+    base = synth.make_event_set(synth.EventSetSpec(n_events=3000, hits_mean=6, p_inject=0.5, sigma=0.0, salt=91))
+    cfg = R.OracleConfig(test=test)
+    c, _, _, _ = R.select_set(base, cfg)
+    d = R.disjoint_accept(base.offsets, base.x, base.y, cfg)
+    assert ((d == 1) <= (c >= 2)).all()
+    assert d.sum() > 100
+    rng = np.random.default_rng(3)
+    perm = np.arange(base.n_hits)
+    for q in range(3 * base.n_events):
+        lo, hi = base.offsets[q], base.offsets[q + 1]
+        perm[lo:hi] = lo + rng.permutation(hi - lo)
+    assert np.array_equal(R.disjoint_accept(base.offsets, base.x[perm], base.y[perm], cfg), d)
