@@ -120,6 +120,11 @@ def _load():
         if not os.path.exists(LIB):
             build()
         lib = ctypes.CDLL(LIB)
+        lib.trig_select_ref_z.restype = ctypes.c_double
+        lib.trig_select_ref_z.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32, ctypes.c_void_p,
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Cfg),
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint32),
+                                          ctypes.c_int32]
         lib.trig_select_ref.restype = ctypes.c_double
         lib.trig_select_ref.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_int32,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Cfg),
@@ -131,7 +136,8 @@ def _load():
                                                    ctypes.POINTER(_Cfg), ctypes.c_void_p]
         lib.trig_ref_disjoint.restype = ctypes.c_int64
         lib.trig_ref_disjoint.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_void_p, ctypes.c_int32,
-                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Cfg), ctypes.c_void_p]
+                                          ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(_Cfg),
+                                          ctypes.c_void_p]
         lib.oracle_has_disjoint_pair.restype = ctypes.c_int32
         lib.oracle_has_disjoint_pair.argtypes = [ctypes.c_int64, ctypes.c_void_p]
         lib.oracle_triplet_msd.restype = ctypes.c_float
@@ -147,8 +153,9 @@ def _ptr(a: np.ndarray):
     return a.ctypes.data_as(ctypes.c_void_p) if a.size else None
 
 
-def select(offsets, x, y, cfg: OracleConfig = OracleConfig(), n_threads: int = 1):
-    """C oracle over a CSR batch.
+def select(offsets, x, y, cfg: OracleConfig = OracleConfig(), n_threads: int = 1, z=None):
+    """C oracle over a CSR batch (z: per-hit z positions, or None for the
+    configured layer positions).
 
     Returns (counts int32[E], accept uint8[E], status uint32, seconds).
     counts[e] is the number of passing triplets, -1 for a malformed layer
@@ -157,20 +164,21 @@ def select(offsets, x, y, cfg: OracleConfig = OracleConfig(), n_threads: int = 1
     off = np.ascontiguousarray(offsets, dtype=np.int32)
     xs = np.ascontiguousarray(x, dtype=np.float32)
     ys = np.ascontiguousarray(y, dtype=np.float32)
+    zs = None if z is None else np.ascontiguousarray(z, dtype=np.float32)
     n_ev = (len(off) - 1) // 3
     counts = np.zeros(n_ev, np.int32)
     accept = np.zeros(n_ev, np.uint8)
     st = ctypes.c_uint32(0)
     c = _to_c(cfg)
-    dt = lib.trig_select_ref(n_ev, _ptr(off), len(xs), _ptr(xs), _ptr(ys), ctypes.byref(c),
-                           _ptr(counts), _ptr(accept), ctypes.byref(st), int(n_threads))
+    dt = lib.trig_select_ref_z(n_ev, _ptr(off), len(xs), _ptr(xs), _ptr(ys), None if zs is None else _ptr(zs),
+                               ctypes.byref(c), _ptr(counts), _ptr(accept), ctypes.byref(st), int(n_threads))
     if dt < 0:
         raise ValueError("trig_select_ref rejected its arguments")
     return counts, accept, int(st.value), float(dt)
 
 
 def select_set(evset, cfg: OracleConfig = OracleConfig(), n_threads: int = 1):
-    return select(evset.offsets, evset.x, evset.y, cfg, n_threads)
+    return select(evset.offsets, evset.x, evset.y, cfg, n_threads, z=getattr(evset, "z", None))
 
 
 def msd_disagreements(offsets, x, y, cfg: OracleConfig = OracleConfig(), n_threads: int = 1):
@@ -202,7 +210,7 @@ def msd_disagreements(offsets, x, y, cfg: OracleConfig = OracleConfig(), n_threa
     return out
 
 
-def disjoint_accept(offsets, x, y, cfg: OracleConfig = OracleConfig(), n_threads: int = 1):
+def disjoint_accept(offsets, x, y, cfg: OracleConfig = OracleConfig(), n_threads: int = 1, z=None):
     """Two-particle acceptance per event (uint8[E]): 1 if two of the event's
     passing triplets have no hit in common (the trigger signature of Sec. 3.1,
     two particles pointing back to the target), else 0.  The passing triplets
@@ -212,6 +220,7 @@ def disjoint_accept(offsets, x, y, cfg: OracleConfig = OracleConfig(), n_threads
     off = np.ascontiguousarray(offsets, dtype=np.int32)
     xs = np.ascontiguousarray(x, dtype=np.float32)
     ys = np.ascontiguousarray(y, dtype=np.float32)
+    zs = None if z is None else np.ascontiguousarray(z, dtype=np.float32)
     n_ev = (len(off) - 1) // 3
     out = np.zeros(n_ev, np.uint8)
     c = _to_c(cfg)
@@ -222,7 +231,8 @@ def disjoint_accept(offsets, x, y, cfg: OracleConfig = OracleConfig(), n_threads
         e0, e1 = int(bounds[k]), int(bounds[k + 1])
         if e1 > e0:
             part = out[e0:e1]
-            r = lib.trig_ref_disjoint(e0, e1, _ptr(off), len(xs), _ptr(xs), _ptr(ys), ctypes.byref(c),
+            r = lib.trig_ref_disjoint(e0, e1, _ptr(off), len(xs), _ptr(xs), _ptr(ys),
+                                      None if zs is None else _ptr(zs), ctypes.byref(c),
                                       part.ctypes.data_as(ctypes.c_void_p))
             if r < 0:
                 raise ValueError("trig_ref_disjoint rejected its arguments")
@@ -356,7 +366,7 @@ def fit_msd_f64(ci, cj, ck, z, ndf):
     return q / ndf
 
 
-def fp32_fit_error_bound(ci, cj, ck, z):
+def fp32_fit_error_bound(ci, cj, ck, z, w_division=False):
     """Upper bound on |Q_fp32 - Q_exact| for the default evaluation (the fit
     written out), before the division by ndf, vectorised over triplets of
     finite binary32 inputs whose intermediate results stay finite.
@@ -383,7 +393,9 @@ def fp32_fit_error_bound(ci, cj, ck, z):
     zf = [float(np.float32(v)) for v in z]
     z32 = [np.float32(v) for v in z]
     szz32 = (z32[0] * z32[0] + z32[1] * z32[1]) + z32[2] * z32[2]
-    w32 = np.float32(1.0 / float(szz32))
+    # w as the evaluation takes it: f32(1 / f64(Szz)) for layer positions, a
+    # binary32 division for per-hit z (w_division)
+    w32 = np.float32(1.0) / szz32 if w_division else np.float32(1.0 / float(szz32))
     S_exact = sum(Fraction(v) ** 2 for v in zf)
     e_w = float(abs(Fraction(float(w32)) * S_exact - 1))
     S = float(S_exact)

@@ -101,14 +101,56 @@ static int plane_fit(float ci, float cj, float ck, const oracle_consts *k, float
     return msd <= T;
 }
 
+/* One plane of the MSD test when every hit carries its own z (staggered
+ * detector modules, Sec. 3.2 last paragraph): the same fit, with the sum of
+ * squares of the triplet's own z and its reciprocal taken per triplet (one
+ * binary32 division). */
+static int plane_fit_z(float ci, float cj, float ck, float zi, float zj, float zk, float T, float ndf) {
+    float szz = (zi * zi + zj * zj) + zk * zk;
+    float w = 1.0f / szz;
+    float m = ((ci * zi + cj * zj) + ck * zk) * w;
+    float r0 = ci - m * zi;
+    float r1 = cj - m * zj;
+    float r2 = ck - m * zk;
+    float q = (r0 * r0 + r1 * r1) + r2 * r2;
+    float msd = q / ndf;
+    return msd <= T;
+}
+
+/* One plane of the slope-window test with per-hit z. */
+static int plane_window_z(float ci, float cj, float ck, float zi, float zj, float zk, float W) {
+    float si = ci / zi, sj = cj / zj, sk = ck / zk;
+    return fabsf(sj - si) < W && fabsf(sk - si) < W;
+}
+
 /* One plane of the slope-window test. */
 static int plane_window(float ci, float cj, float ck, const oracle_consts *k, float W) {
     float si = ci / k->zf[0], sj = cj / k->zf[1], sk = ck / k->zf[2];
     return fabsf(sj - si) < W && fabsf(sk - si) < W;
 }
 
+/* Whether triplet (i, j, kk) passes both planes of the configured test;
+ * z (may be NULL) holds per-hit z positions. */
+static int triplet_passes(const oracle_cfg *c, const oracle_consts *k, const float *x, const float *y,
+                          const float *z, int64_t i, int64_t j, int64_t kk) {
+    const float ndf = (float)c->ndf;
+    if (z) {
+        if (c->test == OR_TEST_WINDOW)
+            return plane_window_z(x[i], x[j], x[kk], z[i], z[j], z[kk], c->window[0]) &&
+                   plane_window_z(y[i], y[j], y[kk], z[i], z[j], z[kk], c->window[1]);
+        return plane_fit_z(x[i], x[j], x[kk], z[i], z[j], z[kk], c->msd_max[0], ndf) &&
+               plane_fit_z(y[i], y[j], y[kk], z[i], z[j], z[kk], c->msd_max[1], ndf);
+    }
+    if (c->test == OR_TEST_WINDOW)
+        return plane_window(x[i], x[j], x[kk], k, c->window[0]) && plane_window(y[i], y[j], y[kk], k, c->window[1]);
+    if (c->test == OR_TEST_MSD_BASIS)
+        return plane_msd(x[i], x[j], x[kk], k, c->msd_max[0], ndf) &&
+               plane_msd(y[i], y[j], y[kk], k, c->msd_max[1], ndf);
+    return plane_fit(x[i], x[j], x[kk], k, c->msd_max[0], ndf) && plane_fit(y[i], y[j], y[kk], k, c->msd_max[1], ndf);
+}
+
 static int32_t event_count(const oracle_cfg *c, const oracle_consts *k, const int32_t *off,
-                           int64_t e, int32_t n_hits, const float *x, const float *y,
+                           int64_t e, int32_t n_hits, const float *x, const float *y, const float *z,
                            uint32_t *status) {
     int64_t o0 = off[3 * e], o1 = off[3 * e + 1], o2 = off[3 * e + 2], o3 = off[3 * e + 3];
     if (!(0 <= o0 && o0 <= o1 && o1 <= o2 && o2 <= o3 && o3 <= n_hits)) {
@@ -121,24 +163,10 @@ static int32_t event_count(const oracle_cfg *c, const oracle_consts *k, const in
         *status |= 2u;
         return -2;
     }
-    const float ndf = (float)c->ndf;
     int32_t cnt = 0;
     for (int64_t i = o0; i < o1; ++i)
         for (int64_t j = o1; j < o2; ++j)
-            for (int64_t kk = o2; kk < o3; ++kk) {
-                int pass;
-                if (c->test == OR_TEST_WINDOW) {
-                    pass = plane_window(x[i], x[j], x[kk], k, c->window[0]) &&
-                           plane_window(y[i], y[j], y[kk], k, c->window[1]);
-                } else if (c->test == OR_TEST_MSD_BASIS) {
-                    pass = plane_msd(x[i], x[j], x[kk], k, c->msd_max[0], ndf) &&
-                           plane_msd(y[i], y[j], y[kk], k, c->msd_max[1], ndf);
-                } else {
-                    pass = plane_fit(x[i], x[j], x[kk], k, c->msd_max[0], ndf) &&
-                           plane_fit(y[i], y[j], y[kk], k, c->msd_max[1], ndf);
-                }
-                cnt += pass;
-            }
+            for (int64_t kk = o2; kk < o3; ++kk) cnt += triplet_passes(c, k, x, y, z, i, j, kk);
     return cnt;
 }
 
@@ -147,7 +175,7 @@ typedef struct {
     const oracle_consts *k;
     const int32_t *off;
     int32_t n_hits;
-    const float *x, *y;
+    const float *x, *y, *z;
     int32_t *counts;
     uint8_t *accept;
     int64_t e0, e1;
@@ -158,7 +186,7 @@ static void *worker(void *p) {
     worker_arg *a = (worker_arg *)p;
     uint32_t st = 0;
     for (int64_t e = a->e0; e < a->e1; ++e) {
-        int32_t cnt = event_count(a->cfg, a->k, a->off, e, a->n_hits, a->x, a->y, &st);
+        int32_t cnt = event_count(a->cfg, a->k, a->off, e, a->n_hits, a->x, a->y, a->z, &st);
         a->counts[e] = cnt;
         a->accept[e] = (uint8_t)(cnt >= 0 && cnt >= a->cfg->min_triplets);
     }
@@ -187,17 +215,31 @@ static int64_t event_cost(const int32_t *off, int64_t e) {
  * compute time in seconds (thread start to join), or a negative value on bad
  * arguments.  *status receives the OR of per-event error bits (1 malformed
  * CSR range, 2 triplet count not representable in int32). */
+double trig_select_ref_z(int32_t n_events, const int32_t *off, int32_t n_hits, const float *x,
+                         const float *y, const float *z, const oracle_cfg *cfg, int32_t *counts,
+                         uint8_t *accept, uint32_t *status, int32_t n_threads);
+
 double trig_select_ref(int32_t n_events, const int32_t *off, int32_t n_hits, const float *x,
                        const float *y, const oracle_cfg *cfg, int32_t *counts, uint8_t *accept,
                        uint32_t *status, int32_t n_threads) {
+    return trig_select_ref_z(n_events, off, n_hits, x, y, NULL, cfg, counts, accept, status, n_threads);
+}
+
+/* trig_select_ref with per-hit z positions (z: n_hits floats, or NULL for
+ * the configured layer positions).  The basis-form test is not defined for
+ * per-hit z (-1). */
+double trig_select_ref_z(int32_t n_events, const int32_t *off, int32_t n_hits, const float *x,
+                         const float *y, const float *z, const oracle_cfg *cfg, int32_t *counts,
+                         uint8_t *accept, uint32_t *status, int32_t n_threads) {
     if (n_events < 0 || (n_events > 0 && (!off || !counts || !accept)) || !cfg || !status)
         return -1.0;
+    if (z && cfg->test == OR_TEST_MSD_BASIS) return -1.0;
     if (n_threads < 1) n_threads = 1;
     oracle_consts k;
     make_consts(cfg, &k);
     double t0 = now_s();
     if (n_threads == 1 || n_events < 2) {
-        worker_arg a = {cfg, &k, off, n_hits, x, y, counts, accept, 0, n_events, 0};
+        worker_arg a = {cfg, &k, off, n_hits, x, y, z, counts, accept, 0, n_events, 0};
         worker(&a);
         *status = a.status;
         return now_s() - t0;
@@ -211,7 +253,7 @@ double trig_select_ref(int32_t n_events, const int32_t *off, int32_t n_hits, con
         int64_t target = total * (t + 1) / n_threads;
         int64_t e0 = e;
         while (e < n_events && (acc < target || t == n_threads - 1)) acc += event_cost(off, e++);
-        worker_arg a = {cfg, &k, off, n_hits, x, y, counts, accept, e0, e, 0};
+        worker_arg a = {cfg, &k, off, n_hits, x, y, z, counts, accept, e0, e, 0};
         args[t] = a;
         pthread_create(&th[t], NULL, worker, &args[t]);
     }
@@ -310,11 +352,11 @@ int32_t oracle_has_disjoint_pair(int64_t n, const int64_t *trip) {
  * the number of accepted events, or -1 on bad arguments or memory.  One
  * thread; callers split the event range. */
 int64_t trig_ref_disjoint(int64_t e0, int64_t e1, const int32_t *off, int32_t n_hits, const float *x,
-                          const float *y, const oracle_cfg *cfg, uint8_t *out) {
+                          const float *y, const float *z, const oracle_cfg *cfg, uint8_t *out) {
     if (e0 < 0 || e1 < e0 || (e1 > e0 && (!off || !out)) || !cfg) return -1;
+    if (z && cfg->test == OR_TEST_MSD_BASIS) return -1;
     oracle_consts k;
     make_consts(cfg, &k);
-    const float ndf = (float)cfg->ndf;
     int64_t cap = 0, accepted = 0;
     int64_t *trip = NULL;
     for (int64_t e = e0; e < e1; ++e) {
@@ -326,18 +368,7 @@ int64_t trig_ref_disjoint(int64_t e0, int64_t e1, const int32_t *off, int32_t n_
             for (int64_t i = o0; i < o1; ++i)
                 for (int64_t j = o1; j < o2; ++j)
                     for (int64_t kk = o2; kk < o3; ++kk) {
-                        int pass;
-                        if (cfg->test == OR_TEST_WINDOW) {
-                            pass = plane_window(x[i], x[j], x[kk], &k, cfg->window[0]) &&
-                                   plane_window(y[i], y[j], y[kk], &k, cfg->window[1]);
-                        } else if (cfg->test == OR_TEST_MSD_BASIS) {
-                            pass = plane_msd(x[i], x[j], x[kk], &k, cfg->msd_max[0], ndf) &&
-                                   plane_msd(y[i], y[j], y[kk], &k, cfg->msd_max[1], ndf);
-                        } else {
-                            pass = plane_fit(x[i], x[j], x[kk], &k, cfg->msd_max[0], ndf) &&
-                                   plane_fit(y[i], y[j], y[kk], &k, cfg->msd_max[1], ndf);
-                        }
-                        if (!pass) continue;
+                        if (!triplet_passes(cfg, &k, x, y, z, i, j, kk)) continue;
                         if (n == cap) {
                             cap = cap ? 2 * cap : 64;
                             int64_t *grown = (int64_t *)realloc(trip, (size_t)cap * 3 * sizeof(int64_t));

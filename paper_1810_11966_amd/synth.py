@@ -89,6 +89,7 @@ class EventSet:
     spec: Optional[EventSetSpec] = None
     seed: int = 0
     meta: dict = field(default_factory=dict)
+    z: Optional[np.ndarray] = None  # float32[H]: per-hit z (cm), or None for the layer positions
 
     @property
     def n_events(self) -> int:
@@ -104,7 +105,7 @@ class EventSet:
 
     def sha256(self) -> str:
         h = hashlib.sha256()
-        for a in (self.offsets, self.x, self.y):
+        for a in (self.offsets, self.x, self.y) + ((self.z,) if self.z is not None else ()):
             h.update(np.ascontiguousarray(a).tobytes())
         return h.hexdigest()
 
@@ -114,7 +115,8 @@ class EventSet:
         hi = int(self.offsets[3 * (first + count)])
         off = (self.offsets[3 * first: 3 * (first + count) + 1].astype(np.int64) - lo)
         return EventSet(off.astype(np.int32), self.x[lo:hi].copy(), self.y[lo:hi].copy(),
-                        self.n_tracks[first:first + count].copy(), self.spec, self.seed)
+                        self.n_tracks[first:first + count].copy(), self.spec, self.seed,
+                        z=None if self.z is None else self.z[lo:hi].copy())
 
 
 def _track_tan_range(spec: EventSetSpec):
@@ -239,17 +241,41 @@ def from_layers(events) -> EventSet:
 
 
 def concat(sets) -> EventSet:
-    """Concatenate event sets into one batch (offsets rebased)."""
+    """Concatenate event sets into one batch (offsets rebased).  Per-hit z
+    is kept if every set has it."""
+    sets = list(sets)
     offs, xs, ys, nts = [np.zeros(1, np.int64)], [], [], []
     base = 0
     for s in sets:
         offs.append(s.offsets[1:].astype(np.int64) + base)
         base += s.n_hits
         xs.append(s.x); ys.append(s.y); nts.append(s.n_tracks)
+    z = None
+    if sets and all(s.z is not None for s in sets):
+        z = np.concatenate([s.z for s in sets])
     return EventSet(np.concatenate(offs).astype(np.int32),
                     np.concatenate(xs) if xs else np.zeros(0, np.float32),
                     np.concatenate(ys) if ys else np.zeros(0, np.float32),
-                    np.concatenate(nts) if nts else np.zeros(0, np.int8))
+                    np.concatenate(nts) if nts else np.zeros(0, np.int8), z=z)
+
+
+def staggered(s: EventSet, z=Z_LAYERS, dz: float = 0.75, n_sectors: int = 16) -> EventSet:
+    """The events of ``s`` (generated at the layer positions ``z``) on
+    staggered modules: a hit in azimuthal sector k of 2 pi / n_sectors sits at
+    z_l - dz for even k and z_l + dz for odd k (overlapping module rows, as
+    each hit carries its own position, Sec. 3.2 last paragraph), and is moved
+    along its line of sight from the target to that z, so that a straight
+    track from the target stays one.  Returns a set with per-hit z."""
+    n = np.diff(s.offsets.astype(np.int64))
+    layer = np.repeat(np.tile(np.arange(3), s.n_events), n)
+    x = s.x.astype(np.float64)
+    y = s.y.astype(np.float64)
+    sector = np.floor((np.arctan2(y, x) + np.pi) / (2 * np.pi / n_sectors)).astype(np.int64) % n_sectors
+    zl = np.asarray(z, np.float64)[layer]
+    zh = zl + np.where(sector % 2 == 0, -dz, dz)
+    f = zh / zl
+    return EventSet(s.offsets.copy(), (x * f).astype(np.float32), (y * f).astype(np.float32), s.n_tracks.copy(),
+                    s.spec, s.seed, z=zh.astype(np.float32))
 
 
 def slice_stream(n_slices: int, seed: int = 0, offered_rate: float = 1e7,

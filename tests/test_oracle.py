@@ -470,3 +470,77 @@ def test_disjoint_acceptance_invariants(oracle_lib, test):
         lo, hi = base.offsets[q], base.offsets[q + 1]
         perm[lo:hi] = lo + rng.permutation(hi - lo)
     assert np.array_equal(R.disjoint_accept(base.offsets, base.x[perm], base.y[perm], cfg), d)
+
+
+# --------------------------------------------------------------- per-hit z ---
+
+def _with_z(s, z):
+    return synth.EventSet(s.offsets, s.x, s.y, s.n_tracks, z=np.asarray(z, np.float32))
+
+
+def test_per_hit_z_at_layer_positions_equals_layer_path(oracle_lib):
+    """Per-hit z equal to the layer positions gives the layer path's counts
+    for the fit and the window test: at the default geometry the binary32
+    division 1 / Szz and the rounded binary64 reciprocal are the same number,
+    so both paths take the same slope."""
+    z32 = [np.float32(v) for v in Z]
+    szz = (z32[0] * z32[0] + z32[1] * z32[1]) + z32[2] * z32[2]
+    assert np.float32(1.0) / szz == np.float32(1.0 / float(szz))
+    s = synth.make_event_set(synth.SMALL_10K, n_events=3000)
+    n = np.diff(s.offsets.astype(np.int64))
+    zh = np.asarray(Z, np.float32)[np.repeat(np.tile(np.arange(3), s.n_events), n)]
+    for test in ("msd", "window"):
+        cfg = R.OracleConfig(test=test)
+        assert np.array_equal(R.select_set(_with_z(s, zh), cfg)[0], R.select_set(s, cfg)[0])
+
+
+def test_per_hit_z_near_threshold_against_exact_fit(oracle_lib):
+    """Staggered z per hit (z_l -/+ 0.75 cm, all eight combinations): the
+    fp32 MSD of near-threshold triplets stays within the rigorous bound of its
+    own evaluation order (binary32 reciprocal of the triplet's Szz) from the
+    exact rational fit, and the decision equals the exact decision outside
+    that band."""
+    rng = np.random.default_rng(21)
+    T = 0.03
+    T32 = Fraction(float(np.float32(T)))
+    decided = 0
+    for combo in range(8):
+        zt = tuple(Z[l] + (0.75 if (combo >> l) & 1 else -0.75) for l in range(3))
+        ci, cj, ck = helpers.near_threshold_triplets(80, seed=100 + combo, plane_T=T, rel=3e-3, z=zt)
+        bound = R.fp32_fit_error_bound(ci, cj, ck, zt, w_division=True)
+        # one event per triplet: (x, y) = (c, 0) passes the y plane
+        s = synth.from_layers([[[(float(ci[t]), 0.0)], [(float(cj[t]), 0.0)], [(float(ck[t]), 0.0)]]
+                               for t in range(len(ci))])
+        zh = np.tile(np.asarray(zt, np.float32), len(ci))
+        got = R.select_set(_with_z(s, zh), R.OracleConfig(msd_max=(T, T)))[0]
+        for t in range(len(ci)):
+            exact = R.fit_msd_exact(ci[t], cj[t], ck[t], zt, 2)
+            if abs(exact - T32) > Fraction(float(bound[t])) / 2 + T32 * Fraction(1, 2 ** 21):
+                decided += 1
+                assert bool(got[t]) == (exact <= T32), (combo, t)
+    assert decided > 500
+
+
+def test_per_hit_z_invariants(oracle_lib):
+    """Staggered events: doubling every z leaves every decision bit-exact
+    (the slope halves exactly and m z is unchanged), and so does permuting the
+    hits of a layer together with their z; exact tracks on staggered modules
+    still pass."""
+    base = synth.make_event_set(synth.EventSetSpec(n_events=2000, hits_mean=6, p_inject=0.5, sigma=0.0, salt=33))
+    s = synth.staggered(base)
+    assert len(np.unique(s.z)) == 6
+    for test in ("msd", "window"):
+        cfg = R.OracleConfig(test=test)
+        c = R.select_set(s, cfg)[0]
+        assert (c[base.n_tracks > 0] >= 2).all()
+        if test == "msd":
+            assert np.array_equal(R.select_set(_with_z(s, 2 * s.z), cfg)[0], c)
+        rng = np.random.default_rng(4)
+        perm = np.arange(s.n_hits)
+        for q in range(3 * s.n_events):
+            lo, hi = s.offsets[q], s.offsets[q + 1]
+            perm[lo:hi] = lo + rng.permutation(hi - lo)
+        p = synth.EventSet(s.offsets, s.x[perm], s.y[perm], s.n_tracks, z=s.z[perm])
+        assert np.array_equal(R.select_set(p, cfg)[0], c)
+    with pytest.raises(ValueError):
+        R.select_set(s, R.OracleConfig(test="msd_basis"))
