@@ -146,13 +146,29 @@ enum {
                                    these flags */
     TRIG_OUT_COMPACT = 8u,      /* also write the ascending ids of accepted
                                    events; needs workspace */
-    TRIG_EXEC_PRUNED = 16u      /* batched form: workgroups stage blocks of
+    TRIG_EXEC_PRUNED = 16u,     /* batched form: workgroups stage blocks of
                                    consecutive events in LDS and complete only
                                    pairs that provably can pass (MSD tests: a
                                    bound on the pair's partial sum a that
                                    every passing triplet meets; window: the
                                    layer-1 window is part of the test); same
                                    counts */
+    TRIG_ACCEPT_TWO_PARTICLES = 32u, /* acceptance by the trigger signature of
+                                   Sec. 3.1, two particles pointing back to
+                                   the target: accept iff two of the event's
+                                   passing triplets have no hit in common
+                                   (they differ in every layer's hit);
+                                   min_triplets is not used.  out_counts keep
+                                   the passing-triplet counts.  Any execution
+                                   form; events with two or more passing
+                                   triplets are then decided by one more
+                                   kernel */
+    TRIG_DECISION_ONLY = 64u    /* only the decision is wanted: out_counts[e]
+                                   = min(count, K), K = min_triplets (2 with
+                                   TRIG_ACCEPT_TWO_PARTICLES), errors
+                                   unchanged, and an event's search may stop
+                                   once its count reaches K; the accept flags
+                                   are those of the full count */
 };
 
 typedef struct {

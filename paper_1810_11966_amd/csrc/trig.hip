@@ -66,7 +66,7 @@ struct Chunk<MsdFitTest> { static constexpr int value = kChunkFit; };
 __device__ __forceinline__ void write_result(int e, int32_t cnt, const Consts& c,
                                              int32_t* counts, uint8_t* accept,
                                              uint32_t* status) {
-    counts[e] = cnt;
+    counts[e] = capped(cnt, c);
     accept[e] = (uint8_t)(cnt >= 0 && cnt >= c.min_triplets);
     if (cnt < 0 && status) atomicOr(status, cnt == -1 ? TRIG_STATUS_MALFORMED : TRIG_STATUS_OVERFLOW);
 }
@@ -326,11 +326,12 @@ __global__ __launch_bounds__(WPB * kWave) void k_persistent(
 }
 
 __global__ __launch_bounds__(kScanBlock) void k_finalize(int n_events, Consts c,
-                                                         const int32_t* __restrict__ counts,
+                                                         int32_t* __restrict__ counts,
                                                          uint8_t* __restrict__ accept) {
     const int64_t e = (int64_t)blockIdx.x * kScanBlock + threadIdx.x;
     if (e < n_events) {
         const int32_t cnt = counts[e];
+        counts[e] = capped(cnt, c);
         accept[e] = (uint8_t)(cnt >= 0 && cnt >= c.min_triplets);
     }
 }
@@ -393,6 +394,37 @@ __global__ __launch_bounds__(kBinWaves * kWave) __attribute__((amdgpu_waves_per_
     }
 }
 
+// -------------------------------------------------- two-particle mode ---
+
+// TRIG_ACCEPT_TWO_PARTICLES, after the counting form has flagged the
+// candidates (count >= 2): each wave scans the flags of 64 consecutive
+// events and decides its candidates one by one (wave_two_particles), writing
+// the final flag.  Events without a candidate cost one coalesced read.
+constexpr int kTwoWaves = 4;
+
+template <class P>
+__global__ __launch_bounds__(kTwoWaves * kWave) void k_two_particles(const int32_t* __restrict__ off, int n_events,
+                                                                     const float* __restrict__ x,
+                                                                     const float* __restrict__ y, Consts c,
+                                                                     uint8_t* __restrict__ accept) {
+    const int w = uniform_i((int)(threadIdx.x / kWave));
+    const int64_t base = ((int64_t)blockIdx.x * kTwoWaves + w) * kWave;
+    if (base >= n_events) return;
+    const int64_t e = base + lane_id();
+    uint64_t m = lanes(e < n_events && accept[e] != 0);
+    const GlobalHits gh{x, y};
+    while (m) {
+        const int L = __builtin_ctzll(m);
+        m &= m - 1;
+        const int ev_i = (int)(base + L);
+        EventRange ev;
+        bool two = false;
+        if (load_event(off, ev_i, c.n_hits, ev) == 0 && ev.n0 > 0 && ev.n1 > 0 && ev.n2 > 0)
+            two = wave_two_particles<P>(c, gh, ev.o0, ev.n0, ev.o1, ev.n1, ev.o2, ev.n2);
+        if (lane_id() == 0) accept[ev_i] = (uint8_t)two;
+    }
+}
+
 // ------------------------------------------------------------------ host ---
 
 thread_local std::string g_detail;
@@ -448,7 +480,9 @@ Consts make_consts(const trig_params* p, int n_hits) {
     c.win_x = p->slope_window[0];
     c.win_y = p->slope_window[1];
     c.bin_r = p->test == TRIG_TEST_SLOPE_WINDOW ? c.win_x : std::nextafter(c.beta_x, INFINITY);
-    c.min_triplets = p->min_triplets;
+    const bool two = (p->flags & TRIG_ACCEPT_TWO_PARTICLES) != 0;
+    c.min_triplets = two ? 2 : p->min_triplets;  // two particles need two passing triplets
+    c.count_cap = (p->flags & TRIG_DECISION_ONLY) ? (two ? 2 : p->min_triplets) : INT32_MAX;
     c.n_hits = n_hits;
     return c;
 }
@@ -488,7 +522,7 @@ int validate_params(const trig_params* p, bool need_outputs) {
     for (int r : p->reserved)
         if (r) return fail(TRIG_EINVAL, "reserved fields must be zero");
     const uint32_t known = TRIG_EXEC_PERSISTENT | TRIG_EXEC_PRUNED | TRIG_EXEC_BINNED |
-                           TRIG_EXEC_AUTOTUNE | TRIG_OUT_COMPACT;
+                           TRIG_EXEC_AUTOTUNE | TRIG_OUT_COMPACT | TRIG_ACCEPT_TWO_PARTICLES | TRIG_DECISION_ONLY;
     if (p->flags & ~known) return fail(TRIG_EINVAL, "unknown flag bits");
     if (need_outputs && (p->flags & TRIG_OUT_COMPACT) && (!p->out_accepted_ids || !p->out_n_accepted))
         return fail(TRIG_EINVAL, "TRIG_OUT_COMPACT needs out_accepted_ids and out_n_accepted");
@@ -710,9 +744,18 @@ int launch_binned(const trig_events_csr* ev, const trig_hits* h, const trig_para
     return TRIG_OK;
 }
 
+template <class P>
+int launch_two_particles(const trig_events_csr* ev, const trig_hits* h, const Consts& c, uint8_t* accept,
+                         hipStream_t s) {
+    const int64_t waves = cdiv(ev->n_events, kWave);
+    hipLaunchKernelGGL(k_two_particles<P>, dim3((unsigned)cdiv(waves, kTwoWaves)), dim3(kTwoWaves * kWave), 0, s,
+                       ev->layer_offsets, ev->n_events, h->x, h->y, c, accept);
+    return check_launch("k_two_particles");
+}
+
 template <class T, class P, class B>
-int run_form(const trig_events_csr* ev, const trig_hits* h, const trig_params* p, const Consts& c,
-             const Layout& L, char* ws, int32_t* counts, uint8_t* accept, hipStream_t s) {
+int run_counting_form(const trig_events_csr* ev, const trig_hits* h, const trig_params* p, const Consts& c,
+                      const Layout& L, char* ws, int32_t* counts, uint8_t* accept, hipStream_t s) {
     if (p->flags & TRIG_EXEC_BINNED) return launch_binned<B>(ev, h, p, c, L, ws, counts, accept, s);
     if (p->flags & TRIG_EXEC_PRUNED) return launch_block<P>(ev, h, p, c, L, ws, counts, accept, s);
     if (p->flags & TRIG_EXEC_PERSISTENT) {
@@ -721,6 +764,15 @@ int run_form(const trig_events_csr* ev, const trig_hits* h, const trig_params* p
     }
     return launch_plain<T>(ev, h, c, counts, accept, p->out_status, s);
 }
+
+template <class T, class P, class B>
+int run_form(const trig_events_csr* ev, const trig_hits* h, const trig_params* p, const Consts& c,
+             const Layout& L, char* ws, int32_t* counts, uint8_t* accept, hipStream_t s) {
+    int r = run_counting_form<T, P, B>(ev, h, p, c, L, ws, counts, accept, s);
+    if (r == TRIG_OK && (p->flags & TRIG_ACCEPT_TWO_PARTICLES)) r = launch_two_particles<P>(ev, h, c, accept, s);
+    return r;
+}
+
 
 // ------------------------------------------------------------ autotuner ---
 

@@ -399,6 +399,8 @@ __device__ uint32_t wave_event_binned(const Consts& c, const float* __restrict__
         if (i0 + lane < n0) cnt += B::count_i(c, bb, xi, yi, b1, b2, L);
         xi = xn;
         yi = yn;
+        // decision only: stop once the (capped) result is known
+        if (c.count_cap != INT32_MAX && i0 + kWave < n0 && wave_sum_u(cnt) >= (uint32_t)c.count_cap) break;
     }
     cnt = wave_sum_u(cnt);
     wave_lds_sync();  // the next event rebuilds the cells

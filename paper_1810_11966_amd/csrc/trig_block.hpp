@@ -165,6 +165,27 @@ struct MsdBasisPrune {
         }
         return cnt;
     }
+    // Lanes k (layer-2 hits o2 + k0 + lane, k < n2) whose triplet with
+    // (hi, hj) passes.
+    template <class H>
+    __device__ static uint64_t complete_mask(const Consts& c, const H& hits, int hi, int hj, int o2, int n2, int k0) {
+        const float2 ci = hits.at(hi), cj = hits.at(hj);
+        const float ax = c.U0 * ci.x + c.U1 * cj.x;
+        const float ay = c.U0 * ci.y + c.U1 * cj.y;
+        const float bx0 = c.V0 * ci.x + c.V1 * cj.x;
+        const float by0 = c.V0 * ci.y + c.V1 * cj.y;
+        const int k = k0 + (int)lane_id();
+        float2 w = nan2();
+        if (k < n2) {
+            const float2 ck = hits.at(o2 + k);
+            w = make_float2(c.V2 * ck.x, c.V2 * ck.y);
+        }
+        const float bx = bx0 + w.x;
+        const float qx = ax * ax + bx * bx;
+        const float by = by0 + w.y;
+        const float qy = ay * ay + by * by;
+        return lanes(qx <= c.qmax_x) & lanes(qy <= c.qmax_y);
+    }
 };
 
 // TRIG_TEST_MSD: the basis-form partials a prune pairs with the bounds of
@@ -204,6 +225,17 @@ struct MsdFitPrune {
             cnt += (uint32_t)__builtin_popcountll(lanes(qx <= c.qmax_x) & lanes(qy <= c.qmax_y));
         }
         return cnt;
+    }
+    template <class H>
+    __device__ static uint64_t complete_mask(const Consts& c, const H& hits, int hi, int hj, int o2, int n2, int k0) {
+        const float2 ci = hits.at(hi), cj = hits.at(hj);
+        const float sx01 = ci.x * c.z0 + cj.x * c.z1;
+        const float sy01 = ci.y * c.z0 + cj.y * c.z1;
+        const int k = k0 + (int)lane_id();
+        const float2 ck = k < n2 ? hits.at(o2 + k) : nan2();
+        const float qx = MsdFitTest::plane_q(c, ci.x, cj.x, sx01, ck.x, ck.x * c.z2);
+        const float qy = MsdFitTest::plane_q(c, ci.y, cj.y, sy01, ck.y, ck.y * c.z2);
+        return lanes(qx <= c.qmax_x) & lanes(qy <= c.qmax_y);
     }
 };
 
@@ -246,7 +278,121 @@ struct WindowPrune {
         }
         return cnt;
     }
+    // (hj is tested by the pair test: the layer-1 window)
+    template <class H>
+    __device__ static uint64_t complete_mask(const Consts& c, const H& hits, int hi, int /*hj*/, int o2, int n2,
+                                             int k0) {
+        const float2 ci = hits.at(hi);
+        const float sxi = ci.x / c.z0, syi = ci.y / c.z0;
+        const int k = k0 + (int)lane_id();
+        float2 s = nan2();
+        if (k < n2) {
+            const float2 ck = hits.at(o2 + k);
+            s = make_float2(ck.x / c.z2, ck.y / c.z2);
+        }
+        return lanes(__builtin_fabsf(s.x - sxi) < c.win_x) & lanes(__builtin_fabsf(s.y - syi) < c.win_y);
+    }
 };
+
+// Two-particle acceptance: whether an event's passing triplets include two
+// with no hit in common (the trigger signature of Sec. 3.1, two particles
+// pointing back to the target), decided while the passing triplets stream
+// by, in O(1) state.  Let e1 = (a, b, c) be the first passing triplet.  A
+// later triplet with no hit of e1 decides at once.  Otherwise two passing
+// triplets f, g with no common hit both meet e1, in different hits x != y of
+// e1 (they cannot share one), f without y and g without x: for (x, y) =
+// (a, b), f = (a, j, k) with j != b and g = (i, b, k') with i != a, and
+// they share no hit exactly when k != k'.  So for each of the three pairs of
+// e1's hits, it is enough to keep up to two distinct values of the third
+// layer's hit among the triplets through x but not y, and among those through
+// y but not x: two such triplets differ there iff not both sides hold one
+// and the same value.  Wave-uniform (every lane runs the same updates).
+struct TwoValues {
+    int n, v0, v1;  // up to two distinct values seen (n of them)
+};
+// t with v added when `when` holds (selects, no branches: the state stays in
+// registers).
+__device__ __forceinline__ TwoValues two_values_add(TwoValues t, int v, bool when) {
+    const bool first = when && t.n == 0, second = when && t.n == 1 && v != t.v0;
+    return TwoValues{first ? 1 : (second ? 2 : t.n), first ? v : t.v0, second ? v : t.v1};
+}
+// some value of a differs from some value of b
+__device__ __forceinline__ bool two_values_differ(TwoValues a, TwoValues b) {
+    return a.n > 0 && b.n > 0 && !(a.n == 1 && b.n == 1 && a.v0 == b.v0);
+}
+
+struct DisjointState {
+    bool have, found;
+    int a, b, c;
+    TwoValues ab_a, ab_b, ac_a, ac_c, bc_b, bc_c;
+};
+
+__device__ __forceinline__ DisjointState disjoint_start() {
+    const TwoValues z{0, 0, 0};
+    return DisjointState{false, false, 0, 0, 0, z, z, z, z, z, z};
+}
+
+__device__ __forceinline__ DisjointState disjoint_add(DisjointState s, int i, int j, int k) {
+    if (!s.have) {
+        s.have = true;
+        s.a = i;
+        s.b = j;
+        s.c = k;
+        return s;
+    }
+    if (i != s.a && j != s.b && k != s.c) {
+        s.found = true;
+        return s;
+    }
+    s.ab_a = two_values_add(s.ab_a, k, i == s.a && j != s.b);  // through a, not b: layer-2 hit
+    s.ab_b = two_values_add(s.ab_b, k, j == s.b && i != s.a);
+    s.ac_a = two_values_add(s.ac_a, j, i == s.a && k != s.c);  // through a, not c: layer-1 hit
+    s.ac_c = two_values_add(s.ac_c, j, k == s.c && i != s.a);
+    s.bc_b = two_values_add(s.bc_b, i, j == s.b && k != s.c);  // through b, not c: layer-0 hit
+    s.bc_c = two_values_add(s.bc_c, i, k == s.c && j != s.b);
+    s.found = two_values_differ(s.ab_a, s.ab_b) || two_values_differ(s.ac_a, s.ac_c) ||
+              two_values_differ(s.bc_b, s.bc_c);
+    return s;
+}
+
+// Whether event (o0, n0, o1, n1, o2, n2) (all layers non-empty, n0 n1 n2 in
+// int32) has two passing triplets with no hit in common: pairs one per lane
+// (the exact pair test of the pruned form), surviving pairs completed over
+// layer 2 by lanes, each passing triplet fed to the state above.  Whole wave.
+template <class P, class H>
+__device__ bool wave_two_particles(const Consts& c, const H& hits, int o0, int n0, int o1, int n1, int o2, int n2) {
+    float M = 0.0f;
+    if constexpr (P::kMag) M = layer_mag(hits, o1, n1);
+    const PairBounds pb = P::bounds(c, M);
+    DisjointState st = disjoint_start();
+    // n0 n1 <= INT32_MAX, so pair indices (and p0 + 63) fit 32-bit unsigned
+    const uint32_t np = (uint32_t)n0 * (uint32_t)n1, un1 = (uint32_t)n1;
+    const uint32_t lane = lane_id();
+    for (uint32_t p0 = 0; p0 < np; p0 += kWave) {
+        const uint32_t p = p0 + lane;
+        const bool v = p < np;
+        const uint32_t q = p / un1;
+        const int i = v ? (int)q : 0, j = v ? (int)(p - q * un1) : 0;
+        const float2 u = v ? P::layer0(c, hits.at(o0 + i)) : nan2();
+        const float2 w = v ? P::layer1(c, hits.at(o1 + j)) : nan2();
+        uint64_t m = P::pair_mask(pb, u, w);
+        while (m) {
+            const int L = __builtin_ctzll(m);
+            m &= m - 1;
+            const int iL = __builtin_amdgcn_readlane(i, L), jL = __builtin_amdgcn_readlane(j, L);
+            for (int k0 = 0; k0 < n2; k0 += kWave) {
+                uint64_t km = P::complete_mask(c, hits, o0 + iL, o1 + jL, o2, n2, k0);
+                while (km) {
+                    const int kk = k0 + __builtin_ctzll(km);
+                    km &= km - 1;
+                    st = disjoint_add(st, iL, jL, kk);
+                    if (st.found) return true;
+                }
+            }
+        }
+    }
+    return false;
+}
 
 // Passing triplets of one event (all layers non-empty), by one wave.
 // o0, o1, o2 index `hits`; px/py are this wave's kPBuf-entry LDS buffers
@@ -291,6 +437,7 @@ __device__ uint32_t wave_event_pruned(const Consts& c, const PairBounds& pb, con
                     const int iL = __builtin_amdgcn_readlane(g, L) * T + t;
                     const int jL = __builtin_amdgcn_readlane(j, L);
                     cnt += P::complete(c, hits, o0 + ic + iL, o1 + jL, o2, n2);
+                    if (cnt >= (uint32_t)c.count_cap) return;  // the result is capped there
                 }
             };
             const float4* ppx = reinterpret_cast<const float4*>(px + g * T);
@@ -376,6 +523,7 @@ __device__ uint32_t fast_exact(const Consts& c, const PairBounds& pb, const H& h
             const int hB = oB + __builtin_amdgcn_readlane(g, L) * T + t;
             const int hL = oL + __builtin_amdgcn_readlane(j, L);
             cnt += S ? P::complete(c, hits, hL, hB, o2, n2) : P::complete(c, hits, hB, hL, o2, n2);
+            if (cnt >= (uint32_t)c.count_cap) return;  // the result is capped there
         }
     };
     const float4* ppx = reinterpret_cast<const float4*>(px + g * T);
@@ -460,7 +608,7 @@ __device__ void wave_event(const Consts& c, const H& hits, int h_base, int o0, i
                                             n2, px, py);
     }
     if (lane_id() == 0) {
-        counts[e] = cnt;
+        counts[e] = capped(cnt, c);
         accept[e] = (uint8_t)(cnt >= 0 && cnt >= c.min_triplets);
         if (cnt < 0 && status) atomicOr(status, TRIG_STATUS_OVERFLOW);
     }
@@ -685,7 +833,7 @@ __device__ void block_count(BlockLds<HB, NW>& L, const Consts& c, int e_first, i
     __syncthreads();
     for (int te = threadIdx.x; te < nsub; te += NT) {
         const int32_t r = L.sres[te];
-        counts[e_first + te] = r;
+        counts[e_first + te] = capped(r, c);
         accept[e_first + te] = (uint8_t)(r >= 0 && r >= c.min_triplets);
         if (r < 0 && status) atomicOr(status, TRIG_STATUS_OVERFLOW);
     }

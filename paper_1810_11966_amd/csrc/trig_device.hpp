@@ -45,9 +45,18 @@ struct Consts {
     // around a hit's centre (MSD_BASIS: the binary32 value above beta_x;
     // window: win_x).
     float bin_r;
+    // accept iff count >= min_triplets (two-particle mode: the candidates,
+    // count >= 2)
     int32_t min_triplets;
+    // counts are written as min(count, count_cap) (INT32_MAX unless the
+    // caller asked for the decision only); an event's search may stop once
+    // its count reaches the cap
+    int32_t count_cap;
     int32_t n_hits;
 };
+
+// The count an event's result holds (errors, negative, unchanged).
+__device__ __forceinline__ int32_t capped(int32_t cnt, const Consts& c) { return cnt < c.count_cap ? cnt : c.count_cap; }
 
 __device__ __forceinline__ int uniform_i(int v) { return __builtin_amdgcn_readfirstlane(v); }
 // cond ? a : b for wave-uniform operands, on the scalar unit (a compare
@@ -309,6 +318,7 @@ template <class T, int KCH>
 __device__ uint32_t wave_count(const float* __restrict__ x, const float* __restrict__ y,
                                const EventRange& ev, uint32_t t_begin, uint32_t t_end,
                                const Consts& c, float* __restrict__ lds) {
+    const uint32_t stop = (uint32_t)c.count_cap;  // enough: the result is capped there
     static_assert(KCH % 4 == 0, "chunk must hold whole float4 groups");
     const unsigned lane = lane_id();
     const uint32_t n0 = (uint32_t)ev.n0, n1 = (uint32_t)ev.n1;
@@ -346,8 +356,10 @@ __device__ uint32_t wave_count(const float* __restrict__ x, const float* __restr
                 j -= n1;
                 ++i;
             }
+            if (cnt >= stop) break;  // wave-uniform
         }
         wave_lds_sync();
+        if (cnt >= stop) break;
     }
     return cnt;
 }

@@ -34,6 +34,7 @@ TRIG_STATUS_MALFORMED, TRIG_STATUS_OVERFLOW = 1, 2
 TRIG_TEST_MSD, TRIG_TEST_SLOPE_WINDOW, TRIG_TEST_MSD_BASIS = 0, 1, 2
 TRIG_EXEC_PLAIN, TRIG_EXEC_PERSISTENT, TRIG_EXEC_BINNED = 0, 1, 2
 TRIG_EXEC_AUTOTUNE, TRIG_OUT_COMPACT, TRIG_EXEC_PRUNED = 4, 8, 16
+TRIG_ACCEPT_TWO_PARTICLES, TRIG_DECISION_ONLY = 32, 64
 
 TESTS = {"msd": TRIG_TEST_MSD, "window": TRIG_TEST_SLOPE_WINDOW, "msd_basis": TRIG_TEST_MSD_BASIS}
 FORMS = {
@@ -231,7 +232,8 @@ def _prepare(offsets, x, y, test, form, compact, want_status, stream, workspace,
     if offsets.numel() != 3 * n_ev + 1:
         raise ValueError("offsets must hold 3*n_events+1 entries")
     dev = offsets.device
-    flags = FORMS[form] | (TRIG_OUT_COMPACT if compact else 0)
+    extra = int(param_kw.pop("extra_flags", 0))
+    flags = FORMS[form] | (TRIG_OUT_COMPACT if compact else 0) | extra
     p = make_params(test=test, flags=flags, **param_kw)
     if out is None:
         counts = torch.empty(n_ev, dtype=torch.int32, device=dev)

@@ -194,3 +194,32 @@ def special_values_events(seed):
         layers[1][-1] = (nan, nan)
         events.append(layers)
     return synth.from_layers(events)
+
+
+def two_particle_events(n_events, seed, z=(400.0, 410.0, 420.0), noise=6):
+    """Events whose passing triplets share hits in many ways: 1-3 exact
+    vertex tracks, each hit duplicated with probability 0.3 and joined by a
+    hit within 0.05 cm of it with probability 0.3 (per layer), plus uniform
+    noise hits.  One track with near hits gives several passing triplets
+    that all share a hit; duplicates and second tracks give triplets with no
+    hit in common."""
+    rng = np.random.default_rng(seed)
+    events = []
+    for _ in range(n_events):
+        layers = [[], [], []]
+        for _t in range(int(rng.integers(1, 4)) if rng.random() < 0.9 else 0):
+            m = rng.uniform(-0.4, 0.4, 2)
+            for l, zl in enumerate(z):
+                h = (float(np.float32(m[0] * zl)), float(np.float32(m[1] * zl)))
+                layers[l].append(h)
+                if rng.random() < 0.3:
+                    layers[l].append(h)
+                if rng.random() < 0.3:
+                    d = rng.uniform(-0.05, 0.05, 2)
+                    layers[l].append((float(np.float32(h[0] + d[0])), float(np.float32(h[1] + d[1]))))
+        for l in range(3):
+            pts = rng.uniform(-200, 200, (int(rng.integers(0, noise + 1)), 2)).astype(np.float32)
+            layers[l] += [tuple(map(float, p)) for p in pts]
+            rng.shuffle(layers[l])
+        events.append(layers)
+    return synth.from_layers(events)

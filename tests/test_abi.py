@@ -277,3 +277,4 @@ def test_binned_interval_widening_covers_one_step():
         up = (vals + d).astype(f32)
     assert (down <= np.nextafter(vals, f32(-np.inf))).all()
     assert (up >= np.nextafter(vals, f32(np.inf))).all()
+

@@ -488,3 +488,76 @@ def test_autotune_records_and_matches_oracle(gpu, test):
                   block_events=3)
     trig.trig_autotune_reset()
     assert_parity(gpu, s, test, "auto", "rule after reset")
+
+
+# ---------------------------------------- two particles, decision only ---
+
+def two_particle_oracle(s, test, **kw):
+    cfg = oracle_cfg(test, **kw)
+    c, _, st, _ = oracle_result(s, cfg)
+    d = R.disjoint_accept(s.offsets, s.x, s.y, cfg, n_threads=THREADS)
+    return c, d, st
+
+
+def test_two_particle_acceptance_all_forms(gpu):
+    """TRIG_ACCEPT_TWO_PARTICLES (two passing triplets with no hit in
+    common, Sec. 3.1) in every form and test: flags and ids equal the
+    oracle's pairwise comparison of the listed passing triplets, counts stay
+    exact.  Events with duplicated hits and hits near the tracks give
+    hundreds of events with two or more passing triplets that all share a
+    hit."""
+    from paper_1810_11966_amd import trig
+    s = synth.concat([helpers.two_particle_events(3000, seed=5),
+                      synth.make_event_set(synth.SMALL_10K, n_events=3000),
+                      helpers.ragged_sizes_set([(70, 60, 90), (1, 300, 2), (40, 40, 600)], seed=3)])
+    for test in TESTS:
+        c, d, st = two_particle_oracle(s, test)
+        assert d.sum() > 500 and ((c >= 2) & (d == 0)).sum() > 200
+        for form in FORMS:
+            print(f"[two particles] test={test} form={form}", flush=True)
+            got = run_gpu(gpu, s, test, form, extra_flags=trig.TRIG_ACCEPT_TWO_PARTICLES)
+            assert np.array_equal(got["counts"], c), (test, form)
+            assert np.array_equal(got["accept"], d), (test, form, np.flatnonzero(got["accept"] != d)[:5])
+            assert np.array_equal(got["ids"], R.accepted_ids(d)), (test, form)
+            assert got["status"] == st
+
+
+def test_two_particle_acceptance_dense_and_edges(gpu):
+    """High multiplicity (events of the 100k-event workload, pairs injected)
+    and the near-threshold and far-from-axis sets, two-particle mode."""
+    from paper_1810_11966_amd import trig
+    sets = {"dense": synth.make_event_set(synth.DENSE_100K, n_events=300),
+            "near": helpers.near_threshold_events(200, 8, seed=31, rel=1e-6),
+            "far": helpers.near_threshold_events(150, 8, seed=40, rel=1e-3, slope_max=25.0)}
+    for name, s in sets.items():
+        c, d, _ = two_particle_oracle(s, "msd")
+        for form in ("plain", "pruned", "binned", "auto"):
+            print(f"[two particles] {name} form={form}", flush=True)
+            got = run_gpu(gpu, s, "msd", form, extra_flags=trig.TRIG_ACCEPT_TWO_PARTICLES)
+            assert np.array_equal(got["counts"], c), (name, form)
+            assert np.array_equal(got["accept"], d), (name, form)
+
+
+def test_decision_only(gpu):
+    """TRIG_DECISION_ONLY: counts are min(count, K) (K = min_triplets, or 2
+    with two-particle acceptance), errors unchanged, flags those of the full
+    count; forms may stop an event's search early."""
+    from paper_1810_11966_amd import trig
+    s = synth.concat([helpers.two_particle_events(1500, seed=8),
+                      synth.make_event_set(synth.DENSE_100K, n_events=200),
+                      synth.make_event_set(synth.SMALL_10K, n_events=2000)])
+    for test in ("msd", "window"):
+        for k in (0, 1, 2, 5):
+            c, a, st, _ = oracle_result(s, oracle_cfg(test, min_triplets=k))
+            for form in FORMS:
+                print(f"[decision only] test={test} K={k} form={form}", flush=True)
+                got = run_gpu(gpu, s, test, form, min_triplets=k, extra_flags=trig.TRIG_DECISION_ONLY)
+                assert np.array_equal(got["counts"], np.where(c < 0, c, np.minimum(c, k))), (test, k, form)
+                assert np.array_equal(got["accept"], a), (test, k, form)
+                assert np.array_equal(got["ids"], R.accepted_ids(a)), (test, k, form)
+        c, d, _ = two_particle_oracle(s, test)
+        for form in ("plain", "persistent", "pruned", "binned"):
+            got = run_gpu(gpu, s, test, form,
+                          extra_flags=trig.TRIG_DECISION_ONLY | trig.TRIG_ACCEPT_TWO_PARTICLES)
+            assert np.array_equal(got["counts"], np.where(c < 0, c, np.minimum(c, 2))), (test, form)
+            assert np.array_equal(got["accept"], d), (test, form)
