@@ -128,3 +128,32 @@ def test_filtered_events_feed_the_selection(gpu):
     sub = base.subset(0, 5000)
     c, _, _, _ = R.select_set(sub, n_threads=8)
     assert np.array_equal(sel.counts.cpu().numpy()[:5000], c)
+
+
+def test_trigger_hit_lists_at_capacity(gpu):
+    """The count kernel lists each group of 8 events' trigger hits (events
+    w, w+4, ..., w+28 of a block of 32) for the scatter, up to 2048 entries;
+    a group with more is scattered from a second pass over its station
+    numbers.  Groups at exactly 2048 and at 2049 trigger hits, in both
+    paths, bit-exact against the oracle."""
+    rng = np.random.default_rng(9)
+    n_ev = 64
+    trig_per_event = np.full(n_ev, 256)
+    trig_per_event[1 + 4 * 3] = 257           # group 1 of block 0: 2049 entries
+    trig_per_event[32 + 2 + 4 * 5] = 255      # group 2 of block 1: 2047 entries
+    trig_per_event[32 + 3] = 0                # group 3 of block 1: 1792 entries
+    off = [0]
+    st_parts = []
+    for e in range(n_ev):
+        other = int(rng.integers(0, 300))
+        s = np.concatenate([rng.choice(np.array([13, 14, 15], np.uint8), int(trig_per_event[e])),
+                            rng.integers(0, 12, other).astype(np.uint8)])
+        rng.shuffle(s)
+        st_parts.append(s)
+        off.append(off[-1] + len(s))
+    st = np.concatenate(st_parts)
+    off = np.asarray(off, np.int64)
+    x = rng.standard_normal(len(st)).astype(np.float32)
+    y = rng.standard_normal(len(st)).astype(np.float32)
+    assert_filter_parity(gpu, "lists at capacity", off, st, x, y)
+    assert_filter_parity(gpu, "lists at capacity misaligned", off, st, x, y, misalign=True)
