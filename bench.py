@@ -36,7 +36,7 @@ sys.path.insert(0, ROOT)
 # non-fused, non-packed fp32 operation per lane per clock.
 HBM_PEAK_GBS = 8000.0
 VALU_F32_PEAK_TOPS = 256 * 128 * 2.4e9 / 1e12  # 78.64
-OPS_PER_TRIPLET = {"msd": 8, "msd_fit": 28, "window": 4}
+OPS_PER_TRIPLET = {"msd": 28, "msd_basis": 8, "window": 4}
 
 WORKLOAD_TEXT = {
     "medium_1m": "1,000,000 events; Poisson(30) noise hits per layer in r=[20,200] cm; "
@@ -58,19 +58,20 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="medium_1m", choices=sorted(WORKLOAD_TEXT))
-    ap.add_argument("--test", default="msd", choices=["msd", "msd_fit", "window"])
+    ap.add_argument("--test", default="msd", choices=["msd", "msd_basis", "window"])
     ap.add_argument("--form", default="auto",
                     help="form of the timed step (auto: trig_autotune picks the shape in the warm-up)")
     ap.add_argument("--compare", default="plain,pruned,persistent_pruned,binned",
                     help="other forms timed on the same input (comma separated)")
     ap.add_argument("--compare-steps", type=int, default=5, help="timed steps of each compared form")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0,
-                    help="target wall time of the CPU-oracle baseline sample")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0,
+                    help="target wall time of the CPU-oracle baseline sample (all threads; the one-thread "
+                         "sample takes about as long again)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--only-form", action="store_true", help="time only --form (profiling runs)")
     ap.add_argument("--shape", default="", metavar="HB,NW,EB",
                     help="explicit block_hits,block_waves,block_events for --form (profiling runs)")
-    ap.add_argument("--serve-slices", type=int, default=100,
+    ap.add_argument("--serve-slices", type=int, default=1000,
                     help="timeslices of the serving leg (0 = skip it)")
     ap.add_argument("--serve-load", type=float, default=1e7, help="offered load of the serving leg, events/s")
     ap.add_argument("--serve-streams", type=int, default=4)
@@ -206,7 +207,9 @@ def serving_leg(s, full_counts, test, n_slices, load, n_streams, seed=11):
     big = max(sl.x.size for sl in slices)
     dev_slice = 16 * big + 32 * int(max(sizes)) + (8 << 20)   # generous device footprint
     host_slice = 8 * big + 32 * int(max(sizes)) + (8 << 20)   # staging: inputs and results
-    params = trig.make_params(test=test, flags=trig.TRIG_EXEC_PRUNED)
+    # the autotuned form: the record trig_autotune made on the full batch
+    # covers the slices' multiplicity class
+    params = trig.make_params(test=test, flags=trig.TRIG_EXEC_AUTOTUNE)
     with serve.Server(hbm_budget_bytes=(n_streams + 1) * dev_slice,
                       pinned_budget_bytes=(n_streams + 4) * host_slice,
                       n_streams=n_streams, max_pending=64, params=params) as srv:
@@ -214,8 +217,9 @@ def serving_leg(s, full_counts, test, n_slices, load, n_streams, seed=11):
         srv.submit(slices[0].offsets, slices[0].x, slices[0].y)
         srv.poll(60000)
         origin = srv.now()
+        trace = {}
         done, tickets, wall = serve.run_stream(srv, slices, arrivals, pace=True, poll_ms=1, deadline_s=240,
-                                               submit_threads=4)
+                                               submit_threads=4, trace=trace)
         st = srv.stats()
     lat, qwait, ev_done, rows = [], [], 0, []
     for i, sl in enumerate(slices):
@@ -227,10 +231,14 @@ def serving_leg(s, full_counts, test, n_slices, load, n_streams, seed=11):
         lat.append(f.t_done - arrive)
         qwait.append(f.t_admit - f.t_submit)
         ev_done += sl.n_events
+        tr = trace.get(i, {})
         rows.append({"latency_ms": 1e3 * (f.t_done - arrive), "events": sl.n_events,
                      "input_mb": (sl.x.size * 8 + sl.offsets.size * 4) / 1e6,
                      "submit_delay_ms": 1e3 * (f.t_submit - arrive), "admit_ms": 1e3 * (f.t_admit - f.t_submit),
-                     "admit_to_done_ms": 1e3 * (f.t_done - f.t_admit)})
+                     "admit_to_done_ms": 1e3 * (f.t_done - f.t_admit),
+                     "submitter_wake_late_ms": 1e3 * tr.get("wake_late_s", float("nan")),
+                     "busy_retries": tr.get("busy_retries", -1),
+                     "staging_ms": 1e3 * tr.get("submit_call_s", float("nan"))})
     lat = np.array(lat) * 1e3
     mb = np.array([r["input_mb"] for r in rows])
     fit = np.linalg.lstsq(np.vstack([np.ones_like(mb), mb]).T, lat, rcond=None)[0]
@@ -242,23 +250,50 @@ def serving_leg(s, full_counts, test, n_slices, load, n_streams, seed=11):
             "latency": "scheduled arrival to result on the host (includes the copy into pinned staging, "
                        "H2D, kernels, D2H)",
             "latency_fit_ms": {"intercept": float(fit[0]), "per_mb": float(fit[1])},
+            "submit_delay_ms": {"p50": float(np.percentile([r["submit_delay_ms"] for r in rows], 50)),
+                                "p99": float(np.percentile([r["submit_delay_ms"] for r in rows], 99)),
+                                "max": float(max(r["submit_delay_ms"] for r in rows))},
+            "busy_rejections": int(st.rejected_busy),
+            "form": "autotuned (the record of the full batch's multiplicity class)",
+            "graph_capture": "none: each slice issues its copies and five launches directly on its stream",
             "slowest": sorted(rows, key=lambda r: -r["latency_ms"])[:3],
             "counts_identical_to_full_batch": True}
 
 
 def cpu_baseline(s, test, target_s):
+    """The oracle on the host: all threads of the affinity mask over a prefix
+    sized to about target_s, and one thread over a prefix sized to about
+    target_s as well."""
     from oracle import reference as R
     threads = max(1, len(os.sched_getaffinity(0)))
     cfg = R.OracleConfig(test=test)
-    probe = min(s.n_events, 5000)
-    _, _, _, dt = R.select_set(s.subset(0, probe), cfg, n_threads=threads)
-    per_event = max(dt, 1e-6) / probe
-    n = int(min(s.n_events, max(probe, target_s / per_event)))
-    sub = s.subset(0, n)
-    counts, _, _, dt = R.select_set(sub, cfg, n_threads=threads)
+
+    def sized(n_threads, budget):
+        probe = min(s.n_events, 2000 if n_threads == 1 else 5000)
+        _, _, _, dt = R.select_set(s.subset(0, probe), cfg, n_threads=n_threads)
+        per_event = max(dt, 1e-6) / probe
+        n = int(min(s.n_events, max(probe, budget / per_event)))
+        counts, _, _, dt = R.select_set(s.subset(0, n), cfg, n_threads=n_threads)
+        return n, dt, counts
+
+    n, dt, counts = sized(threads, target_s)
+    n1, dt1, counts1 = sized(1, target_s)
+    if not np.array_equal(counts1, counts[:n1] if n1 <= n else counts1):
+        print("bench.py: the oracle's counts depend on its thread count", file=sys.stderr)
+        sys.exit(1)
+    import platform
+    cpu = platform.processor() or platform.machine()
+    try:
+        with open("/proc/cpuinfo") as f:
+            cpu = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), cpu)
+    except OSError:
+        pass
     return {"value": n / dt, "unit": "events/s", "cores": threads, "kind": "oracle",
             "sample": f"first {n} events of the workload, plain C oracle (gcc -O2, fp contraction "
-                      f"off), {threads} threads, compute only, {dt:.2f} s"}, counts
+                      f"off), {threads} threads, compute only, {dt:.2f} s",
+            "host_cpu": cpu,
+            "one_thread": {"value": n1 / dt1, "unit": "events/s", "cores": 1,
+                           "sample": f"first {n1} events, 1 thread, compute only, {dt1:.2f} s"}}, counts
 
 
 def filter_leg(n_events, reps=20, seed=0):
@@ -340,8 +375,8 @@ def main():
         f"dominant kernel {main_r['kernel_ms_mean']:.3f} ms")
 
     # algorithmic bytes of the dominant kernel: 12 B of offsets per event,
-    # 8 B per hit, 4 B count per event (plain kernel: +1 B flag)
-    kern_bytes = 12 * n_ev + 8 * hits + 4 * n_ev
+    # 8 B per hit, 4 B count and 1 B flag per event
+    kern_bytes = 12 * n_ev + 8 * hits + 5 * n_ev
     kern_s = main_r["kernel_ms_mean"] / 1e3
     tuned = main_r["autotuned"]
     if tuned:
@@ -408,6 +443,16 @@ def main():
         log(f"[bench] filter: {filt['ms']:.3f} ms, {filt['events_per_s']:.4g} events/s, "
             f"{filt['roofline']['achieved']:.0f} GB/s")
 
+    probes = None
+    if not args.only_form:
+        from paper_1810_11966_amd import probe
+        log("[bench] device probes: fp32 VALU rate, copy bandwidth")
+        probes = {"valu_f32_tops": probe.measure_valu(torch) / 1e12,
+                  "copy_gbs": probe.measure_copy(torch) / 1e9,
+                  "valu_note": "non-fused, non-packed fp32 mul/add, 16 independent ops per thread and iteration",
+                  "copy_note": "1 GiB float4 copy, read + write bytes per second"}
+        log(f"[bench] probes: {probes['valu_f32_tops']:.1f} T fp32 ops/s, {probes['copy_gbs']:.0f} GB/s copy")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline")
@@ -444,6 +489,7 @@ def main():
         "p99_slice_latency_ms": serving["p99_ms"] if serving else None,
         "serving": serving,
         "station_filter": filt,
+        "device_probes": probes,
         **extra,
     }
     print(json.dumps(out), flush=True)

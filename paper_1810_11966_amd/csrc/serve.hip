@@ -27,19 +27,21 @@ constexpr size_t kAlign = 256;
 size_t r256(size_t b) { return (b + kAlign - 1) & ~(kAlign - 1); }
 
 // Byte layout of one slice, identical in pinned staging and in HBM:
-// offsets | x | y | status | counts | accept | ids | n_accepted [| workspace]
+// offsets | x | y | status | n_accepted | counts | accept | ids [| workspace]
+// Results come back in two copies: status to accept at once, then the first
+// n_accepted ids once that number is on the host.
 struct Layout {
-    size_t off, x, y, status, counts, accept, ids, n_acc, ws, host_bytes, dev_bytes;
+    size_t off, x, y, status, n_acc, counts, accept, ids, ws, host_bytes, dev_bytes;
     Layout(int64_t n_events, int64_t n_hits, size_t ws_bytes) {
         size_t at = 0;
         off = at; at += r256(4 * (size_t)(3 * n_events + 1));
         x = at; at += r256(4 * (size_t)n_hits);
         y = at; at += r256(4 * (size_t)n_hits);
         status = at; at += r256(4);
+        n_acc = at; at += r256(4);
         counts = at; at += r256(4 * (size_t)n_events);
         accept = at; at += r256((size_t)n_events);
         ids = at; at += r256(4 * (size_t)(n_events > 0 ? n_events : 1));
-        n_acc = at; at += r256(4);
         host_bytes = at;
         ws = at; at += r256(ws_bytes);
         dev_bytes = at;
@@ -88,6 +90,7 @@ struct Slice {
     size_t staged = 0;    // bytes of the input prefix (offsets | x | y) in pinned staging
     size_t issued = 0;    // bytes of it whose copy to the device is enqueued
     bool launched = false;  // selection and result copy enqueued
+    bool ids_issued = false;  // copy of the accepted ids enqueued (after the first result copy)
     int stream = -1;
     State state = State::Queued;
     int32_t status = TRIG_OK;
@@ -163,8 +166,7 @@ struct trig_server {
         if (rc == TRIG_OK && s.issued < total) return;  // more to come
         s.launched = true;
         if (rc == TRIG_OK &&
-            hipMemcpyAsync(d + L.status, h + L.status, L.counts - L.status, hipMemcpyHostToDevice, st) !=
-                hipSuccess)
+            hipMemcpyAsync(d + L.status, h + L.status, 4, hipMemcpyHostToDevice, st) != hipSuccess)
             rc = TRIG_EHIP;
         if (rc == TRIG_OK) {
             trig_params p = cfg.params;
@@ -180,10 +182,30 @@ struct trig_server {
                              reinterpret_cast<uint8_t*>(d + L.accept), st);
         }
         if (rc == TRIG_OK &&
-            hipMemcpyAsync(h + L.status, d + L.status, L.host_bytes - L.status, hipMemcpyDeviceToHost, st) != hipSuccess)
+            hipMemcpyAsync(h + L.status, d + L.status, L.ids - L.status, hipMemcpyDeviceToHost, st) != hipSuccess)
             rc = TRIG_EHIP;
         if (rc == TRIG_OK && hipEventRecord(events[s.stream], st) != hipSuccess) rc = TRIG_EHIP;
         s.status = rc;
+    }
+
+    // After the first result copy (mu held): enqueues the copy of the
+    // n_accepted ids the host now holds; returns false if there are none.
+    bool issue_ids(Slice& s) {
+        s.ids_issued = true;
+        const Layout L(s.n_events, s.n_hits, s.ws_bytes);
+        char* h = pin_base + s.pin_off;
+        int32_t n = 0;
+        std::memcpy(&n, h + L.n_acc, 4);
+        n = std::max(0, std::min(n, s.n_events));
+        if (n == 0) return false;
+        hipStream_t st = streams[s.stream];
+        if (hipMemcpyAsync(h + L.ids, dev_base + s.dev_off + L.ids, 4 * (size_t)n, hipMemcpyDeviceToHost, st) !=
+                hipSuccess ||
+            hipEventRecord(events[s.stream], st) != hipSuccess) {
+            s.status = TRIG_EHIP;
+            return false;
+        }
+        return true;
     }
 
     // Marks a slice finished (mu held): frees its device memory and stream.
@@ -229,6 +251,10 @@ struct trig_server {
                     continue;
                 }
                 if (s.status != TRIG_OK || hipEventQuery(events[si]) == hipSuccess) {
+                    if (s.status == TRIG_OK && !s.ids_issued && issue_ids(s)) {
+                        busy = true;  // the ids are on their way
+                        continue;
+                    }
                     finish(s);
                     any = true;
                 } else {

@@ -162,14 +162,17 @@ class Server:
 
 
 def run_stream(server: Server, slices, arrivals_s, pace: bool = True, poll_ms: int = 1,
-               deadline_s: float = 300.0, submit_threads: int = 1):
+               deadline_s: float = 300.0, submit_threads: int = 1, trace: Optional[dict] = None):
     """Submits ``slices`` (EventSet-like objects with offsets, x, y) at
     ``arrivals_s`` (seconds from now; if pace is False, as fast as possible)
     and returns {ticket: Finished} plus the index -> ticket map and the wall
     time.  With ``submit_threads`` > 1, slices are submitted by that many
     threads (concurrent arrivals stage in parallel; each thread takes the next
     slice in arrival order).  Busy servers are retried after a short wait.
-    Raises TimeoutError if the stream has not finished after ``deadline_s``."""
+    Raises TimeoutError if the stream has not finished after ``deadline_s``.
+    ``trace`` (a dict) receives per slice index: how late its submitter woke
+    after the arrival time, the busy retries, and the seconds spent in the
+    accepted submit call (the host copy into pinned staging)."""
     import threading
 
     done, tickets = {}, {}
@@ -190,10 +193,13 @@ def run_stream(server: Server, slices, arrivals_s, pace: bool = True, poll_ms: i
                 if dt > 0:
                     time.sleep(dt)
             s = slices[i]
+            woke = time.perf_counter() - start
+            retries = 0
             while True:
                 if time.perf_counter() - start > deadline_s:
                     errors.append(TimeoutError(f"slice {i} not accepted before the deadline"))
                     return
+                t_call = time.perf_counter()
                 try:
                     t = server.submit(s.offsets, s.x, s.y)
                 except Exception as e:  # surfaced in the caller
@@ -202,7 +208,11 @@ def run_stream(server: Server, slices, arrivals_s, pace: bool = True, poll_ms: i
                 if t is not None:
                     with lock:
                         tickets[i] = t
+                        if trace is not None:
+                            trace[i] = {"wake_late_s": woke - (arrivals_s[i] if pace else 0.0),
+                                        "busy_retries": retries, "submit_call_s": time.perf_counter() - t_call}
                     break
+                retries += 1
                 time.sleep(poll_ms / 1e3)
 
     threads = [threading.Thread(target=submitter, daemon=True) for _ in range(max(1, submit_threads))]
