@@ -242,6 +242,26 @@ size_t trig_workspace_bytes(const trig_events_csr *ev, const trig_params *p);
 int trig_select(const trig_events_csr *ev, const trig_hits *hits, const trig_params *p,
                 int32_t *out_counts, uint8_t *out_accept, void *stream);
 
+/* Bytes of the library's static device scratch used by trig_select_noalloc. */
+#define TRIG_NOALLOC_SCRATCH_BYTES (4u << 20)
+
+/* trig_select without a caller workspace and without any allocation, for
+ * callers that cannot allocate: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc.  Same arguments, outputs and errors
+ * as trig_select, except that p->workspace must be NULL and
+ * p->workspace_bytes 0 (else TRIG_EINVAL): the kernels use a static device
+ * array of TRIG_NOALLOC_SCRATCH_BYTES that every GPU the library runs on
+ * holds until the process ends (its address is looked up on the first call
+ * on each device).  A batch whose trig_workspace_bytes() exceeds that size
+ * gets TRIG_EWORKSPACE before anything is enqueued: with TRIG_EXEC_PERSISTENT
+ * alone (8 bytes per event) about 520,000 events at most; every other form
+ * up to n_events of 2^31 - 1.  The kernels reset what must start at zero;
+ * the array keeps the last call's contents.  All calls on one GPU share the
+ * array: calls that overlap in time on one GPU (other streams, other host
+ * threads) race and must be serialised by the caller. */
+int trig_select_noalloc(const trig_events_csr *ev, const trig_hits *hits, const trig_params *p,
+                        int32_t *out_counts, uint8_t *out_accept, void *stream);
+
 /* Result of trig_autotune (host). */
 typedef struct {
     int32_t n_candidates;     /* launch shapes timed (0 for an empty batch) */

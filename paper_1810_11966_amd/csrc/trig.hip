@@ -425,6 +425,14 @@ __global__ __launch_bounds__(kTwoWaves * kWave) void k_two_particles(const int32
     }
 }
 
+// ------------------------------------------------------- static scratch ---
+
+// Device scratch of trig_select_noalloc: the workspace of trig_select for
+// callers that cannot allocate.  Every GPU the library runs on holds its own
+// copy until the process ends; kernels receive its device address (looked up
+// once per device), never this host-side name.
+static __device__ __align__(256) unsigned char scratch[TRIG_NOALLOC_SCRATCH_BYTES];
+
 // ------------------------------------------------------------------ host ---
 
 thread_local std::string g_detail;
@@ -443,6 +451,28 @@ int mark_stop(hipStream_t s) {
 int fail(int code, const std::string& why) {
     g_detail = why;
     return code;
+}
+
+// Device address of `scratch` on the current device, looked up on the first
+// call per device (that device current) and kept.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices] = {};
+
+int scratch_address(void** out) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices)
+        return fail(TRIG_EHIP, "no current device (or a device index beyond 63)");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(TRIG_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_dev[dev] = ptr;
+    }
+    *out = g_scratch_dev[dev];
+    return TRIG_OK;
 }
 
 size_t align256(size_t v) { return (v + 255) & ~(size_t)255; }
@@ -1034,6 +1064,26 @@ int trig_autotune(const trig_events_csr* ev, const trig_hits* hits, const trig_p
     if (out) *out = res;
     g_detail.clear();
     return TRIG_OK;
+}
+
+int trig_select_noalloc(const trig_events_csr* ev, const trig_hits* hits, const trig_params* p,
+                        int32_t* out_counts, uint8_t* out_accept, void* stream) {
+    if (!ev || !hits || !p) return fail(TRIG_EINVAL, "NULL descriptor");
+    if (p->workspace || p->workspace_bytes)
+        return fail(TRIG_EINVAL, "trig_select_noalloc uses the library's scratch: workspace must be NULL, "
+                                 "workspace_bytes 0");
+    const size_t need = trig_workspace_bytes(ev, p);
+    if (need > (size_t)TRIG_NOALLOC_SCRATCH_BYTES)
+        return fail(TRIG_EWORKSPACE, "this batch and these flags need " + std::to_string(need) +
+                                         " bytes of scratch, more than the " +
+                                         std::to_string((size_t)TRIG_NOALLOC_SCRATCH_BYTES) +
+                                         " of trig_select_noalloc");
+    trig_params q = *p;
+    if (need) {
+        if (int r = scratch_address(&q.workspace)) return r;
+        q.workspace_bytes = TRIG_NOALLOC_SCRATCH_BYTES;
+    }
+    return trig_select(ev, hits, &q, out_counts, out_accept, stream);
 }
 
 int trig_set_kernel_events(void* start, void* stop) {

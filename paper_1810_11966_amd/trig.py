@@ -28,6 +28,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(PKG, "libtrig.so")
 
 TRIG_ABI_VERSION = 2
+TRIG_NOALLOC_SCRATCH_BYTES = 4 << 20
 TRIG_OK, TRIG_EINVAL, TRIG_EWORKSPACE, TRIG_EHIP, TRIG_EUNSUPPORTED = 0, -1, -2, -3, -4
 TRIG_COUNT_MALFORMED, TRIG_COUNT_OVERFLOW = -1, -2
 TRIG_STATUS_MALFORMED, TRIG_STATUS_OVERFLOW = 1, 2
@@ -48,7 +49,7 @@ FORMS = {
 }
 
 # Every symbol include/trig.h declares.
-EXPORTED = ("trig_params_init", "trig_params_check", "trig_workspace_bytes", "trig_select",
+EXPORTED = ("trig_params_init", "trig_params_check", "trig_workspace_bytes", "trig_select", "trig_select_noalloc",
             "trig_autotune", "trig_autotune_reset", "trig_set_kernel_events", "trig_strerror", "trig_last_error_detail", "trig_probe_valu",
             "trig_probe_copy", "trig_server_create", "trig_server_submit", "trig_server_poll",
             "trig_server_release", "trig_server_pause", "trig_server_stats_get", "trig_server_now", "trig_server_destroy",
@@ -107,6 +108,8 @@ def load(path: str = LIB_PATH):
     lib.trig_select.argtypes = [ctypes.POINTER(TrigEventsCsr), ctypes.POINTER(TrigHits),
                                 ctypes.POINTER(TrigParams), ctypes.c_void_p, ctypes.c_void_p,
                                 ctypes.c_void_p]
+    lib.trig_select_noalloc.restype = ctypes.c_int
+    lib.trig_select_noalloc.argtypes = lib.trig_select.argtypes
     lib.trig_autotune.restype = ctypes.c_int
     lib.trig_autotune.argtypes = [ctypes.POINTER(TrigEventsCsr), ctypes.POINTER(TrigHits),
                                   ctypes.POINTER(TrigParams), ctypes.c_void_p, ctypes.c_void_p,
@@ -175,6 +178,15 @@ def trig_select(events: TrigEventsCsr, hits: TrigHits, params: TrigParams, out_c
     return int(load().trig_select(ctypes.byref(events), ctypes.byref(hits), ctypes.byref(params),
                                   ctypes.c_void_p(out_counts or None), ctypes.c_void_p(out_accept or None),
                                   ctypes.c_void_p(stream or None)))
+
+
+def trig_select_noalloc(events: TrigEventsCsr, hits: TrigHits, params: TrigParams, out_counts: int,
+                        out_accept: int, stream: int) -> int:
+    """Raw call of the allocation-free variant (params.workspace must be
+    None, workspace_bytes 0): the library's static device scratch."""
+    return int(load().trig_select_noalloc(ctypes.byref(events), ctypes.byref(hits), ctypes.byref(params),
+                                          ctypes.c_void_p(out_counts or None), ctypes.c_void_p(out_accept or None),
+                                          ctypes.c_void_p(stream or None)))
 
 
 def trig_autotune(events: TrigEventsCsr, hits: TrigHits, params: TrigParams, out_counts: int,

@@ -278,3 +278,17 @@ def test_binned_interval_widening_covers_one_step():
     assert (down <= np.nextafter(vals, f32(-np.inf))).all()
     assert (up >= np.nextafter(vals, f32(np.inf))).all()
 
+
+def test_noalloc_rejects_before_any_launch(lib):
+    """trig_select_noalloc takes no workspace, and refuses a batch whose
+    scratch need exceeds its static array before touching the device."""
+    p = trig.make_params(flags=trig.TRIG_EXEC_PERSISTENT)
+    ev = trig.TrigEventsCsr(1_000_000, 0x1000)
+    hits = trig.TrigHits(12, 0x2000, 0x3000)
+    assert trig.trig_workspace_bytes(1_000_000, p) > trig.TRIG_NOALLOC_SCRATCH_BYTES
+    assert trig.trig_select_noalloc(ev, hits, p, 0x4000, 0x5000, 0) == trig.TRIG_EWORKSPACE
+    assert "scratch" in trig.trig_last_error_detail()
+    p.workspace = 0x10000
+    p.workspace_bytes = 1 << 30
+    assert trig.trig_select_noalloc(ev, hits, p, 0x4000, 0x5000, 0) == trig.TRIG_EINVAL
+    assert lib.trig_select_noalloc(None, None, None, None, None, None) == trig.TRIG_EINVAL
