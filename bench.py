@@ -75,6 +75,7 @@ def parse():
                     help="timeslices of the serving leg (0 = skip it)")
     ap.add_argument("--serve-load", type=float, default=1e7, help="offered load of the serving leg, events/s")
     ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--no-extra-legs", action="store_true", help="skip the two-particle and per-hit z legs")
     ap.add_argument("--filter-events", type=int, default=100_000,
                     help="events of the station-filter leg (0: skip it)")
     return ap.parse_args()
@@ -296,6 +297,73 @@ def cpu_baseline(s, test, target_s):
                            "sample": f"first {n1} events, 1 thread, compute only, {dt1:.2f} s"}}, counts
 
 
+def _timed_calls(torch, trig, dev_in, n_ev, form, test, steps, extra_flags=0, hit_z=None):
+    """Mean ms of one trig_select call (steps after one warm-up) and its
+    outputs."""
+    off, x, y = dev_in
+    r = None
+    for _ in range(1 + steps):
+        if r is None:
+            r = trig.select(off, x, y, hit_z=hit_z, test=test, form=form, compact=True, extra_flags=extra_flags)
+            torch.cuda.synchronize()
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record()
+        else:
+            trig.select(off, x, y, hit_z=hit_z, test=test, form=form, compact=True, extra_flags=extra_flags,
+                        workspace=r.workspace, out=(r.counts, r.accept))
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps, r
+
+
+def two_particle_leg(torch, trig, dev_in, n_ev, test, steps=10):
+    """Two-particle acceptance (two passing triplets with no common hit) in
+    the autotuned form on the resident batch: time per call and accepted
+    events, beside the count mode."""
+    ms, r = _timed_calls(torch, trig, dev_in, n_ev, "auto", test, steps, trig.TRIG_ACCEPT_TWO_PARTICLES)
+    ms_c, rc = _timed_calls(torch, trig, dev_in, n_ev, "auto", test, steps)
+    if not torch.equal(r.counts, rc.counts):
+        print("bench.py: two-particle mode changed the counts", file=sys.stderr)
+        sys.exit(1)
+    return {"ms": ms, "events_per_s": n_ev / (ms * 1e-3), "accepted": int(r.n_accepted.item()),
+            "count_mode_ms": ms_c, "count_mode_accepted": int(rc.n_accepted.item()),
+            "form": "autotuned counting form, then the two-particle kernel on events with two or more passing triplets"}
+
+
+def per_hit_z_leg(torch, trig, s, test, steps=5, oracle_events=5000):
+    """The same events on staggered modules (each hit at z_l -/+ 0.75 cm by
+    azimuthal sector, its own z per hit): the per-event slope-pruned form and
+    the every-triplet form, identical counts, and the oracle on the first
+    events."""
+    from paper_1810_11966_amd import synth
+    sz = synth.staggered(s)
+    d = torch.device("cuda:0")
+    dev_in = tuple(torch.from_numpy(a).to(d) for a in (sz.offsets, sz.x, sz.y))
+    zt = torch.from_numpy(sz.z).to(d)
+    out = {"workload": "the medium workload's events on staggered modules: z_l -/+ 0.75 cm by azimuthal "
+                       "sector (16 sectors), hits moved along their line of sight"}
+    ref = None
+    for form in ("pruned", "plain"):
+        ms, r = _timed_calls(torch, trig, dev_in, sz.n_events, form, test, steps, hit_z=zt)
+        out[form] = {"ms": ms, "events_per_s": sz.n_events / (ms * 1e-3)}
+        if ref is None:
+            ref = r.counts.clone()
+        elif not torch.equal(ref, r.counts):
+            print("bench.py: per-hit z forms disagree", file=sys.stderr)
+            sys.exit(1)
+    from oracle import reference as R
+    sub = sz.subset(0, oracle_events)
+    c = R.select_set(sub, R.OracleConfig(test=test), n_threads=max(1, len(os.sched_getaffinity(0))))[0]
+    if not np.array_equal(ref[:oracle_events].cpu().numpy(), c):
+        print("bench.py: per-hit z counts differ from the oracle", file=sys.stderr)
+        sys.exit(1)
+    out["oracle_sample_bit_exact"] = f"first {oracle_events} events"
+    out["pruned_vs_plain"] = out["plain"]["ms"] / out["pruned"]["ms"]
+    del dev_in, zt
+    torch.cuda.empty_cache()
+    return out
+
+
 def filter_leg(n_events, reps=20, seed=0):
     """Trigger-station filtering (include/trig_filter.h) on events with about
     5000 hits on 16 stations in detector order (the trigger layers are three
@@ -436,6 +504,17 @@ def main():
         log(f"[bench] serving: p50 {serving['p50_ms']:.2f} ms, p99 {serving['p99_ms']:.2f} ms, "
             f"{serving['events_per_s']:.4g} events/s")
 
+    two = hz = None
+    if not args.only_form and not args.no_extra_legs:
+        log("[bench] two-particle leg")
+        two = two_particle_leg(torch, trig, dev_in, n_ev, args.test)
+        log(f"[bench] two particles: {two['ms']:.3f} ms, {two['accepted']} accepted "
+            f"(count mode {two['count_mode_ms']:.3f} ms, {two['count_mode_accepted']})")
+        if args.test != "msd_basis":
+            log("[bench] per-hit z leg")
+            hz = per_hit_z_leg(torch, trig, s, args.test)
+            log(f"[bench] per-hit z: pruned {hz['pruned']['ms']:.3f} ms, plain {hz['plain']['ms']:.3f} ms")
+
     filt = None
     if args.filter_events > 0 and not args.only_form:
         log(f"[bench] station filter leg: {args.filter_events} events")
@@ -489,6 +568,8 @@ def main():
         "p99_slice_latency_ms": serving["p99_ms"] if serving else None,
         "serving": serving,
         "station_filter": filt,
+        "two_particles": two,
+        "per_hit_z": hz,
         "device_probes": probes,
         **extra,
     }

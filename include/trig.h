@@ -95,11 +95,25 @@ typedef struct {
     const int32_t *layer_offsets;
 } trig_events_csr;
 
-/* Hit coordinates, structure of arrays: device float32[n_hits] each, cm. */
+/* Hit coordinates, structure of arrays: device float32[n_hits] each, cm.
+ * z is optional: NULL takes the layer positions of trig_params.z; otherwise
+ * every hit carries its own z (staggered modules; the paper's hits carry a
+ * position each, Sec. 3.2 last paragraph) and each triplet is fitted with
+ * its hits' z:
+ *   TRIG_TEST_MSD: Szz = (zi*zi + zj*zj) + zk*zk, w = 1 / Szz (binary32
+ *     division), m = ((ci*zi + cj*zj) + ck*zk) * w, r_l = c_l - m*z_l,
+ *     Q = (r0*r0 + r1*r1) + r2*r2;
+ *   TRIG_TEST_SLOPE_WINDOW: s_l = c_l / z_l with each hit's z;
+ *   TRIG_TEST_MSD_BASIS: not provided (TRIG_EUNSUPPORTED).
+ * With per-hit z the batched, binned and autotuned forms run one wave per
+ * event from HBM, pruning pairs on their slopes c / z (a bound that every
+ * passing triplet meets, for events whose layer-0 and layer-1 z lie in
+ * (0, inf)); the plain and persistent forms test every triplet. */
 typedef struct {
     int32_t n_hits;
     const float *x;
     const float *y;
+    const float *z;
 } trig_hits;
 
 /* Triplet test (see the floating point contract above). */

@@ -31,6 +31,7 @@
 #include <mutex>
 #include <string>
 #include <tuple>
+#include <type_traits>
 #include <vector>
 
 #include "trig.h"
@@ -46,6 +47,7 @@ namespace {
 constexpr int kPlainWaves = 4;      // waves (events) per workgroup, plain form
 constexpr int kChunkMsd = 512;      // layer-2 hits per LDS chunk (2 floats each)
 constexpr int kChunkFit = 256;      // layer-2 hits per LDS chunk (4 floats each)
+constexpr int kChunkZ = 160;        // layer-2 hits per LDS chunk (6 floats each)
 constexpr int kScanBlock = 256;     // threads of the scan/compaction kernels
 constexpr int kCompactItems = 4;    // events per thread in compaction
 constexpr int kPersistWaves = 4;    // waves per workgroup, persistent form
@@ -62,6 +64,10 @@ template <>
 struct Chunk<WindowTest> { static constexpr int value = kChunkMsd; };
 template <>
 struct Chunk<MsdFitTest> { static constexpr int value = kChunkFit; };
+template <>
+struct Chunk<MsdZTest> { static constexpr int value = kChunkZ; };
+template <>
+struct Chunk<WindowZTest> { static constexpr int value = kChunkMsd; };
 
 __device__ __forceinline__ void write_result(int e, int32_t cnt, const Consts& c,
                                              int32_t* counts, uint8_t* accept,
@@ -76,7 +82,8 @@ __device__ __forceinline__ void write_result(int e, int32_t cnt, const Consts& c
 template <class T, int WPB>
 __global__ __launch_bounds__(WPB * kWave) void k_plain(const int32_t* __restrict__ off,
                                                        int n_events, const float* __restrict__ x,
-                                                       const float* __restrict__ y, Consts c,
+                                                       const float* __restrict__ y,
+                                                       const float* __restrict__ z, Consts c,
                                                        int32_t* __restrict__ counts,
                                                        uint8_t* __restrict__ accept,
                                                        uint32_t* status) {
@@ -89,7 +96,7 @@ __global__ __launch_bounds__(WPB * kWave) void k_plain(const int32_t* __restrict
     int32_t cnt = load_event(off, e, c.n_hits, ev);
     if (cnt == 0) {
         const uint32_t tiles = pair_tiles(ev);
-        if (tiles) cnt = (int32_t)wave_count<T, KCH>(x, y, ev, 0, tiles, c, lds_all[w]);
+        if (tiles) cnt = (int32_t)wave_count<T, KCH>(x, y, z, ev, 0, tiles, c, lds_all[w]);
     }
     if (lane_id() == 0) write_result(e, cnt, c, counts, accept, status);
 }
@@ -289,7 +296,8 @@ __device__ int wave_find_event(const int64_t* __restrict__ ustart, int n, int64_
 template <class T, int WPB>
 __global__ __launch_bounds__(WPB * kWave) void k_persistent(
     const int32_t* __restrict__ off, int n_events, const float* __restrict__ x,
-    const float* __restrict__ y, Consts c, const int64_t* __restrict__ ustart, int tile_units,
+    const float* __restrict__ y, const float* __restrict__ z, Consts c, const int64_t* __restrict__ ustart,
+    int tile_units,
     unsigned long long* counter, int32_t* counts) {
     constexpr int KCH = Chunk<T>::value;
     __shared__ __align__(16) float lds_all[WPB][KCH * T::HF];
@@ -318,7 +326,7 @@ __global__ __launch_bounds__(WPB * kWave) void k_persistent(
                 const uint32_t tiles = pair_tiles(ev);
                 const uint32_t tb = (uint32_t)((u - ustart[e]) * tile_units);
                 const uint32_t te = min(tiles, tb + (uint32_t)tile_units);
-                const uint32_t cnt = wave_count<T, KCH>(x, y, ev, tb, te, c, lds);
+                const uint32_t cnt = wave_count<T, KCH>(x, y, z, ev, tb, te, c, lds);
                 if (lane_id() == 0 && cnt) atomicAdd(&counts[e], (int32_t)cnt);
             }
         }
@@ -405,14 +413,20 @@ constexpr int kTwoWaves = 4;
 template <class P>
 __global__ __launch_bounds__(kTwoWaves * kWave) void k_two_particles(const int32_t* __restrict__ off, int n_events,
                                                                      const float* __restrict__ x,
-                                                                     const float* __restrict__ y, Consts c,
+                                                                     const float* __restrict__ y,
+                                                                     const float* __restrict__ z, Consts c,
                                                                      uint8_t* __restrict__ accept) {
     const int w = uniform_i((int)(threadIdx.x / kWave));
     const int64_t base = ((int64_t)blockIdx.x * kTwoWaves + w) * kWave;
     if (base >= n_events) return;
     const int64_t e = base + lane_id();
     uint64_t m = lanes(e < n_events && accept[e] != 0);
-    const GlobalHits gh{x, y};
+    using H = typename std::conditional<P::kZ, SlopeHits, GlobalHits>::type;
+    H gh;
+    if constexpr (P::kZ)
+        gh = SlopeHits{x, y, z};
+    else
+        gh = GlobalHits{x, y};
     while (m) {
         const int L = __builtin_ctzll(m);
         m &= m - 1;
@@ -423,6 +437,40 @@ __global__ __launch_bounds__(kTwoWaves * kWave) void k_two_particles(const int32
             two = wave_two_particles<P>(c, gh, ev.o0, ev.n0, ev.o1, ev.n1, ev.o2, ev.n2);
         if (lane_id() == 0) accept[ev_i] = (uint8_t)two;
     }
+}
+
+// ------------------------------------------------------------ per-hit z ---
+
+// Per-hit z (trig_hits.z), batched, binned and autotuned forms: one wave per
+// event from HBM, pairs pruned on their slopes with the event's bound
+// (wave_event_pruned over SlopeHits), or every triplet (wave_count) when the
+// event has no valid bound.
+template <class P, class T>
+__global__ __launch_bounds__(kBinWaves * kWave) void k_event_z(const int32_t* __restrict__ off, int n_events,
+                                                               const float* __restrict__ x,
+                                                               const float* __restrict__ y,
+                                                               const float* __restrict__ z, Consts c,
+                                                               int32_t* __restrict__ counts,
+                                                               uint8_t* __restrict__ accept, uint32_t* status) {
+    constexpr int KCH = Chunk<T>::value;
+    static_assert(KCH * T::HF >= 2 * kPBuf, "the pruned path's buffers fit in the staging slice");
+    __shared__ __align__(16) float lds_all[kBinWaves][KCH * T::HF];
+    const int w = uniform_i((int)(threadIdx.x / kWave));
+    const int64_t e64 = (int64_t)blockIdx.x * kBinWaves + w;
+    if (e64 >= n_events) return;
+    const int e = (int)e64;
+    float* lds = lds_all[w];
+    EventRange ev;
+    int32_t cnt = load_event(off, e, c.n_hits, ev);
+    if (cnt == 0 && ev.n0 > 0 && ev.n1 > 0 && ev.n2 > 0) {
+        const SlopeHits sh{x, y, z};
+        const PairBounds pb = event_bounds<P>(c, sh, ev.o0, ev.n0, ev.o1, ev.n1);
+        if (pb.prune)
+            cnt = (int32_t)wave_event_pruned<P>(c, pb, sh, ev.o0, ev.n0, ev.o1, ev.n1, ev.o2, ev.n2, lds, lds + kPBuf);
+        else
+            cnt = (int32_t)wave_count<T, KCH>(x, y, z, ev, 0, pair_tiles(ev), c, lds);
+    }
+    if (lane_id() == 0) write_result(e, cnt, c, counts, accept, status);
 }
 
 // ------------------------------------------------------- static scratch ---
@@ -505,6 +553,11 @@ Consts make_consts(const trig_params* p, int n_hits) {
     c.fit_a1y = fy.a1;
     c.fit_b0x = fx.b0;
     c.fit_b1x = fx.b1;
+    const SlopeBounds sx = slope_bounds(c.qmax_x), sy = slope_bounds(c.qmax_y);
+    c.zs_a0x = sx.a0;
+    c.zs_a1x = sx.a1;
+    c.zs_a0y = sy.a0;
+    c.zs_a1y = sy.a1;
     c.pre_msd = std::max(c.beta_x, c.beta_y);
     c.pre_win = std::max(p->slope_window[0], p->slope_window[1]);
     c.win_x = p->slope_window[0];
@@ -525,7 +578,10 @@ int validate(const trig_events_csr* ev, const trig_hits* hits, const trig_params
     if (hits->n_hits < 0) return fail(TRIG_EINVAL, "n_hits < 0");
     if (ev->n_events > 0 && !ev->layer_offsets) return fail(TRIG_EINVAL, "layer_offsets is NULL");
     if (hits->n_hits > 0 && (!hits->x || !hits->y)) return fail(TRIG_EINVAL, "x or y is NULL");
-    return validate_params(p, true);
+    if (int r = validate_params(p, true)) return r;
+    if (hits->z && p->test == TRIG_TEST_MSD_BASIS)
+        return fail(TRIG_EUNSUPPORTED, "per-hit z is not provided for TRIG_TEST_MSD_BASIS");
+    return TRIG_OK;
 }
 
 int validate_params(const trig_params* p, bool need_outputs) {
@@ -626,7 +682,7 @@ int launch_plain(const trig_events_csr* ev, const trig_hits* h, const Consts& c,
     const unsigned grid = (unsigned)cdiv(n, kPlainWaves);
     if (mark_start(s)) return fail(TRIG_EHIP, "hipEventRecord(start)");
     hipLaunchKernelGGL((k_plain<T, kPlainWaves>), dim3(grid), dim3(kPlainWaves * kWave), 0, s,
-                       ev->layer_offsets, n, h->x, h->y, c, counts, accept, status);
+                       ev->layer_offsets, n, h->x, h->y, h->z, c, counts, accept, status);
     if (int r = check_launch("k_plain")) return r;
     if (mark_stop(s)) return fail(TRIG_EHIP, "hipEventRecord(stop)");
     return TRIG_OK;
@@ -653,7 +709,7 @@ int launch_persistent(const trig_events_csr* ev, const trig_hits* h, const Const
     const unsigned grid = (unsigned)device_cus() * 8u;
     if (mark_start(s)) return fail(TRIG_EHIP, "hipEventRecord(start)");
     hipLaunchKernelGGL((k_persistent<T, kPersistWaves>), dim3(grid), dim3(kPersistWaves * kWave), 0, s,
-                       ev->layer_offsets, n, h->x, h->y, c, ustart, tile_units, counter, counts);
+                       ev->layer_offsets, n, h->x, h->y, h->z, c, ustart, tile_units, counter, counts);
     if (int r = check_launch("k_persistent")) return r;
     if (mark_stop(s)) return fail(TRIG_EHIP, "hipEventRecord(stop)");
     hipLaunchKernelGGL(k_finalize, dim3(L.unit_blocks), dim3(kScanBlock), 0, s, n, c, counts, accept);
@@ -779,8 +835,30 @@ int launch_two_particles(const trig_events_csr* ev, const trig_hits* h, const Co
                          hipStream_t s) {
     const int64_t waves = cdiv(ev->n_events, kWave);
     hipLaunchKernelGGL(k_two_particles<P>, dim3((unsigned)cdiv(waves, kTwoWaves)), dim3(kTwoWaves * kWave), 0, s,
-                       ev->layer_offsets, ev->n_events, h->x, h->y, c, accept);
+                       ev->layer_offsets, ev->n_events, h->x, h->y, h->z, c, accept);
     return check_launch("k_two_particles");
+}
+
+// Per-hit z: brute force as asked, every other form one wave per event with
+// slope pruning (k_event_z).
+template <class T, class P>
+int run_form_z(const trig_events_csr* ev, const trig_hits* h, const trig_params* p, const Consts& c,
+               const Layout& L, char* ws, int32_t* counts, uint8_t* accept, hipStream_t s) {
+    int r = TRIG_OK;
+    if (p->flags & (TRIG_EXEC_PRUNED | TRIG_EXEC_BINNED)) {
+        if (mark_start(s)) return fail(TRIG_EHIP, "hipEventRecord(start)");
+        hipLaunchKernelGGL((k_event_z<P, T>), dim3((unsigned)cdiv(ev->n_events, kBinWaves)), dim3(kBinWaves * kWave),
+                           0, s, ev->layer_offsets, ev->n_events, h->x, h->y, h->z, c, counts, accept, p->out_status);
+        if ((r = check_launch("k_event_z"))) return r;
+        if (mark_stop(s)) return fail(TRIG_EHIP, "hipEventRecord(stop)");
+    } else if (p->flags & TRIG_EXEC_PERSISTENT) {
+        const int tile_units = p->tile_pairs ? p->tile_pairs / kWave : kDefaultTileUnits;
+        r = launch_persistent<T>(ev, h, c, tile_units, L, ws, counts, accept, p->out_status, s);
+    } else {
+        r = launch_plain<T>(ev, h, c, counts, accept, p->out_status, s);
+    }
+    if (r == TRIG_OK && (p->flags & TRIG_ACCEPT_TWO_PARTICLES)) r = launch_two_particles<P>(ev, h, c, accept, s);
+    return r;
 }
 
 template <class T, class P, class B>
@@ -914,7 +992,13 @@ int trig_select(const trig_events_csr* ev, const trig_hits* hits, const trig_par
     char* ws = static_cast<char*>(p->workspace);
     const Consts c = make_consts(p, hits->n_hits);
 
-    if (n > 0) {
+    if (n > 0 && hits->z) {
+        // per-hit z (validated: not with the basis form)
+        const int r = p->test == TRIG_TEST_MSD
+                          ? run_form_z<MsdZTest, MsdZPrune>(ev, hits, p, c, L, ws, out_counts, out_accept, s)
+                          : run_form_z<WindowZTest, WindowZPrune>(ev, hits, p, c, L, ws, out_counts, out_accept, s);
+        if (r) return r;
+    } else if (n > 0) {
         int r = TRIG_OK;
         switch (p->test) {
             case TRIG_TEST_MSD:

@@ -379,11 +379,11 @@ __device__ uint32_t wave_event_binned(const Consts& c, const float* __restrict__
     float xi = x[o0 + min(lane, n0 - 1)], yi = y[o0 + min(lane, n0 - 1)];
     float M = 0.0f;  // largest layer-1 |x|, |y| (rounds past the layer hold 0 or a layer-1 hit)
     if constexpr (B::kMag) {
-        float m = 0.0f;
+        uint32_t m = 0u;
 #pragma unroll
         for (int r = 0; r < kBinRounds; ++r)
-            if (r * kWave < n1) m = mag4(m, h1.x[r], h1.y[r], 0.0f, 0.0f);
-        M = wave_max_f(m);
+            if (r * kWave < n1) m = max(m, max(abs_bits(h1.x[r]), abs_bits(h1.y[r])));
+        M = wave_max_f(mag_of(m));
     }
     const BinBounds bb = B::bounds(c, M);
     const Bins b1 = build_bins<typename B::Key1>(c, h1, n1, L.end1, L.a1, L.b1);

@@ -103,14 +103,28 @@ __device__ float layer_mag(const H& hits, int o, int n) {
 
 // Pair test bounds of a block or event: the exact pair test is
 // |a_x| <= bx and |a_y| <= by (window: strict), and the prefilter score of a
-// pair that passes it is at most pre.
+// pair that passes it is at most pre.  prune = false: no valid bound (per-hit
+// z outside (0, inf) in layers 0 or 1): every pair must be completed.
 struct PairBounds {
     float bx, by, pre;
+    bool prune = true;
+};
+
+// Per-hit z: hits read from HBM whose at() gives the slopes (x / z, y / z),
+// the partials the per-hit-z pair tests compare; x, y and z stay reachable
+// for the completion.
+struct SlopeHits {
+    const float* x;
+    const float* y;
+    const float* z;
+    __device__ __forceinline__ float2 at(int h) const { return make_float2(x[h] / z[h], y[h] / z[h]); }
 };
 
 // TRIG_TEST_MSD_BASIS.
 struct MsdBasisPrune {
     static constexpr bool kMag = false;  // bounds do not depend on M
+    static constexpr bool kEventBounds = false;
+    static constexpr bool kZ = false;
     __device__ static __forceinline__ PairBounds bounds(const Consts& c, float) {
         return PairBounds{c.beta_x, c.beta_y, c.pre_msd};
     }
@@ -193,6 +207,8 @@ struct MsdBasisPrune {
 // written out.
 struct MsdFitPrune {
     static constexpr bool kMag = true;  // bounds grow with M >= |c_j|
+    static constexpr bool kEventBounds = false;
+    static constexpr bool kZ = false;
     __device__ static __forceinline__ PairBounds bounds(const Consts& c, float M) {
         const float bx = c.fit_a0x + c.fit_a1x * M;
         const float by = c.fit_a0y + c.fit_a1y * M;
@@ -241,6 +257,8 @@ struct MsdFitPrune {
 
 struct WindowPrune {
     static constexpr bool kMag = false;
+    static constexpr bool kEventBounds = false;
+    static constexpr bool kZ = false;
     __device__ static __forceinline__ PairBounds bounds(const Consts& c, float) {
         return PairBounds{c.win_x, c.win_y, c.pre_win};
     }
@@ -293,6 +311,121 @@ struct WindowPrune {
         return lanes(__builtin_fabsf(s.x - sxi) < c.win_x) & lanes(__builtin_fabsf(s.y - syi) < c.win_y);
     }
 };
+
+// Per-hit z, TRIG_TEST_MSD: pairs pruned on their slopes (SlopeHits gives
+// s = c / z): a triplet that passes a plane has |f32(s_j - s_i)| <=
+// (a0 + a1 M) / zmin (csrc/trig_bounds.hpp), M and zmin over the event's
+// layers 0 and 1; survivors completed with the per-hit-z fit.
+struct MsdZPrune {
+    static constexpr bool kMag = false;
+    static constexpr bool kEventBounds = true;
+    static constexpr bool kZ = true;  // reads hits through SlopeHits
+    __device__ static __forceinline__ float2 layer0(const Consts&, float2 s) { return s; }
+    __device__ static __forceinline__ float2 layer1(const Consts&, float2 s) { return s; }
+    __device__ static __forceinline__ float2 layer(const Consts&, float2 s, int) { return s; }
+    // M, zmin and zmax over layers 0 and 1 (raw coordinates), by the wave.
+    __device__ static PairBounds event_bounds(const Consts& c, const SlopeHits& h, int o0, int n0, int o1, int n1) {
+        float m = 0.0f, zlo = __builtin_inff(), zhi = 0.0f;
+        bool bad = false;
+        for (int t = (int)lane_id(); t < n0 + n1; t += kWave) {
+            const int q = t < n0 ? o0 + t : o1 + (t - n0);
+            const float z = h.z[q];
+            m = __builtin_fmaxf(m, __builtin_fmaxf(__builtin_fabsf(h.x[q]), __builtin_fabsf(h.y[q])));
+            bad |= !(z > 0.0f && z < __builtin_inff());
+            zlo = __builtin_fminf(zlo, z);
+            zhi = __builtin_fmaxf(zhi, z);
+        }
+        PairBounds b;
+        const float M = wave_max_f(m), zmin = wave_min_f(zlo);
+        const float inv = 1.0f / zmin;
+        // every z of layers 0 and 1 in (0, inf), and no slope that can
+        // overflow (|c| / z <= M / zmin < 2^126): otherwise no pruning
+        b.prune = !wave_any(bad) && M * inv < 0x1p126f;
+        b.bx = (c.zs_a0x + c.zs_a1x * M) * inv + 0x1p-126f;
+        b.by = (c.zs_a0y + c.zs_a1y * M) * inv + 0x1p-126f;
+        b.pre = __builtin_fmaxf(b.bx, b.by);
+        (void)zhi;
+        return b;
+    }
+    __device__ static __forceinline__ uint64_t pair_mask(const PairBounds& b, float2 p, float2 q) {
+        return lanes(__builtin_fabsf(q.x - p.x) <= b.bx) & lanes(__builtin_fabsf(q.y - p.y) <= b.by);
+    }
+    __device__ static __forceinline__ float score(float2 p, float2 q) {
+        return __builtin_fmaxf(__builtin_fabsf(q.x - p.x), __builtin_fabsf(q.y - p.y));
+    }
+    __device__ static __forceinline__ uint64_t triplet_mask(const Consts& c, const SlopeHits& h, int hi, int hj,
+                                                          int hk, bool valid) {
+        const float xi = h.x[hi], yi = h.y[hi], zi = h.z[hi];
+        const float xj = h.x[hj], yj = h.y[hj], zj = h.z[hj];
+        const float n = __builtin_nanf("");
+        const float xk = valid ? h.x[hk] : n, yk = valid ? h.y[hk] : n, zk = valid ? h.z[hk] : n;
+        const MsdZTest::Pair pr = MsdZTest::pair(c, xi, yi, zi, xj, yj, zj);
+        const float w = 1.0f / (pr.szz01 + zk * zk);
+        const float qx = MsdZTest::plane_q(xi, xj, pr.sx01, xk, xk * zk, zi, zj, zk, w);
+        const float qy = MsdZTest::plane_q(yi, yj, pr.sy01, yk, yk * zk, zi, zj, zk, w);
+        return lanes(qx <= c.qmax_x) & lanes(qy <= c.qmax_y);
+    }
+    template <class H>
+    __device__ static uint32_t complete(const Consts& c, const H& hits, int hi, int hj, int o2, int n2) {
+        uint32_t cnt = 0;
+        for (int k0 = 0; k0 < n2; k0 += kWave) {
+            const int k = k0 + (int)lane_id();
+            cnt += (uint32_t)__builtin_popcountll(triplet_mask(c, hits, hi, hj, o2 + min(k, n2 - 1), k < n2));
+        }
+        return cnt;
+    }
+    template <class H>
+    __device__ static uint64_t complete_mask(const Consts& c, const H& hits, int hi, int hj, int o2, int n2, int k0) {
+        const int k = k0 + (int)lane_id();
+        return triplet_mask(c, hits, hi, hj, o2 + min(k, n2 - 1), k < n2);
+    }
+};
+
+// Per-hit z, window test: the slopes are the test's own quantities, so the
+// layer-1 window is exact, as in WindowPrune.
+struct WindowZPrune {
+    static constexpr bool kMag = false;
+    static constexpr bool kEventBounds = false;
+    static constexpr bool kZ = true;  // reads hits through SlopeHits
+    __device__ static __forceinline__ PairBounds bounds(const Consts& c, float) {
+        return PairBounds{c.win_x, c.win_y, c.pre_win};
+    }
+    __device__ static __forceinline__ float2 layer0(const Consts&, float2 s) { return s; }
+    __device__ static __forceinline__ float2 layer1(const Consts&, float2 s) { return s; }
+    __device__ static __forceinline__ float2 layer(const Consts&, float2 s, int) { return s; }
+    __device__ static __forceinline__ uint64_t pair_mask(const PairBounds& b, float2 p, float2 q) {
+        return WindowPrune::pair_mask(b, p, q);
+    }
+    __device__ static __forceinline__ float score(float2 p, float2 q) { return WindowPrune::score(p, q); }
+    template <class H>
+    __device__ static uint64_t complete_mask(const Consts& c, const H& hits, int hi, int /*hj*/, int o2, int n2,
+                                             int k0) {
+        const float2 si = hits.at(hi);
+        const int k = k0 + (int)lane_id();
+        const float2 sk = k < n2 ? hits.at(o2 + k) : nan2();
+        return lanes(__builtin_fabsf(sk.x - si.x) < c.win_x) & lanes(__builtin_fabsf(sk.y - si.y) < c.win_y);
+    }
+    template <class H>
+    __device__ static uint32_t complete(const Consts& c, const H& hits, int hi, int hj, int o2, int n2) {
+        uint32_t cnt = 0;
+        for (int k0 = 0; k0 < n2; k0 += kWave)
+            cnt += (uint32_t)__builtin_popcountll(complete_mask(c, hits, hi, hj, o2, n2, k0));
+        return cnt;
+    }
+};
+
+// Bounds of one event read from HBM: the policy's own event bounds, or its
+// block bounds with M = the largest layer-1 |x|, |y| where they depend on it.
+template <class P, class H>
+__device__ __forceinline__ PairBounds event_bounds(const Consts& c, const H& hits, int o0, int n0, int o1, int n1) {
+    if constexpr (P::kEventBounds) {
+        return P::event_bounds(c, hits, o0, n0, o1, n1);
+    } else {
+        float M = 0.0f;
+        if constexpr (P::kMag) M = layer_mag(hits, o1, n1);
+        return P::bounds(c, M);
+    }
+}
 
 // Two-particle acceptance: whether an event's passing triplets include two
 // with no hit in common (the trigger signature of Sec. 3.1, two particles
@@ -361,9 +494,7 @@ __device__ __forceinline__ DisjointState disjoint_add(DisjointState s, int i, in
 // layer 2 by lanes, each passing triplet fed to the state above.  Whole wave.
 template <class P, class H>
 __device__ bool wave_two_particles(const Consts& c, const H& hits, int o0, int n0, int o1, int n1, int o2, int n2) {
-    float M = 0.0f;
-    if constexpr (P::kMag) M = layer_mag(hits, o1, n1);
-    const PairBounds pb = P::bounds(c, M);
+    const PairBounds pb = event_bounds<P>(c, hits, o0, n0, o1, n1);
     DisjointState st = disjoint_start();
     // n0 n1 <= INT32_MAX, so pair indices (and p0 + 63) fit 32-bit unsigned
     const uint32_t np = (uint32_t)n0 * (uint32_t)n1, un1 = (uint32_t)n1;
@@ -375,7 +506,7 @@ __device__ bool wave_two_particles(const Consts& c, const H& hits, int o0, int n
         const int i = v ? (int)q : 0, j = v ? (int)(p - q * un1) : 0;
         const float2 u = v ? P::layer0(c, hits.at(o0 + i)) : nan2();
         const float2 w = v ? P::layer1(c, hits.at(o1 + j)) : nan2();
-        uint64_t m = P::pair_mask(pb, u, w);
+        uint64_t m = pb.prune ? P::pair_mask(pb, u, w) : lanes(v);
         while (m) {
             const int L = __builtin_ctzll(m);
             m &= m - 1;
@@ -602,10 +733,8 @@ __device__ void wave_event(const Consts& c, const H& hits, int h_base, int o0, i
     if (n2 > 0 && (n01 > (int64_t)INT32_MAX || n01 * n2 > (int64_t)INT32_MAX)) {
         cnt = -2;
     } else if (n0 > 0 && n1 > 0 && n2 > 0) {
-        float M = 0.0f;
-        if constexpr (P::kMag) M = layer_mag(hits, o1 - h_base, n1);
-        cnt = (int32_t)wave_event_pruned<P>(c, P::bounds(c, M), hits, o0 - h_base, n0, o1 - h_base, n1, o2 - h_base,
-                                            n2, px, py);
+        cnt = (int32_t)wave_event_pruned<P>(c, event_bounds<P>(c, hits, o0 - h_base, n0, o1 - h_base, n1), hits,
+                                            o0 - h_base, n0, o1 - h_base, n1, o2 - h_base, n2, px, py);
     }
     if (lane_id() == 0) {
         counts[e] = capped(cnt, c);
@@ -623,22 +752,26 @@ __device__ void wave_event(const Consts& c, const H& hits, int h_base, int o0, i
 // The one float4 group that would cross n_hits is copied element by element
 // by thread 0.  Needs x and y 16-byte aligned (checked by the host; `vec`
 // false otherwise: plain 4-byte loads).
-// Largest |x|, |y| of a staged group (NaN ignored, infinities kept).
-__device__ __forceinline__ float mag4(float m, float a, float b, float c, float d) {
-    return __builtin_fmaxf(__builtin_fmaxf(m, __builtin_fmaxf(__builtin_fabsf(a), __builtin_fabsf(b))),
-                           __builtin_fmaxf(__builtin_fabsf(c), __builtin_fabsf(d)));
+// Largest |x|, |y| of staged values as binary32 bit patterns without the
+// sign: for non-negative floats the integer order is the float order, so an
+// integer max (no NaN canonicalisation) finds it; a NaN pattern lies above
+// +inf and is clamped to +inf (an infinite bound: no pruning), see mag_of.
+__device__ __forceinline__ uint32_t abs_bits(float v) { return __builtin_bit_cast(uint32_t, v) & 0x7fffffffu; }
+__device__ __forceinline__ uint32_t mag4(uint32_t m, float a, float b, float c, float d) {
+    return max(max(m, max(abs_bits(a), abs_bits(b))), max(abs_bits(c), abs_bits(d)));
 }
+__device__ __forceinline__ float mag_of(uint32_t m) { return __builtin_bit_cast(float, min(m, 0x7f800000u)); }
 
 // Returns the largest |x|, |y| among the hits this thread staged (and a few
 // neighbours of the range: only an upper bound is needed).
 template <int HB, int NT>
-__device__ __forceinline__ float stage_hits(const float* __restrict__ x, const float* __restrict__ y,
-                                            int base, int nh, int n_hits, bool vec, float* xs, float* ys) {
+__device__ __forceinline__ uint32_t stage_hits(const float* __restrict__ x, const float* __restrict__ y,
+                                               int base, int nh, int n_hits, bool vec, float* xs, float* ys) {
     constexpr int Q = (HB + 6) / 4 / NT + 1;  // float4 groups per thread, upper bound
     const int a0 = base & ~3;
     const int nq = (base + nh - a0 + 3) >> 2;             // float4 groups to copy
     const int t = (int)threadIdx.x;
-    float mag = 0.0f;
+    uint32_t mag = 0u;
     if (vec) {
         const int nq_full = min(nq, (n_hits - a0) >> 2);   // groups entirely below n_hits
         if (nq_full > 0) {
@@ -705,10 +838,10 @@ struct BlockLds {
 };
 
 // Each wave's largest staged |x|, |y| into L.wmag (whole waves; read after
-// the next barrier by block_mag).
+// the next barrier by block_mag).  m: mag4 bits.
 template <int HB, int NW>
-__device__ __forceinline__ void publish_mag(BlockLds<HB, NW>& L, float m) {
-    const float wm = wave_max_f(m);
+__device__ __forceinline__ void publish_mag(BlockLds<HB, NW>& L, uint32_t m) {
+    const float wm = wave_max_f(mag_of(m));
     if (lane_id() == 0) L.wmag[threadIdx.x / kWave] = wm;
 }
 template <int HB, int NW>
@@ -887,7 +1020,7 @@ __device__ void block_general(BlockLds<HB, NW>& L, const Consts& c, const float*
         }
         const int end = cur + nfit;
         const int nh = L.soff[3 * end] - base;
-        const float mag = stage_hits<HB, NT>(x, y, base, nh, c.n_hits, vec, L.stage_x, L.stage_y);
+        const uint32_t mag = stage_hits<HB, NT>(x, y, base, nh, c.n_hits, vec, L.stage_x, L.stage_y);
         if constexpr (P::kMag) publish_mag(L, mag);
         block_descriptors(L, cur, nfit, base & ~3);
         block_count<P>(L, c, e0 + cur, nfit, counts, accept, status);
@@ -915,8 +1048,8 @@ struct HitGroups {
         vy = *reinterpret_cast<const f32x4*>(y + a0 + 4 * q);
         rest.load(x, y, a0, nq_full);
     }
-    // Returns the largest |x|, |y| of the groups (and m).
-    __device__ __forceinline__ float store(int nq_full, float* xs, float* ys, float m) const {
+    // Returns the largest |x|, |y| of the groups (and m), as mag4 bits.
+    __device__ __forceinline__ uint32_t store(int nq_full, float* xs, float* ys, uint32_t m) const {
         const int q = (int)threadIdx.x + (K - 1) * NT;
         if (q < nq_full) {
             reinterpret_cast<f32x4*>(xs)[q] = vx;
@@ -929,7 +1062,7 @@ struct HitGroups {
 template <int NT>
 struct HitGroups<0, NT> {
     __device__ __forceinline__ void load(const float*, const float*, int, int) {}
-    __device__ __forceinline__ float store(int, float*, float*, float m) const { return m; }
+    __device__ __forceinline__ uint32_t store(int, float*, float*, uint32_t m) const { return m; }
 };
 
 template <int HB, int NT>
@@ -951,10 +1084,10 @@ struct HitPrefetch {
     }
     // Stores the block's hits; returns the largest |x|, |y| this thread
     // stored (the groups of a block with nq_full <= 0 are not loaded: 0).
-    __device__ __forceinline__ float store(const float* __restrict__ x, const float* __restrict__ y, int base,
-                                           int nh, float* xs, float* ys) const {
+    __device__ __forceinline__ uint32_t store(const float* __restrict__ x, const float* __restrict__ y, int base,
+                                              int nh, float* xs, float* ys) const {
         const int a0 = base & ~3;
-        float m = nq_full > 0 ? g.store(nq_full, xs, ys, 0.0f) : 0.0f;
+        uint32_t m = nq_full > 0 ? g.store(nq_full, xs, ys, 0u) : 0u;
         if (threadIdx.x == 0)
             for (int h = a0 + 4 * max(nq_full, 0); h < base + nh; ++h) {
                 xs[h - a0] = x[h];
@@ -994,7 +1127,7 @@ __global__ __launch_bounds__(NW * kWave) void k_block(const int32_t* __restrict_
     if (whole) pf.issue(x, y, base, end - base, c.n_hits);
     block_check_describe(L, c, e0, ne, base & ~3, counts, accept, status);
     if (whole) {
-        const float mag = pf.store(x, y, base, end - base, L.stage_x, L.stage_y);
+        const uint32_t mag = pf.store(x, y, base, end - base, L.stage_x, L.stage_y);
         if constexpr (P::kMag) publish_mag(L, mag);
     }
     __syncthreads();
@@ -1073,7 +1206,7 @@ __global__ __launch_bounds__(NW * kWave) void k_block_pipe(const int32_t* __rest
         if (regular) {
             const int base = L.soff[0];
             const int nh = L.soff[3 * ne] - base;
-            const float mag = pf.store(x, y, base, nh, L.stage_x, L.stage_y);
+            const uint32_t mag = pf.store(x, y, base, nh, L.stage_x, L.stage_y);
             if constexpr (P::kMag) publish_mag(L, mag);
             block_descriptors(L, 0, ne, base & ~3);
         } else {

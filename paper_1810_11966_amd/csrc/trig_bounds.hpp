@@ -180,4 +180,31 @@ inline FitBounds fit_bounds(float z0f, float z1f, float z2f, float qmax) {
     return f;
 }
 
+// Per-hit z (each hit at its own z_h > 0): the pruned form compares the
+// hits' slopes s_h = f32(c_h / z_h).  For the computed slope m of the fit,
+// c_i/z_i - c_j/z_j = rho_i/z_i - rho_j/z_j exactly (rho_l = c_l - m z_l, as
+// above, whatever m's rounding), so a triplet that passes a plane has
+//   |c_j/z_j - c_i/z_i| <= sqrt(2) |(rho_i, rho_j)| / zmin,
+//   |(rho_i, rho_j)| <= (Rr/(1-u) + u sqrt(2) M + 2^-149.5) / (1-u),
+// with zmin <= z_i, z_j and M >= |c_i|, |c_j|; the two divisions and the
+// difference add (1+u) and 2u M / zmin:
+//   |f32(s_j - s_i)| <= (a0 + a1 M) / zmin + (1+u) 2^-149.
+// The device evaluates D = f32(f32(f32(a0 + f32(a1 M)) * f32(1 / zmin)) + 2^-126)
+// (four roundings more, covered by the inflation below), for each plane.
+struct SlopeBounds {
+    float a0, a1;
+};
+
+inline SlopeBounds slope_bounds(float qmax) {
+    typedef long double LD;
+    const LD u = std::ldexp((LD)1, -24);
+    const LD slack = std::ldexp((LD)1, -50);
+    const LD Rr = std::sqrt((LD)qmax / ((1 - u) * (1 - u) * (1 - u)) + 3 * std::ldexp((LD)1, -150)) * (1 + slack);
+    const LD r2 = std::sqrt((LD)2) * (1 + slack);
+    const LD A0 = (1 + u) * r2 * (Rr / (1 - u) + std::ldexp((LD)1, -149)) / (1 - u);
+    const LD A1 = (1 + u) * (r2 * r2 * u / (1 - u) + 2 * u);
+    const LD up = 1 / ((1 - u) * (1 - u) * (1 - u) * (1 - u) * (1 - u));
+    return SlopeBounds{round_up_f32(A0 * up * (1 + slack)), round_up_f32(A1 * up * (1 + slack))};
+}
+
 }  // namespace trig_host

@@ -31,6 +31,10 @@ struct Consts {
     // TRIG_TEST_MSD_BASIS pair bound: largest binary32 b >= 0 with
     // f32(b * b) <= qmax, per plane
     float beta_x, beta_y;
+    // Per-hit z, pruned form: a triplet that passes a plane has
+    // |f32(s_j - s_i)| <= (a0 + a1 M) / zmin for the hits' slopes s = c / z
+    // (M >= |c_i|, |c_j|, zmin <= z_i, z_j), per plane
+    float zs_a0x, zs_a1x, zs_a0y, zs_a1y;
     // TRIG_TEST_MSD: a triplet that passes a plane has |a| <= a0 + a1 M and
     // |b| <= b0 + b1 M (device evaluation order, M >= |c1| the plane's
     // layer-1 coordinate), per plane for a, x-z plane for b
@@ -172,6 +176,7 @@ __device__ __forceinline__ uint64_t lanes(bool cmp) { return __builtin_amdgcn_ba
 // TRIG_TEST_MSD_BASIS: Q = a^2 + b^2 in the basis (u, v).
 struct MsdBasisTest {
     static constexpr int HF = 2;
+    static constexpr bool kZ = false;  // layer positions from the parameters
     struct Pair {
         float ax2, bx0, ay2, by0;
     };
@@ -211,6 +216,7 @@ struct MsdBasisTest {
 // their sum of squares), the paper's definition of the test.
 struct MsdFitTest {
     static constexpr int HF = 4;
+    static constexpr bool kZ = false;  // layer positions from the parameters
     struct Pair {
         float xi, xj, sx01, yi, yj, sy01;
     };
@@ -253,6 +259,7 @@ struct MsdFitTest {
 
 struct WindowTest {
     static constexpr int HF = 2;
+    static constexpr bool kZ = false;  // layer positions from the parameters
     struct Pair {
         float sxi, syi;  // NaN when the layer-1 window already fails
     };
@@ -268,6 +275,89 @@ struct WindowTest {
                                                 float yj) {
         const float sxi = xi / c.z0, syi = yi / c.z0;
         const float sxj = xj / c.z1, syj = yj / c.z1;
+        const bool ok = (__builtin_fabsf(sxj - sxi) < c.win_x) & (__builtin_fabsf(syj - syi) < c.win_y);
+        const float n = __builtin_nanf("");
+        return Pair{ok ? sxi : n, ok ? syi : n};
+    }
+    __device__ static __forceinline__ Pair invalid() {
+        const float n = __builtin_nanf("");
+        return Pair{n, n};
+    }
+    __device__ static __forceinline__ uint64_t pass(const Consts& c, const Pair& p, const float* h) {
+        return lanes(__builtin_fabsf(h[0] - p.sxi) < c.win_x) & lanes(__builtin_fabsf(h[1] - p.syi) < c.win_y);
+    }
+};
+
+// Per-hit z (trig_hits.z): the fit written out with each hit's own z, its
+// Szz and reciprocal per triplet (one binary32 division shared by both
+// planes):  Szz = (zi*zi + zj*zj) + zk*zk,  w = 1 / Szz,
+// m = ((ci*zi + cj*zj) + ck*zk) * w,  r_l = c_l - m*z_l.
+struct MsdZTest {
+    static constexpr int HF = 6;
+    static constexpr bool kZ = true;
+    struct Pair {
+        float xi, xj, sx01, yi, yj, sy01, zi, zj, szz01;
+    };
+    __device__ static __forceinline__ void stage(const Consts&, float x, float y, float z, float* h) {
+        h[0] = x;
+        h[1] = y;
+        h[2] = z;
+        h[3] = x * z;
+        h[4] = y * z;
+        h[5] = z * z;
+    }
+    __device__ static __forceinline__ void pad(float* h) {
+        const float n = __builtin_nanf("");
+        h[0] = n; h[1] = n; h[2] = n; h[3] = n; h[4] = n; h[5] = n;
+    }
+    __device__ static __forceinline__ Pair pair(const Consts&, float xi, float yi, float zi, float xj, float yj,
+                                                float zj) {
+        Pair p;
+        p.xi = xi; p.xj = xj; p.yi = yi; p.yj = yj; p.zi = zi; p.zj = zj;
+        p.sx01 = xi * zi + xj * zj;
+        p.sy01 = yi * zi + yj * zj;
+        p.szz01 = zi * zi + zj * zj;
+        return p;
+    }
+    __device__ static __forceinline__ Pair invalid() {
+        const float n = __builtin_nanf("");
+        return Pair{n, n, n, n, n, n, n, n, n};
+    }
+    __device__ static __forceinline__ float plane_q(float ci, float cj, float s01, float ck, float pk, float zi,
+                                                    float zj, float zk, float w) {
+        const float m = (s01 + pk) * w;
+        const float r0 = ci - m * zi;
+        const float r1 = cj - m * zj;
+        const float r2 = ck - m * zk;
+        return (r0 * r0 + r1 * r1) + r2 * r2;
+    }
+    __device__ static __forceinline__ uint64_t pass(const Consts& c, const Pair& p, const float* h) {
+        const float w = 1.0f / (p.szz01 + h[5]);
+        const float qx = plane_q(p.xi, p.xj, p.sx01, h[0], h[3], p.zi, p.zj, h[2], w);
+        const float qy = plane_q(p.yi, p.yj, p.sy01, h[1], h[4], p.zi, p.zj, h[2], w);
+        return lanes(qx <= c.qmax_x) & lanes(qy <= c.qmax_y);
+    }
+};
+
+// Per-hit z, window test: slopes c / z with each hit's own z.
+struct WindowZTest {
+    static constexpr int HF = 2;
+    static constexpr bool kZ = true;
+    struct Pair {
+        float sxi, syi;  // NaN when the layer-1 window already fails
+    };
+    __device__ static __forceinline__ void stage(const Consts&, float x, float y, float z, float* h) {
+        h[0] = x / z;
+        h[1] = y / z;
+    }
+    __device__ static __forceinline__ void pad(float* h) {
+        h[0] = __builtin_nanf("");
+        h[1] = __builtin_nanf("");
+    }
+    __device__ static __forceinline__ Pair pair(const Consts& c, float xi, float yi, float zi, float xj, float yj,
+                                                float zj) {
+        const float sxi = xi / zi, syi = yi / zi;
+        const float sxj = xj / zj, syj = yj / zj;
         const bool ok = (__builtin_fabsf(sxj - sxi) < c.win_x) & (__builtin_fabsf(syj - syi) < c.win_y);
         const float n = __builtin_nanf("");
         return Pair{ok ? sxi : n, ok ? syi : n};
@@ -316,8 +406,8 @@ __device__ __forceinline__ uint32_t pair_tiles(const EventRange& ev) {
 // uniform arguments; returns the same count on every lane.
 template <class T, int KCH>
 __device__ uint32_t wave_count(const float* __restrict__ x, const float* __restrict__ y,
-                               const EventRange& ev, uint32_t t_begin, uint32_t t_end,
-                               const Consts& c, float* __restrict__ lds) {
+                               const float* __restrict__ z, const EventRange& ev, uint32_t t_begin,
+                               uint32_t t_end, const Consts& c, float* __restrict__ lds) {
     const uint32_t stop = (uint32_t)c.count_cap;  // enough: the result is capped there
     static_assert(KCH % 4 == 0, "chunk must hold whole float4 groups");
     const unsigned lane = lane_id();
@@ -329,17 +419,27 @@ __device__ uint32_t wave_count(const float* __restrict__ x, const float* __restr
         const int nk_pad = (nk + 3) & ~3;
         for (int t = (int)lane; t < nk_pad; t += kWave) {
             float* h = lds + t * T::HF;
-            if (t < nk)
-                T::stage(c, x[ev.o2 + k0 + t], y[ev.o2 + k0 + t], h);
-            else
+            if (t < nk) {
+                if constexpr (T::kZ)
+                    T::stage(c, x[ev.o2 + k0 + t], y[ev.o2 + k0 + t], z[ev.o2 + k0 + t], h);
+                else
+                    T::stage(c, x[ev.o2 + k0 + t], y[ev.o2 + k0 + t], h);
+            } else {
                 T::pad(h);
+            }
         }
         wave_lds_sync();
         const uint32_t p0 = t_begin * (uint32_t)kWave + lane;
         uint32_t i = p0 / n1, j = p0 - (p0 / n1) * n1;
         for (uint32_t t = t_begin; t < t_end; ++t) {
             typename T::Pair pr = T::invalid();
-            if (i < n0) pr = T::pair(c, x[ev.o0 + i], y[ev.o0 + i], x[ev.o1 + j], y[ev.o1 + j]);
+            if (i < n0) {
+                if constexpr (T::kZ)
+                    pr = T::pair(c, x[ev.o0 + i], y[ev.o0 + i], z[ev.o0 + i], x[ev.o1 + j], y[ev.o1 + j],
+                                 z[ev.o1 + j]);
+                else
+                    pr = T::pair(c, x[ev.o0 + i], y[ev.o0 + i], x[ev.o1 + j], y[ev.o1 + j]);
+            }
             // nk_pad is a multiple of 4: four layer-2 hits per iteration
             for (int k = 0; k < nk_pad; k += 4) {
                 const float* h = lds + k * T::HF;

@@ -61,7 +61,8 @@ class TrigEventsCsr(ctypes.Structure):
 
 
 class TrigHits(ctypes.Structure):
-    _fields_ = [("n_hits", ctypes.c_int32), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p)]
+    _fields_ = [("n_hits", ctypes.c_int32), ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
+                ("z", ctypes.c_void_p)]
 
 
 class TrigParams(ctypes.Structure):
@@ -233,13 +234,17 @@ def _check_tensor(t, dtype, name):
         raise ValueError(f"{name} must be a contiguous {dtype} tensor on a GPU")
 
 
-def _prepare(offsets, x, y, test, form, compact, want_status, stream, workspace, out, param_kw):
+def _prepare(offsets, x, y, test, form, compact, want_status, stream, workspace, out, param_kw, hit_z=None):
     import torch
     _check_tensor(offsets, torch.int32, "offsets")
     _check_tensor(x, torch.float32, "x")
     _check_tensor(y, torch.float32, "y")
     if x.numel() != y.numel():
         raise ValueError("x and y differ in length")
+    if hit_z is not None:
+        _check_tensor(hit_z, torch.float32, "hit_z")
+        if hit_z.numel() != x.numel():
+            raise ValueError("hit_z and x differ in length")
     n_ev = (offsets.numel() - 1) // 3
     if offsets.numel() != 3 * n_ev + 1:
         raise ValueError("offsets must hold 3*n_events+1 entries")
@@ -271,18 +276,20 @@ def _prepare(offsets, x, y, test, form, compact, want_status, stream, workspace,
         p.workspace_bytes = workspace.numel() - (aligned - addr)
     s = torch.cuda.current_stream(dev).cuda_stream if stream is None else int(stream)
     ev = TrigEventsCsr(n_ev, offsets.data_ptr())
-    hits = TrigHits(x.numel(), x.data_ptr(), y.data_ptr())
+    hits = TrigHits(x.numel(), x.data_ptr(), y.data_ptr(), hit_z.data_ptr() if hit_z is not None else None)
     res.workspace = workspace  # kept until the result is dropped (the call is asynchronous)
     return p, res, ev, hits, s
 
 
-def select(offsets, x, y, *, test: str = "msd", form: str = "plain", compact: bool = False,
+def select(offsets, x, y, *, hit_z=None, test: str = "msd", form: str = "plain", compact: bool = False,
            want_status: bool = False, stream=None, workspace=None, out=None, **param_kw) -> SelectResult:
     """Run trig_select on torch device tensors (int32 offsets [3E+1], float32
-    x, y [H]).  ``form`` is a key of FORMS; extra keywords go to make_params.
-    ``out`` may hold preallocated (counts, accept) tensors."""
+    x, y [H], optional float32 per-hit z positions ``hit_z`` [H]).  ``form``
+    is a key of FORMS;
+    extra keywords go to make_params (``extra_flags`` is OR-ed into the
+    flags).  ``out`` may hold preallocated (counts, accept) tensors."""
     p, res, ev, hits, s = _prepare(offsets, x, y, test, form, compact, want_status, stream, workspace,
-                                   out, param_kw)
+                                   out, param_kw, hit_z=hit_z)
     rc = trig_select(ev, hits, p, res.counts.data_ptr(), res.accept.data_ptr(), s)
     if rc:
         raise TrigError(rc, trig_last_error_detail())

@@ -223,3 +223,51 @@ def two_particle_events(n_events, seed, z=(400.0, 410.0, 420.0), noise=6):
             rng.shuffle(layers[l])
         events.append(layers)
     return synth.from_layers(events)
+
+
+def near_threshold_events_z(n_events, per_layer, seed, rel=1e-4, dz=0.75, z=(400.0, 410.0, 420.0), slope_max=0.45):
+    """Events on staggered modules whose tracks sit near the MSD cut: each
+    track's three hits at z_l -/+ dz (chosen per hit), displaced orthogonally
+    to its own (zi, zj, zk) so that its residual sum of squares lies within a
+    relative ``rel`` of ndf*T in both planes.  Returns a set with per-hit z."""
+    rng = np.random.default_rng(seed + 91)
+    xs, ys, zs, off = [], [], [], [0]
+    for e in range(n_events):
+        cx, cy, cz = [], [], []
+        for t in range(per_layer):
+            zt = tuple(zl + dz * rng.choice([-1.0, 1.0]) for zl in z)
+            xi, xj, xk = near_threshold_triplets(1, seed * 100000 + 2 * (e * per_layer + t), 0.03, 2, rel, zt,
+                                                 slope_max)
+            yi, yj, yk = near_threshold_triplets(1, seed * 100000 + 2 * (e * per_layer + t) + 1, 0.025, 2, rel, zt,
+                                                 slope_max)
+            cx.append((xi[0], xj[0], xk[0]))
+            cy.append((yi[0], yj[0], yk[0]))
+            cz.append(zt)
+        cx, cy, cz = np.asarray(cx, np.float32), np.asarray(cy, np.float32), np.asarray(cz, np.float32)
+        for l in range(3):
+            perm = rng.permutation(per_layer)
+            xs.append(cx[perm, l]); ys.append(cy[perm, l]); zs.append(cz[perm, l])
+            off.append(off[-1] + per_layer)
+    return synth.EventSet(np.asarray(off, np.int32), np.concatenate(xs), np.concatenate(ys),
+                          np.zeros(n_events, np.int8), z=np.concatenate(zs))
+
+
+def odd_z_events(seed):
+    """Per-hit z that no slope bound covers, among exact tracks: z = 0,
+    negative, NaN and infinite z in each layer, and huge coordinates over tiny
+    z (slopes near overflow)."""
+    rng = np.random.default_rng(seed)
+    base = two_particle_events(40, seed=seed + 1, noise=4)
+    s = synth.staggered(base)
+    z = s.z.copy()
+    x, y = s.x.copy(), s.y.copy()
+    for e in range(0, base.n_events, 4):
+        l = e % 3
+        lo, hi = s.offsets[3 * e + l], s.offsets[3 * e + l + 1]
+        if hi > lo:
+            z[lo] = (0.0, -405.0, np.nan, np.inf)[(e // 4) % 4]
+    for e in range(2, base.n_events, 8):
+        lo, hi = s.offsets[3 * e], s.offsets[3 * e + 3]
+        z[lo:hi] = np.float32(1e-3)
+        x[lo:hi] = (rng.uniform(-1, 1, hi - lo) * 3e37).astype(np.float32)
+    return synth.EventSet(s.offsets, x, y, s.n_tracks, z=z)

@@ -41,6 +41,8 @@ def to_dev(torch, s):
 def run_gpu(torch, s, test="msd", form="plain", compact=True, **kw):
     from paper_1810_11966_amd import trig
     off, x, y = to_dev(torch, s)
+    if getattr(s, "z", None) is not None:
+        kw["hit_z"] = torch.from_numpy(np.ascontiguousarray(s.z)).to(off.device)
     r = trig.select(off, x, y, test=test, form=form, compact=compact, want_status=True, **kw)
     torch.cuda.synchronize()
     out = {"counts": r.counts.cpu().numpy(), "accept": r.accept.cpu().numpy(),
@@ -561,3 +563,62 @@ def test_decision_only(gpu):
                           extra_flags=trig.TRIG_DECISION_ONLY | trig.TRIG_ACCEPT_TWO_PARTICLES)
             assert np.array_equal(got["counts"], np.where(c < 0, c, np.minimum(c, 2))), (test, form)
             assert np.array_equal(got["accept"], d), (test, form)
+
+
+# ------------------------------------------------------------- per-hit z ---
+
+def test_per_hit_z_all_forms(gpu):
+    """Hits on staggered modules, each with its own z (trig_hits.z): every
+    form against the oracle's per-triplet fit (Szz and its reciprocal per
+    triplet) and slope window, on the 10k workload, near-threshold tracks on
+    all stagger combinations, events with many passing triplets, and events
+    whose z no slope bound covers (0, negative, NaN, infinite, tiny z under
+    huge coordinates: the every-triplet path)."""
+    sets = {"small_10k": synth.staggered(synth.make_event_set(synth.SMALL_10K, n_events=4000)),
+            "near": helpers.near_threshold_events_z(300, 6, seed=3, rel=1e-4),
+            "near 1e-6": helpers.near_threshold_events_z(200, 6, seed=4, rel=1e-6),
+            "two particles": synth.staggered(helpers.two_particle_events(1500, seed=6)),
+            "odd z": helpers.odd_z_events(5)}
+    for name, s in sets.items():
+        for test in ("msd", "window"):
+            with np.errstate(all="ignore"):
+                c = oracle_result(s, oracle_cfg(test))[0]
+            assert c.sum() > 0, (name, test)
+            for form in FORMS:
+                print(f"[per-hit z] {name} test={test} form={form}", flush=True)
+                with np.errstate(all="ignore"):
+                    assert_parity(gpu, s, test, form, f"per-hit z {name}")
+
+
+def test_per_hit_z_at_layer_positions_and_refusals(gpu):
+    """Per-hit z equal to the layer positions gives the layer path's counts
+    (the reciprocal of Szz is the same binary32 number at this geometry);
+    the basis form with per-hit z is refused before any launch."""
+    from paper_1810_11966_amd import trig
+    s = synth.make_event_set(synth.SMALL_10K, n_events=3000)
+    n = np.diff(s.offsets.astype(np.int64))
+    zl = np.asarray(synth.Z_LAYERS, np.float32)[np.repeat(np.tile(np.arange(3), s.n_events), n)]
+    sz = synth.EventSet(s.offsets, s.x, s.y, s.n_tracks, z=zl)
+    for form in ("plain", "pruned", "binned"):
+        assert np.array_equal(run_gpu(gpu, sz, "msd", form)["counts"], run_gpu(gpu, s, "msd", form)["counts"])
+    with pytest.raises(trig.TrigError) as err:
+        run_gpu(gpu, sz, "msd_basis", "plain")
+    assert err.value.code == trig.TRIG_EUNSUPPORTED
+
+
+def test_per_hit_z_two_particles_and_decision_only(gpu):
+    from paper_1810_11966_amd import trig
+    s = synth.concat([synth.staggered(helpers.two_particle_events(1500, seed=9)), helpers.odd_z_events(7)])
+    for test in ("msd", "window"):
+        cfg = oracle_cfg(test)
+        with np.errstate(all="ignore"):
+            c = oracle_result(s, cfg)[0]
+            d = R.disjoint_accept(s.offsets, s.x, s.y, cfg, n_threads=THREADS, z=s.z)
+        assert d.sum() > 100 and ((c >= 2) & (d == 0)).sum() > 50
+        for form in ("plain", "persistent", "pruned", "auto"):
+            print(f"[per-hit z] two particles test={test} form={form}", flush=True)
+            got = run_gpu(gpu, s, test, form, extra_flags=trig.TRIG_ACCEPT_TWO_PARTICLES)
+            assert np.array_equal(got["counts"], c), (test, form)
+            assert np.array_equal(got["accept"], d), (test, form)
+            got = run_gpu(gpu, s, test, form, extra_flags=trig.TRIG_DECISION_ONLY, min_triplets=3)
+            assert np.array_equal(got["counts"], np.where(c < 0, c, np.minimum(c, 3))), (test, form)
