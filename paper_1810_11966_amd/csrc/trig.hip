@@ -409,6 +409,7 @@ __global__ __launch_bounds__(kBinWaves * kWave) __attribute__((amdgpu_waves_per_
 // events and decides its candidates one by one (wave_two_particles), writing
 // the final flag.  Events without a candidate cost one coalesced read.
 constexpr int kTwoWaves = 4;
+constexpr int kTwoPartCap = 512;  // layer-0 and layer-1 partials a wave keeps in LDS
 
 template <class P>
 __global__ __launch_bounds__(kTwoWaves * kWave) void k_two_particles(const int32_t* __restrict__ off, int n_events,
@@ -421,6 +422,7 @@ __global__ __launch_bounds__(kTwoWaves * kWave) void k_two_particles(const int32
     if (base >= n_events) return;
     const int64_t e = base + lane_id();
     uint64_t m = lanes(e < n_events && accept[e] != 0);
+    __shared__ float2 part_all[kTwoWaves][kTwoPartCap];
     using H = typename std::conditional<P::kZ, SlopeHits, GlobalHits>::type;
     H gh;
     if constexpr (P::kZ)
@@ -434,7 +436,7 @@ __global__ __launch_bounds__(kTwoWaves * kWave) void k_two_particles(const int32
         EventRange ev;
         bool two = false;
         if (load_event(off, ev_i, c.n_hits, ev) == 0 && ev.n0 > 0 && ev.n1 > 0 && ev.n2 > 0)
-            two = wave_two_particles<P>(c, gh, ev.o0, ev.n0, ev.o1, ev.n1, ev.o2, ev.n2);
+            two = wave_two_particles<P>(c, gh, ev.o0, ev.n0, ev.o1, ev.n1, ev.o2, ev.n2, part_all[w], kTwoPartCap);
         if (lane_id() == 0) accept[ev_i] = (uint8_t)two;
     }
 }

@@ -493,19 +493,31 @@ __device__ __forceinline__ DisjointState disjoint_add(DisjointState s, int i, in
 // (the exact pair test of the pruned form), surviving pairs completed over
 // layer 2 by lanes, each passing triplet fed to the state above.  Whole wave.
 template <class P, class H>
-__device__ bool wave_two_particles(const Consts& c, const H& hits, int o0, int n0, int o1, int n1, int o2, int n2) {
+__device__ bool wave_two_particles(const Consts& c, const H& hits, int o0, int n0, int o1, int n1, int o2, int n2,
+                                   float2* __restrict__ part, int part_cap) {
     const PairBounds pb = event_bounds<P>(c, hits, o0, n0, o1, n1);
     DisjointState st = disjoint_start();
     // n0 n1 <= INT32_MAX, so pair indices (and p0 + 63) fit 32-bit unsigned
     const uint32_t np = (uint32_t)n0 * (uint32_t)n1, un1 = (uint32_t)n1;
     const uint32_t lane = lane_id();
+    // The pair partials of layers 0 and 1 in LDS when they fit (one round
+    // trip to HBM instead of one per 64 pairs).
+    const bool staged = n0 + n1 <= part_cap;
+    if (staged) {
+        for (int t = (int)lane; t < n0 + n1; t += kWave)
+            part[t] = t < n0 ? P::layer0(c, hits.at(o0 + t)) : P::layer1(c, hits.at(o1 + (t - n0)));
+        wave_lds_sync();
+    }
     for (uint32_t p0 = 0; p0 < np; p0 += kWave) {
         const uint32_t p = p0 + lane;
         const bool v = p < np;
         const uint32_t q = p / un1;
         const int i = v ? (int)q : 0, j = v ? (int)(p - q * un1) : 0;
-        const float2 u = v ? P::layer0(c, hits.at(o0 + i)) : nan2();
-        const float2 w = v ? P::layer1(c, hits.at(o1 + j)) : nan2();
+        float2 u = nan2(), w = nan2();
+        if (v) {
+            u = staged ? part[i] : P::layer0(c, hits.at(o0 + i));
+            w = staged ? part[n0 + j] : P::layer1(c, hits.at(o1 + j));
+        }
         uint64_t m = pb.prune ? P::pair_mask(pb, u, w) : lanes(v);
         while (m) {
             const int L = __builtin_ctzll(m);
@@ -517,12 +529,16 @@ __device__ bool wave_two_particles(const Consts& c, const H& hits, int o0, int n
                     const int kk = k0 + __builtin_ctzll(km);
                     km &= km - 1;
                     st = disjoint_add(st, iL, jL, kk);
-                    if (st.found) return true;
+                    if (st.found) break;
                 }
+                if (st.found) break;
             }
+            if (st.found) break;
         }
+        if (st.found) break;
     }
-    return false;
+    if (staged) wave_lds_sync();  // the next event rewrites the partials
+    return st.found;
 }
 
 // Passing triplets of one event (all layers non-empty), by one wave.
