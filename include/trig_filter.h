@@ -57,8 +57,9 @@ typedef struct {
                                      the capacity are not written, and the offsets past it are not valid */
 
 /* Device workspace trig_filter_stations needs for n_events events (host-only
- * call; 0 for n_events < 0): per event 12 bytes of layer counts and 1 KiB of
- * trigger-hit lists (2048 entries per 8 events), plus 8 bytes per 32 events. */
+ * call; 0 for n_events < 0): per event 16 bytes of layer and record counts
+ * and 512 bytes of window records (128 records of 16 bytes per 4 events),
+ * plus 8 bytes per 16 events. */
 size_t trig_filter_workspace_bytes(int32_t n_events);
 
 /* Keep the hits of the trigger layers, event by event.
@@ -68,12 +69,13 @@ size_t trig_filter_workspace_bytes(int32_t n_events);
  * the index in out_x/out_y of the first hit of event e in trigger layer l,
  * out_layer_offsets[3*n_events] the total, and the hits of each (event,
  * layer) keep their input order.  Kernels: per-event counts of the three
- * layers and lists of the trigger hits' positions (one pass over the station
- * numbers), an exclusive scan of the workgroup totals, then a stable scatter
- * of the trigger hits through the lists (x and y read for trigger hits only).
- * The events of a group of 8 with more than 2048 trigger hits together, or
- * with an event of 2^30 hits or more, are scattered from a second pass over
- * their station numbers instead.
+ * layers and records of the 32-hit windows that hold trigger hits (their
+ * start and per-layer bit masks; one pass over the station numbers), an
+ * exclusive scan of the workgroup totals, then a stable scatter of the
+ * trigger hits through the records (x and y read for trigger hits only).
+ * The events of a group of 4 (events w, w + 4, w + 8, w + 12 of each 16)
+ * that need more than 128 records together are scattered from a second pass
+ * over their station numbers instead.
  * Errors (returned before anything is enqueued): TRIG_EINVAL for a NULL
  * required pointer, n_events < 0, n_hits < 0, equal layer numbers, a non-zero
  * reserved field, out_capacity < 0, or a workspace that is too small or not

@@ -8,14 +8,19 @@
 // wave w takes events w, w + 4, ...  A wave reads an event's station numbers
 // 32 per lane (two 16-byte loads of consecutive hits, 2048 hits per step),
 // so the hits of lane L precede those of lane L + 1 in a step.  The count
-// kernel sums each layer's hits and writes the positions of the trigger hits
-// (with their layer, in input order) to the wave's list in the workspace;
-// the scatter kernel ranks the list's entries per layer with ballots and
-// moves x and y.  A wave whose events hold more trigger hits than its list
-// (or an event of 2^30 hits or more) leaves the list incomplete, and the
-// scatter then reads those events' station numbers again: a hit's rank in its
-// layer is the exclusive prefix over lanes of the per-lane counts plus the
-// count of the lane's earlier hits.
+// kernel sums each layer's hits and writes one record per lane window (32
+// consecutive hits) that holds a trigger hit: the window's start and its
+// three layer masks, to the wave's list in the workspace.  The scatter kernel
+// finds every event's output positions with one lane per event, then each
+// wave takes its list 64 records at a time: a wave scan of the records'
+// layer counts gives each record's first output position per layer, and two
+// records per round, one per half-wave and one lane per hit of the window,
+// move x and y (a hit's rank within its record is the bits below it in the
+// record's mask).  A wave whose events need more records than its list
+// holds leaves the list incomplete, and the scatter then reads those
+// events' station numbers again: a hit's rank in its layer is the exclusive
+// prefix over lanes of the per-lane counts plus the count of the lane's
+// earlier hits.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,7 +34,7 @@ namespace {
 
 constexpr int kFilterThreads = 256;
 constexpr int kFilterWaves = kFilterThreads / trig::kWave;
-constexpr int kFilterEvents = 32;  // events per workgroup
+constexpr int kFilterEvents = 16;  // events per workgroup
 
 struct Range {
     int64_t a, b;
@@ -115,92 +120,116 @@ __device__ __forceinline__ LaneMatch match_lane(const LaneStations& s, int64_t h
     return r;
 }
 
-// Trigger-hit entries one wave keeps for the scatter (its events' trigger
-// hits, input order): (layer << 30) | (hit - event start).
-constexpr int kWaveList = 2048;
-constexpr int64_t kMaxListEvent = (int64_t)1 << 30;  // events this large are not listed
-
-// Offsets of a step's matched hits in the step's list (per wave, in LDS):
-// entry (layer << 11) | (offset of the hit in the step), layer 0's, 1's and
-// 2's hits merged in input order (per-lane counts, a wave scan, then each
-// lane's hits in bit order).  Returns the step's number of entries.
-__device__ __forceinline__ int32_t step_list(const LaneMatch& m, uint16_t* list) {
-    const int lane = (int)trig::lane_id();
-    const uint32_t all = m.m[0] | m.m[1] | m.m[2];
-    const int n = __builtin_popcount(all);
-    const int incl = trig::wave_inclusive_sum(n);
-    int32_t q = incl - n;
-    for (uint32_t bits = all; bits; bits &= bits - 1u) {
-        const int b = __builtin_ctz(bits);
-        const uint32_t l = (m.m[0] >> b) & 1u ? 0u : ((m.m[1] >> b) & 1u ? 1u : 2u);
-        list[q++] = (uint16_t)((l << 11) | (uint32_t)(kLaneHits * lane + b));
-    }
-    return __builtin_amdgcn_readlane(incl, 63);
-}
+// Records one wave keeps for the scatter: per lane window of kLaneHits
+// consecutive hits that holds a trigger hit of its event, the window's start
+// relative to the event's first hit and the layer masks (bit b: hit
+// start + b), in input order.
+constexpr int kWaveRecords = 128;
+typedef unsigned u32x4r __attribute__((ext_vector_type(4)));  // {start, m0, m1, m2}
 
 __global__ __launch_bounds__(kFilterThreads) void k_filter_count(const int64_t* __restrict__ off, int n_events,
                                                                    int64_t n_hits, const uint8_t* __restrict__ st,
                                                                    uint32_t layers, int vec,
                                                                    int32_t* __restrict__ counts,
                                                                    int64_t* __restrict__ partials,
-                                                                   uint32_t* __restrict__ wave_lists,
+                                                                   u32x4r* __restrict__ wave_recs,
+                                                                   int32_t* __restrict__ ev_recs,
                                                                    uint32_t* status) {
+    constexpr int kPer = kFilterEvents / kFilterWaves;  // events of a wave
     __shared__ int64_t wave_total[kFilterWaves];
-    __shared__ uint16_t lists[kFilterWaves][kStepHits];  // per wave: the step's matched hits
     const int w = trig::uniform_i((int)(threadIdx.x / trig::kWave));
     const int lane = (int)trig::lane_id();
     const int e_first = (int)blockIdx.x * kFilterEvents;
-    uint16_t* slist = lists[w];
-    uint32_t* wlist = wave_lists + ((int64_t)blockIdx.x * kFilterWaves + w) * kWaveList;
-    int32_t used = 0;   // entries of wlist written
-    bool keep = true;   // wlist holds every trigger hit of this wave's events so far (wave-uniform)
-    int64_t total = 0;
-    for (int j = w; j < kFilterEvents; j += kFilterWaves) {
-        const int e = e_first + j;
-        if (e >= n_events) break;
-        const Range r = event_range(off, e, n_hits);
-        uint32_t c[3] = {0u, 0u, 0u};
-        if (r.ok) {
-            if (r.b - r.a >= kMaxListEvent) keep = false;
-            // double-buffered: the next step's station numbers are in flight
-            // while this step's are matched
-            int64_t base = r.a & ~(int64_t)15;
-            LaneStations cur, nxt;
-            cur.load(st, base + (int64_t)kLaneHits * lane, n_hits, vec != 0);
-            for (; base < r.b; base += kStepHits) {
-                const int64_t h0 = base + (int64_t)kLaneHits * lane;
-                if (base + kStepHits < r.b) nxt.load(st, h0 + kStepHits, n_hits, vec != 0);  // wave-uniform
-                const LaneMatch m = match_lane(cur, h0, r.a, r.b, layers);
+    u32x4r* wrec = wave_recs + ((int64_t)blockIdx.x * kFilterWaves + w) * kWaveRecords;
+    // The wave's events (w, w + 4, ...): ranges; empty and malformed ones are
+    // written here, the others while their hits stream by.
+    int64_t ra[kPer], rb[kPer];
+    bool live[kPer];
 #pragma unroll
-                for (int l = 0; l < 3; ++l) c[l] += (uint32_t)__builtin_popcount(m.m[l]);
-                cur = nxt;
-                if (keep) {
-                    const int32_t nstep = step_list(m, slist);
-                    if (used + nstep > kWaveList) {
-                        keep = false;
-                    } else if (nstep > 0) {
-                        trig::wave_lds_sync();
-                        // matched hits lie in [r.a, r.b): base - r.a + offset >= 0
-                        const int32_t rel0 = (int32_t)(base - r.a);
-                        for (int32_t i = lane; i < nstep; i += trig::kWave) {
-                            const uint32_t en = slist[i];
-                            wlist[used + i] = ((en >> 11) << 30) | (uint32_t)(rel0 + (int32_t)(en & 2047u));
-                        }
-                        used += nstep;
-                    }
-                    trig::wave_lds_sync();  // the next step rewrites the list
-                }
+    for (int k = 0; k < kPer; ++k) {
+        const int e = e_first + w + kFilterWaves * k;
+        live[k] = false;
+        ra[k] = rb[k] = 0;
+        if (e < n_events) {
+            const Range r = event_range(off, e, n_hits);
+            ra[k] = r.a;
+            rb[k] = r.b;
+            live[k] = r.ok && r.a < r.b;
+            if (!live[k] && lane == 0) {
+                counts[3 * (int64_t)e] = 0;
+                counts[3 * (int64_t)e + 1] = 0;
+                counts[3 * (int64_t)e + 2] = 0;
+                ev_recs[e] = 0;
+                if (!r.ok && status) atomicOr(status, TRIG_FILTER_MALFORMED);
             }
-        } else if (lane == 0 && status) {
-            atomicOr(status, TRIG_FILTER_MALFORMED);
         }
-        const uint32_t s0 = trig::wave_sum_u(c[0]), s1 = trig::wave_sum_u(c[1]), s2 = trig::wave_sum_u(c[2]);
-        if (lane == 0) {
-            counts[3 * (int64_t)e] = (int32_t)s0;
-            counts[3 * (int64_t)e + 1] = (int32_t)s1;
-            counts[3 * (int64_t)e + 2] = (int32_t)s2;
+    }
+    // The first step of the wave's next live event after event k (kPer if none).
+    auto next_live = [&](int k) {
+        int n = kPer;
+#pragma unroll
+        for (int q = kPer - 1; q >= 0; --q)
+            if (q > k && live[q]) n = q;
+        return n;
+    };
+    int32_t used = 0;   // records of wrec written
+    bool keep = true;   // wrec holds every record of this wave's events so far (wave-uniform)
+    int64_t total = 0;
+    // One flat stream over the live events' steps: the next step's station
+    // numbers (of this event or the next) are in flight while this step's
+    // are matched.
+    int k = next_live(-1);
+    if (k < kPer) {
+        int64_t base = ra[k] & ~(int64_t)15;
+        LaneStations cur, nxt;
+        cur.load(st, base + (int64_t)kLaneHits * lane, n_hits, vec != 0);
+        uint32_t c[3] = {0u, 0u, 0u};
+        int32_t recs = 0;  // this event's records
+        for (;;) {
+            // wave-uniform choice of the next step
+            int k1 = k;
+            int64_t base1 = base + kStepHits;
+            if (base1 >= rb[k]) {
+                k1 = next_live(k);
+                base1 = k1 < kPer ? ra[k1] & ~(int64_t)15 : 0;
+            }
+            if (k1 < kPer) nxt.load(st, base1 + (int64_t)kLaneHits * lane, n_hits, vec != 0);
+            const int64_t h0 = base + (int64_t)kLaneHits * lane;
+            const LaneMatch m = match_lane(cur, h0, ra[k], rb[k], layers);
+#pragma unroll
+            for (int l = 0; l < 3; ++l) c[l] += (uint32_t)__builtin_popcount(m.m[l]);
+            cur = nxt;
+            // one record per lane window with a trigger hit, in lane order
+            const bool active = (m.m[0] | m.m[1] | m.m[2]) != 0u;
+            const uint64_t am = trig::lanes(active);
+            const int32_t nrec = (int32_t)__builtin_popcountll(am);
+            recs += nrec;
+            if (keep && used + nrec > kWaveRecords) keep = false;
+            if (keep && active) {
+                const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(am >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)am, 0u));
+                // h0 - ra[k] lies in [-15, rb[k] - ra[k]): an int32
+                wrec[used + rank] = u32x4r{(uint32_t)(int32_t)(h0 - ra[k]), m.m[0], m.m[1], m.m[2]};
+            }
+            if (keep) used += nrec;
+            if (k1 != k) {
+                // event k is complete
+                const int e = e_first + w + kFilterWaves * k;
+                const uint32_t s0 = trig::wave_sum_u(c[0]), s1 = trig::wave_sum_u(c[1]), s2 = trig::wave_sum_u(c[2]);
+                if (lane == 0) {
+                    counts[3 * (int64_t)e] = (int32_t)s0;
+                    counts[3 * (int64_t)e + 1] = (int32_t)s1;
+                    counts[3 * (int64_t)e + 2] = (int32_t)s2;
+                    ev_recs[e] = recs;
+                }
+                total += (int64_t)s0 + s1 + s2;
+                c[0] = c[1] = c[2] = 0u;
+                recs = 0;
+                if (k1 >= kPer) break;
+            }
+            k = k1;
+            base = base1;
         }
-        total += (int64_t)s0 + s1 + s2;
     }
     if (lane == 0) wave_total[w] = total;
     __syncthreads();
@@ -212,19 +241,29 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_count(const int64_t* 
 }
 
 // In-place exclusive scan of partials[0..n) (int64); partials[n] = total.
-// One workgroup: thread t sums its run of ceil(n / threads) consecutive
-// partials, one block scan of those sums (Hillis-Steele in LDS), then each
-// thread rewrites its run from its prefix.
-__global__ __launch_bounds__(kFilterThreads) void k_filter_scan(int64_t* partials, int n) {
-    __shared__ int64_t buf[kFilterThreads];
+// One workgroup of kScanThreads: thread t sums its run of ceil(n / threads)
+// consecutive partials (loads of a run issued together), one block scan of
+// those sums (Hillis-Steele in LDS), then each thread rewrites its run from
+// its prefix.
+constexpr int kScanThreads = 1024;
+constexpr int kScanUnroll = 8;
+
+__global__ __launch_bounds__(kScanThreads) void k_filter_scan(int64_t* partials, int n) {
+    __shared__ int64_t buf[kScanThreads];
     const int t = (int)threadIdx.x;
-    const int per = (n + kFilterThreads - 1) / kFilterThreads;
+    const int per = (n + kScanThreads - 1) / kScanThreads;
     const int lo = min(n, t * per), hi = min(n, lo + per);
     int64_t sum = 0;
-    for (int i = lo; i < hi; ++i) sum += partials[i];
+    for (int i0 = lo; i0 < hi; i0 += kScanUnroll) {
+        int64_t v[kScanUnroll];
+#pragma unroll
+        for (int u = 0; u < kScanUnroll; ++u) v[u] = i0 + u < hi ? partials[i0 + u] : 0;
+#pragma unroll
+        for (int u = 0; u < kScanUnroll; ++u) sum += v[u];
+    }
     buf[t] = sum;
     __syncthreads();
-    for (int d = 1; d < kFilterThreads; d <<= 1) {  // inclusive
+    for (int d = 1; d < kScanThreads; d <<= 1) {  // inclusive
         const int64_t o = t >= d ? buf[t - d] : 0;
         __syncthreads();
         buf[t] += o;
@@ -236,99 +275,179 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_scan(int64_t* partial
         partials[i] = run;
         run += v;
     }
-    if (t == kFilterThreads - 1) partials[n] = buf[t];
+    if (t == kScanThreads - 1) partials[n] = buf[t];
 }
+
+// Per-event data of the scatter's workgroup, in LDS.
+struct ScatterEvent {
+    int64_t s[3];   // first output position of the event's layer-l hits
+    int64_t d[3];   // s[l] minus the layer-l hits of the wave's earlier events
+    int64_t a;      // first hit of the event
+    int32_t rec0;   // first record of the event in its wave's list
+    int32_t nrec;   // records of the event (0 for a malformed one)
+    int32_t ok;     // the event range is well-formed
+    int32_t pad;
+};
+
+// Record data of one chunk of 64 records of a wave, in LDS.
+struct ScatterRec {
+    int64_t h0;        // hit of bit 0
+    int64_t base[3];   // output position of the record's first layer-l hit
+    uint32_t m[3];     // layer masks
+    uint32_t pad;
+};
 
 __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
     const int64_t* __restrict__ off, int n_events, int64_t n_hits, const uint8_t* __restrict__ st,
     const float* __restrict__ x, const float* __restrict__ y, uint32_t layers, int vec,
     const int32_t* __restrict__ counts, const int64_t* __restrict__ partials,
-    const uint32_t* __restrict__ wave_lists, int n_blocks, int32_t capacity, int32_t* __restrict__ out_off,
-    float* __restrict__ out_x, float* __restrict__ out_y, uint32_t* status) {
-    __shared__ int64_t ev_start[kFilterEvents];
-    __shared__ uint16_t lists[kFilterWaves][kStepHits];  // per wave: the step's matched hits (no-list path)
+    const u32x4r* __restrict__ wave_recs, const int32_t* __restrict__ ev_recs, int n_blocks, int32_t capacity,
+    int32_t* __restrict__ out_off, float* __restrict__ out_x, float* __restrict__ out_y, uint32_t* status) {
+    static_assert(kFilterEvents <= trig::kWave, "one lane per event in the prologue");
+    __shared__ ScatterEvent ev[kFilterEvents];
+    __shared__ int64_t cnt_lds[kFilterEvents][3];
+    __shared__ int32_t nrec_lds[kFilterEvents];
+    __shared__ int32_t wave_nrec[kFilterWaves];
+    // Per wave, its own: the record data of a chunk (listed path) or the
+    // step's matched hits (the other path).  Waves of a workgroup may take
+    // different paths, so the two uses overlap only within one wave.
+    __shared__ union {
+        ScatterRec recs[trig::kWave];
+        uint16_t lists[kStepHits];
+    } work[kFilterWaves];
     const int w = trig::uniform_i((int)(threadIdx.x / trig::kWave));
-    uint16_t* list = lists[w];
     const int lane = (int)trig::lane_id();
     const int e_first = (int)blockIdx.x * kFilterEvents;
     const int64_t cap = capacity;
-    if (threadIdx.x == 0) {
-        // Starts of the workgroup's events: its base plus the totals of the
-        // events before (int64: three int32 counts per event).
-        int64_t at = partials[blockIdx.x];
-        for (int j = 0; j < kFilterEvents; ++j) {
-            ev_start[j] = at;
-            const int e = e_first + j;
-            if (e < n_events)
-                at += (int64_t)counts[3 * (int64_t)e] + counts[3 * (int64_t)e + 1] + counts[3 * (int64_t)e + 2];
-        }
-    }
     if ((int)blockIdx.x == n_blocks - 1 && threadIdx.x == 0) {
         const int64_t total = partials[n_blocks];
         if (total > cap && status) atomicOr(status, TRIG_FILTER_CAPACITY);
         out_off[3 * (int64_t)n_events] = (int32_t)std::min<int64_t>(total, cap);
     }
-    __syncthreads();
-    // The wave's list is complete iff the count kernel never stopped writing
-    // it: all its events' trigger hits fit, and none of its events has 2^30
-    // hits or more (the same conditions, from the counts and offsets).
-    const uint32_t* wlist = wave_lists + ((int64_t)blockIdx.x * kFilterWaves + w) * kWaveList;
-    bool listed = true;
-    {
-        int64_t n_list = 0;
-        for (int j = w; j < kFilterEvents; j += kFilterWaves) {
-            const int e = e_first + j;
-            if (e >= n_events) break;
-            const Range r = event_range(off, e, n_hits);
-            if (r.ok && r.b - r.a >= kMaxListEvent) listed = false;
-            n_list += (int64_t)counts[3 * (int64_t)e] + counts[3 * (int64_t)e + 1] + counts[3 * (int64_t)e + 2];
+    // Prologue, one lane of wave 0 per event j: its counts, record count and
+    // range; then its output positions, its first record in its wave's list
+    // (events j % 4, j % 4 + 4, ... form wave j % 4's list) and its offsets
+    // out_off[3 e + l].
+    if (w == 0) {
+        const int j = lane;
+        const int e = e_first + j;
+        const bool in = j < kFilterEvents && e < n_events;
+        int64_t c[3] = {0, 0, 0};
+        int32_t nr = 0;
+        Range r{0, 0, false};
+        if (in) {
+            c[0] = counts[3 * (int64_t)e];
+            c[1] = counts[3 * (int64_t)e + 1];
+            c[2] = counts[3 * (int64_t)e + 2];
+            nr = ev_recs[e];
+            r = event_range(off, e, n_hits);
         }
-        if (n_list > kWaveList) listed = false;
+        if (j < kFilterEvents) {
+            cnt_lds[j][0] = c[0];
+            cnt_lds[j][1] = c[1];
+            cnt_lds[j][2] = c[2];
+            nrec_lds[j] = nr;
+        }
+        trig::wave_lds_sync();
+        if (j < kFilterEvents) {
+            int64_t before = partials[blockIdx.x], wave_before[3] = {0, 0, 0};
+            int32_t rec_before = 0;
+            for (int k = 0; k < j; ++k) before += cnt_lds[k][0] + cnt_lds[k][1] + cnt_lds[k][2];
+            for (int k = j % kFilterWaves; k < j; k += kFilterWaves) {
+                rec_before += nrec_lds[k];
+                wave_before[0] += cnt_lds[k][0];
+                wave_before[1] += cnt_lds[k][1];
+                wave_before[2] += cnt_lds[k][2];
+            }
+            ScatterEvent v;
+            v.s[0] = before;
+            v.s[1] = before + c[0];
+            v.s[2] = before + c[0] + c[1];
+#pragma unroll
+            for (int l = 0; l < 3; ++l) v.d[l] = v.s[l] - wave_before[l];
+            v.a = r.a;
+            v.rec0 = rec_before;
+            v.nrec = nr;
+            v.ok = r.ok ? 1 : 0;
+            v.pad = 0;
+            ev[j] = v;
+            if (in) {
+#pragma unroll
+                for (int l = 0; l < 3; ++l) out_off[3 * (int64_t)e + l] = (int32_t)std::min<int64_t>(v.s[l], cap);
+            }
+        }
+        if (lane < kFilterWaves) {
+            int32_t n = 0;
+            for (int k = lane; k < kFilterEvents; k += kFilterWaves) n += nrec_lds[k];
+            wave_nrec[lane] = n;
+        }
     }
-    int32_t pos = 0;  // this event's first entry in wlist
+    __syncthreads();
+    const int32_t n_rec = trig::uniform_i(wave_nrec[w]);
+    if (n_rec <= kWaveRecords) {
+        // The wave's list is complete (the count kernel's condition): its
+        // records, 64 at a time.  Lane i takes record i: its event (the
+        // wave's event whose record range holds i), layer counts and, by a
+        // wave scan, its first output position per layer; then two records
+        // per round, one per half-wave, lane b of a half on hit h0 + b.
+        const u32x4r* wrec = wave_recs + ((int64_t)blockIdx.x * kFilterWaves + w) * kWaveRecords;
+        ScatterRec* rl = work[w].recs;
+        int32_t carry[3] = {0, 0, 0};  // layer-l hits of the wave's earlier chunks
+        for (int32_t cb = 0; cb < n_rec; cb += trig::kWave) {
+            const int32_t i = cb + lane;
+            const bool valid = i < n_rec;
+            const u32x4r R = valid ? wrec[i] : u32x4r{0u, 0u, 0u, 0u};
+            int j = w;
+            for (int k = w + kFilterWaves; k < kFilterEvents; k += kFilterWaves)
+                if (ev[k].nrec > 0 && ev[k].rec0 <= i) j = k;
+            const uint32_t m[3] = {R.y, R.z, R.w};
+            ScatterRec v;
+            v.h0 = ev[j].a + (int64_t)(int32_t)R.x;
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                const int p = __builtin_popcount(m[l]);
+                const int incl = trig::wave_inclusive_sum(p);
+                v.base[l] = ev[j].d[l] + carry[l] + (incl - p);
+                v.m[l] = m[l];
+                carry[l] += __builtin_amdgcn_readlane(incl, 63);
+            }
+            v.pad = 0;
+            rl[lane] = v;
+            trig::wave_lds_sync();
+            const int32_t nc = min(trig::kWave, n_rec - cb);
+            const int half = lane >> 5, b = lane & 31;
+            const uint32_t below = (1u << b) - 1u;
+#pragma unroll 4
+            for (int32_t q = 0; q < nc; q += 2) {
+                const int32_t k = q + half;
+                if (k < nc) {
+                    const ScatterRec& u = rl[k];
+                    const uint32_t m0 = u.m[0], m1 = u.m[1], m2 = u.m[2];
+                    const uint32_t bit = 1u << b;
+                    if ((m0 | m1 | m2) & bit) {
+                        const int l = (m0 & bit) ? 0 : ((m1 & bit) ? 1 : 2);
+                        const uint32_t ml = l == 0 ? m0 : (l == 1 ? m1 : m2);
+                        const int64_t p = u.base[l] + __builtin_popcount(ml & below);
+                        if (p >= 0 && p < cap) {  // positions past an int32 block prefix are never written
+                            const int64_t h = u.h0 + b;
+                            out_x[p] = x[h];
+                            out_y[p] = y[h];
+                        }
+                    }
+                }
+            }
+            trig::wave_lds_sync();  // the next chunk rewrites rl
+        }
+        return;
+    }
+    // The list is incomplete: read the wave's events' station numbers again.
+    uint16_t* list = work[w].lists;
     for (int j = w; j < kFilterEvents; j += kFilterWaves) {
         const int e = e_first + j;
         if (e >= n_events) break;
-        const int64_t c0 = counts[3 * (int64_t)e], c1 = counts[3 * (int64_t)e + 1];
-        const int64_t c2 = counts[3 * (int64_t)e + 2];
-        int64_t s[3];
-        s[0] = ev_start[j];
-        s[1] = s[0] + c0;
-        s[2] = s[1] + c1;
-        if (lane < 3) {
-            const int64_t v = lane == 0 ? s[0] : (lane == 1 ? s[1] : s[2]);
-            out_off[3 * (int64_t)e + lane] = (int32_t)std::min<int64_t>(v, cap);
-        }
+        if (!ev[j].ok) continue;
+        int64_t s[3] = {ev[j].s[0], ev[j].s[1], ev[j].s[2]};
         const Range r = event_range(off, e, n_hits);
-        if (!r.ok) continue;
-        if (listed) {
-            // 64 entries per round: a lane's rank in its layer is the number
-            // of earlier lanes with the same layer (entries are in input order)
-            const int32_t tot = (int32_t)(c0 + c1 + c2);
-            for (int32_t k0 = 0; k0 < tot; k0 += trig::kWave) {
-                const int32_t k = k0 + lane;
-                const bool valid = k < tot;
-                const uint32_t en = valid ? wlist[pos + k] : 0u;
-                const uint32_t l = en >> 30;
-                const uint64_t b0 = trig::lanes(valid && l == 0u);
-                const uint64_t b1 = trig::lanes(valid && l == 1u);
-                const uint64_t b2 = trig::lanes(valid && l == 2u);
-                const uint64_t mb = l == 0u ? b0 : (l == 1u ? b1 : b2);
-                const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(mb >> 32),
-                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)mb, 0u));
-                const int64_t p = (l == 0u ? s[0] : (l == 1u ? s[1] : s[2])) + rank;
-                if (valid && p >= 0 && p < cap) {
-                    const int64_t h = r.a + (int64_t)(en & 0x3FFFFFFFu);
-                    out_x[p] = x[h];
-                    out_y[p] = y[h];
-                }
-                s[0] += __builtin_popcountll(b0);
-                s[1] += __builtin_popcountll(b1);
-                s[2] += __builtin_popcountll(b2);
-            }
-            pos += tot;
-            continue;
-        }
         int64_t base = r.a & ~(int64_t)15;
         LaneStations cur, nxt;
         cur.load(st, base + (int64_t)kLaneHits * lane, n_hits, vec != 0);
@@ -385,7 +504,7 @@ size_t trig_filter_workspace_bytes(int32_t n_events) {
     if (n_events < 0) return 0;
     const int64_t nb = std::max<int64_t>(1, ((int64_t)n_events + kFilterEvents - 1) / kFilterEvents);
     return align256(sizeof(int32_t) * 3 * (size_t)n_events) + align256(sizeof(int64_t) * (size_t)(nb + 1)) +
-           align256(sizeof(uint32_t) * (size_t)nb * kFilterWaves * kWaveList);
+           align256(sizeof(int32_t) * (size_t)n_events) + align256(16 * (size_t)nb * kFilterWaves * kWaveRecords);
 }
 
 int trig_filter_stations(const trig_raw_events* ev, const trig_filter_params* p, void* stream) {
@@ -410,16 +529,19 @@ int trig_filter_stations(const trig_raw_events* ev, const trig_filter_params* p,
     char* ws = static_cast<char*>(p->workspace);
     const size_t counts_bytes = align256(sizeof(int32_t) * 3 * (size_t)n);
     auto* partials = reinterpret_cast<int64_t*>(ws + counts_bytes);
-    auto* wave_lists = reinterpret_cast<uint32_t*>(ws + counts_bytes + align256(sizeof(int64_t) * (size_t)(nb + 1)));
+    const size_t partial_bytes = align256(sizeof(int64_t) * (size_t)(nb + 1));
+    auto* ev_recs = reinterpret_cast<int32_t*>(ws + counts_bytes + partial_bytes);
+    auto* wave_recs = reinterpret_cast<u32x4r*>(ws + counts_bytes + partial_bytes +
+                                                align256(sizeof(int32_t) * (size_t)n));
     const uint32_t layers = (uint32_t)p->layers[0] | ((uint32_t)p->layers[1] << 8) | ((uint32_t)p->layers[2] << 16);
     const int vec = (reinterpret_cast<uintptr_t>(ev->station) & 15) == 0;
     hipLaunchKernelGGL(k_filter_count, dim3(nb), dim3(kFilterThreads), 0, s, ev->offsets, n, ev->n_hits,
-                       ev->station, layers, vec, counts, partials, wave_lists, p->out_status);
+                       ev->station, layers, vec, counts, partials, wave_recs, ev_recs, p->out_status);
     if (hipGetLastError() != hipSuccess) return TRIG_EHIP;
-    hipLaunchKernelGGL(k_filter_scan, dim3(1), dim3(kFilterThreads), 0, s, partials, nb);
+    hipLaunchKernelGGL(k_filter_scan, dim3(1), dim3(kScanThreads), 0, s, partials, nb);
     if (hipGetLastError() != hipSuccess) return TRIG_EHIP;
     hipLaunchKernelGGL(k_filter_scatter, dim3(nb), dim3(kFilterThreads), 0, s, ev->offsets, n, ev->n_hits,
-                       ev->station, ev->x, ev->y, layers, vec, counts, partials, wave_lists, nb, p->out_capacity,
+                       ev->station, ev->x, ev->y, layers, vec, counts, partials, wave_recs, ev_recs, nb, p->out_capacity,
                        p->out_layer_offsets, p->out_x, p->out_y, p->out_status);
     return hipGetLastError() == hipSuccess ? TRIG_OK : TRIG_EHIP;
 }

@@ -130,30 +130,47 @@ def test_filtered_events_feed_the_selection(gpu):
     assert np.array_equal(sel.counts.cpu().numpy()[:5000], c)
 
 
+def window_records(off, st, layers):
+    """Per event, the lane windows the count kernel records: windows of 32
+    hits from the event's first hit rounded down to a multiple of 16, each
+    counted when it holds a trigger hit of the event."""
+    trig = np.isin(st, np.asarray(layers, np.uint8))
+    recs = np.zeros(len(off) - 1, np.int64)
+    for e in range(len(off) - 1):
+        a, b = int(off[e]), int(off[e + 1])
+        base = a & ~15
+        while base < b:
+            recs[e] += bool(trig[max(a, base):min(b, base + 32)].any())
+            base += 32
+    return recs
+
+
 def test_trigger_hit_lists_at_capacity(gpu):
-    """The count kernel lists each group of 8 events' trigger hits (events
-    w, w+4, ..., w+28 of a block of 32) for the scatter, up to 2048 entries;
-    a group with more is scattered from a second pass over its station
-    numbers.  Groups at exactly 2048 and at 2049 trigger hits, in both
-    paths, bit-exact against the oracle."""
+    """The count kernel keeps, per group of 4 events (events w, w+4, w+8,
+    w+12 of a block of 16), up to 128 records of 32-hit windows with trigger
+    hits for the scatter; a group that needs more is scattered from a second
+    pass over its station numbers.  Groups at 127, 128 and 129 records, in
+    both paths, bit-exact against the oracle."""
     rng = np.random.default_rng(9)
-    n_ev = 64
-    trig_per_event = np.full(n_ev, 256)
-    trig_per_event[1 + 4 * 3] = 257           # group 1 of block 0: 2049 entries
-    trig_per_event[32 + 2 + 4 * 5] = 255      # group 2 of block 1: 2047 entries
-    trig_per_event[32 + 3] = 0                # group 3 of block 1: 1792 entries
-    off = [0]
-    st_parts = []
-    for e in range(n_ev):
-        other = int(rng.integers(0, 300))
-        s = np.concatenate([rng.choice(np.array([13, 14, 15], np.uint8), int(trig_per_event[e])),
-                            rng.integers(0, 12, other).astype(np.uint8)])
-        rng.shuffle(s)
-        st_parts.append(s)
-        off.append(off[-1] + len(s))
-    st = np.concatenate(st_parts)
-    off = np.asarray(off, np.int64)
+    n_ev = 32
+    lens = np.full(n_ev, 1024)             # multiples of 16: every event's windows start at its first hit
+    lens[1 + 4 * 3] = 1024 + 16            # group 1 of block 0: 129 records
+    lens[16 + 2 + 4 * 2] = 1024 - 32       # group 2 of block 1: 127 records
+    lens[n_ev - 1] = 1001                  # a ragged last event
+    off = np.zeros(n_ev + 1, np.int64)
+    np.cumsum(lens, out=off[1:])
+    layers = (13, 14, 15)
+    st = rng.choice(np.array(layers, np.uint8), int(off[-1]))
+    # event 16 + 3 (group 3 of block 1): every other window without a trigger
+    # hit, and the rest a mix of trigger and other stations
+    a = int(off[19])
+    for k in range(32):
+        w = st[a + 32 * k:a + 32 * k + 32]
+        w[:] = rng.integers(0, 12, 32) if k % 2 else np.where(rng.random(32) < 0.5, w, 3)
+    recs = window_records(off, st, layers)
+    groups = recs.reshape(2, 4, 4).sum(axis=1)  # [block, w]
+    assert groups[0, 0] == 128 and groups[0, 1] == 129 and groups[1, 2] == 127 and groups[1, 3] == 112
     x = rng.standard_normal(len(st)).astype(np.float32)
     y = rng.standard_normal(len(st)).astype(np.float32)
-    assert_filter_parity(gpu, "lists at capacity", off, st, x, y)
-    assert_filter_parity(gpu, "lists at capacity misaligned", off, st, x, y, misalign=True)
+    assert_filter_parity(gpu, "lists at capacity", off, st, x, y, layers)
+    assert_filter_parity(gpu, "lists at capacity misaligned", off, st, x, y, layers, misalign=True)
