@@ -87,16 +87,36 @@ struct LaneMatch {
     uint32_t m[3];
 };
 
-// Bytes of w equal to the byte v (v4 = v * 0x01010101): bit k set for byte k.
-// A byte of x = w ^ v4 is zero where they are equal; adding 0x7F to each
-// byte's low seven bits carries into its bit 7 exactly when they are not all
-// zero (never into the next byte), so bit 7 of ~(that | x) marks the zero
-// bytes, and one multiply gathers the four marks into bits 21..24.
-__device__ __forceinline__ uint32_t eq_bytes(uint32_t w, uint32_t v4) {
+// Bytes of w equal to the byte v (v4 = v * 0x01010101), as bit 7 of each
+// byte.  A byte of x = w ^ v4 is zero where they are equal; adding 0x7F to
+// each byte's low seven bits carries into its bit 7 exactly when they are
+// not all zero (never into the next byte), so bit 7 of ~(that | x) marks the
+// zero bytes.
+__device__ __forceinline__ uint32_t byte_flags(uint32_t w, uint32_t v4) {
     const uint32_t x = w ^ v4;
     const uint32_t t = ((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x;
-    const uint32_t z = ~t & 0x80808080u;
-    return (((z >> 7) * 0x00204081u) >> 21) & 0xFu;
+    return ~t & 0x80808080u;
+}
+
+// The same as bits 0..3 (bit k for byte k): one multiply gathers the four
+// marks into bits 21..24.
+__device__ __forceinline__ uint32_t eq_bytes(uint32_t w, uint32_t v4) {
+    return (((byte_flags(w, v4) >> 7) * 0x00204081u) >> 21) & 0xFu;
+}
+
+// Transposed lane masks (the count kernel's records): bit 8 k + q stands for
+// hit 4 q + k of a lane's 32-hit window (word q of its eight station words,
+// byte k).  Shifting word q's byte flags right by 7 - q puts them at bits
+// 8 k + q, so the eight words OR into one mask with a shift and an OR each.
+__device__ __forceinline__ uint32_t tpos(int n) { return 8u * (uint32_t)(n & 3) + (uint32_t)(n >> 2); }
+
+// Transposed mask of the hits [0, h) of a window, 0 <= h <= 32: in byte row
+// k, the words q with 4 q + k < h, i.e. q < (h - k + 3) / 4.
+__device__ __forceinline__ uint32_t tupto(int h) {
+    uint32_t m = 0u;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) m |= ((1u << (uint32_t)((h - k + 3) >> 2)) - 1u) << (8 * k);
+    return m;
 }
 
 __device__ __forceinline__ LaneMatch match_lane(const LaneStations& s, int64_t h0, int64_t a, int64_t b,
@@ -120,10 +140,25 @@ __device__ __forceinline__ LaneMatch match_lane(const LaneStations& s, int64_t h
     return r;
 }
 
+// Transposed layer masks of a lane's window (see tpos), restricted to the
+// hits in_t marks.
+__device__ __forceinline__ LaneMatch match_lane_t(const LaneStations& s, uint32_t in_t, uint32_t layers) {
+    LaneMatch r{{0u, 0u, 0u}};
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const uint32_t v4 = ((layers >> (8 * l)) & 0xFFu) * 0x01010101u;
+        uint32_t acc = 0u;
+#pragma unroll
+        for (int q = 0; q < kLaneHits / 4; ++q) acc |= byte_flags(s.w[q], v4) >> (7 - q);
+        r.m[l] = acc & in_t;
+    }
+    return r;
+}
+
 // Records one wave keeps for the scatter: per lane window of kLaneHits
 // consecutive hits that holds a trigger hit of its event, the window's start
-// relative to the event's first hit and the layer masks (bit b: hit
-// start + b), in input order.
+// relative to the event's first hit and the transposed layer masks (bit
+// tpos(b): hit start + b), in input order.
 constexpr int kWaveRecords = 128;
 typedef unsigned u32x4r __attribute__((ext_vector_type(4)));  // {start, m0, m1, m2}
 
@@ -137,6 +172,9 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_count(const int64_t* 
                                                                    uint32_t* status) {
     constexpr int kPer = kFilterEvents / kFilterWaves;  // events of a wave
     __shared__ int64_t wave_total[kFilterWaves];
+    __shared__ uint32_t tup[kLaneHits + 1];  // tupto(h)
+    if (threadIdx.x <= (unsigned)kLaneHits) tup[threadIdx.x] = tupto((int)threadIdx.x);
+    __syncthreads();
     const int w = trig::uniform_i((int)(threadIdx.x / trig::kWave));
     const int lane = (int)trig::lane_id();
     const int e_first = (int)blockIdx.x * kFilterEvents;
@@ -178,7 +216,14 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_count(const int64_t* 
     // One flat stream over the live events' steps: the next step's station
     // numbers (of this event or the next) are in flight while this step's
     // are matched.
-    int k = next_live(-1);
+    // k and the step starts are wave-uniform; readfirstlane keeps them in
+    // scalar registers (the compiler cannot see it through the loop).
+    auto uniform64 = [](int64_t v) {
+        const uint32_t lo = (uint32_t)trig::uniform_i((int)(uint32_t)v);
+        const uint32_t hi = (uint32_t)trig::uniform_i((int)(uint32_t)((uint64_t)v >> 32));
+        return (int64_t)(((uint64_t)hi << 32) | lo);
+    };
+    int k = trig::uniform_i(next_live(-1));
     if (k < kPer) {
         int64_t base = ra[k] & ~(int64_t)15;
         LaneStations cur, nxt;
@@ -193,9 +238,20 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_count(const int64_t* 
                 k1 = next_live(k);
                 base1 = k1 < kPer ? ra[k1] & ~(int64_t)15 : 0;
             }
+            k1 = trig::uniform_i(k1);
+            base1 = uniform64(base1);
             if (k1 < kPer) nxt.load(st, base1 + (int64_t)kLaneHits * lane, n_hits, vec != 0);
             const int64_t h0 = base + (int64_t)kLaneHits * lane;
-            const LaneMatch m = match_lane(cur, h0, ra[k], rb[k], layers);
+            // the lane's hits of event k: all of them unless the step
+            // straddles an end of the event
+            uint32_t in_t = 0xFFFFFFFFu;
+            if (base < ra[k] || base + kStepHits > rb[k]) {  // wave-uniform
+                const int64_t lo = ra[k] - h0, hi = rb[k] - h0;
+                const int l0 = lo <= 0 ? 0 : (lo >= kLaneHits ? kLaneHits : (int)lo);
+                const int h1 = hi <= 0 ? 0 : (hi >= kLaneHits ? kLaneHits : (int)hi);
+                in_t = h1 > l0 ? tup[h1] & ~tup[l0] : 0u;
+            }
+            const LaneMatch m = match_lane_t(cur, in_t, layers);
 #pragma unroll
             for (int l = 0; l < 3; ++l) c[l] += (uint32_t)__builtin_popcount(m.m[l]);
             cur = nxt;
@@ -304,13 +360,13 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
     const u32x4r* __restrict__ wave_recs, const int32_t* __restrict__ ev_recs, int n_blocks, int32_t capacity,
     int32_t* __restrict__ out_off, float* __restrict__ out_x, float* __restrict__ out_y, uint32_t* status) {
     static_assert(kFilterEvents <= trig::kWave, "one lane per event in the prologue");
-    __shared__ ScatterEvent ev[kFilterEvents];
-    __shared__ int64_t cnt_lds[kFilterEvents][3];
-    __shared__ int32_t nrec_lds[kFilterEvents];
-    __shared__ int32_t wave_nrec[kFilterWaves];
-    // Per wave, its own: the record data of a chunk (listed path) or the
-    // step's matched hits (the other path).  Waves of a workgroup may take
-    // different paths, so the two uses overlap only within one wave.
+    constexpr int kPer = kFilterEvents / kFilterWaves;  // events of a wave
+    // Per wave, its own copies: no wave waits for another.
+    __shared__ ScatterEvent ev_all[kFilterWaves][kPer];  // the wave's events w, w + 4, ...
+    __shared__ int64_t cnt_all[kFilterWaves][kFilterEvents][3];
+    __shared__ int32_t nrec_all[kFilterWaves][kFilterEvents];
+    // Per wave: the record data of a chunk (listed path) or the step's
+    // matched hits (the other path).
     __shared__ union {
         ScatterRec recs[trig::kWave];
         uint16_t lists[kStepHits];
@@ -319,45 +375,57 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
     const int lane = (int)trig::lane_id();
     const int e_first = (int)blockIdx.x * kFilterEvents;
     const int64_t cap = capacity;
+    ScatterEvent* ev = ev_all[w];
+    // The first 64 entries of the wave's list, loaded with the prologue's
+    // loads (one round trip for both; entries past the wave's records are
+    // not used, and the list holds kWaveRecords >= 64 entries).
+    static_assert(kWaveRecords >= trig::kWave, "first chunk inside the list");
+    const u32x4r* wrec = wave_recs + ((int64_t)blockIdx.x * kFilterWaves + w) * kWaveRecords;
+    const u32x4r first = wrec[lane];
     if ((int)blockIdx.x == n_blocks - 1 && threadIdx.x == 0) {
         const int64_t total = partials[n_blocks];
         if (total > cap && status) atomicOr(status, TRIG_FILTER_CAPACITY);
         out_off[3 * (int64_t)n_events] = (int32_t)std::min<int64_t>(total, cap);
     }
-    // Prologue, one lane of wave 0 per event j: its counts, record count and
-    // range; then its output positions, its first record in its wave's list
-    // (events j % 4, j % 4 + 4, ... form wave j % 4's list) and its offsets
-    // out_off[3 e + l].
-    if (w == 0) {
+    // Prologue, every wave for itself, one lane per event j of the
+    // workgroup: its counts and record count; then, for the wave's own
+    // events (j % 4 == w), the output positions, the first record in the
+    // wave's list and the offsets out_off[3 e + l].
+    int32_t n_rec = 0;  // records of the wave's events
+    {
+        const int64_t wg_base = partials[blockIdx.x];
+        int64_t(*cnt)[3] = cnt_all[w];
+        int32_t* nrec = nrec_all[w];
         const int j = lane;
         const int e = e_first + j;
         const bool in = j < kFilterEvents && e < n_events;
         int64_t c[3] = {0, 0, 0};
         int32_t nr = 0;
         Range r{0, 0, false};
+        const bool mine = j < kFilterEvents && j % kFilterWaves == w;
         if (in) {
             c[0] = counts[3 * (int64_t)e];
             c[1] = counts[3 * (int64_t)e + 1];
             c[2] = counts[3 * (int64_t)e + 2];
             nr = ev_recs[e];
-            r = event_range(off, e, n_hits);
+            if (mine) r = event_range(off, e, n_hits);
         }
         if (j < kFilterEvents) {
-            cnt_lds[j][0] = c[0];
-            cnt_lds[j][1] = c[1];
-            cnt_lds[j][2] = c[2];
-            nrec_lds[j] = nr;
+            cnt[j][0] = c[0];
+            cnt[j][1] = c[1];
+            cnt[j][2] = c[2];
+            nrec[j] = nr;
         }
         trig::wave_lds_sync();
-        if (j < kFilterEvents) {
-            int64_t before = partials[blockIdx.x], wave_before[3] = {0, 0, 0};
+        if (mine) {
+            int64_t before = wg_base, wave_before[3] = {0, 0, 0};
             int32_t rec_before = 0;
-            for (int k = 0; k < j; ++k) before += cnt_lds[k][0] + cnt_lds[k][1] + cnt_lds[k][2];
-            for (int k = j % kFilterWaves; k < j; k += kFilterWaves) {
-                rec_before += nrec_lds[k];
-                wave_before[0] += cnt_lds[k][0];
-                wave_before[1] += cnt_lds[k][1];
-                wave_before[2] += cnt_lds[k][2];
+            for (int k = 0; k < j; ++k) before += cnt[k][0] + cnt[k][1] + cnt[k][2];
+            for (int k = w; k < j; k += kFilterWaves) {
+                rec_before += nrec[k];
+                wave_before[0] += cnt[k][0];
+                wave_before[1] += cnt[k][1];
+                wave_before[2] += cnt[k][2];
             }
             ScatterEvent v;
             v.s[0] = before;
@@ -370,35 +438,30 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
             v.nrec = nr;
             v.ok = r.ok ? 1 : 0;
             v.pad = 0;
-            ev[j] = v;
+            ev[j / kFilterWaves] = v;
             if (in) {
 #pragma unroll
                 for (int l = 0; l < 3; ++l) out_off[3 * (int64_t)e + l] = (int32_t)std::min<int64_t>(v.s[l], cap);
             }
         }
-        if (lane < kFilterWaves) {
-            int32_t n = 0;
-            for (int k = lane; k < kFilterEvents; k += kFilterWaves) n += nrec_lds[k];
-            wave_nrec[lane] = n;
-        }
+        for (int k = w; k < kFilterEvents; k += kFilterWaves) n_rec += nrec[k];  // wave-uniform LDS reads
+        n_rec = trig::uniform_i(n_rec);
+        trig::wave_lds_sync();  // ev[] written
     }
-    __syncthreads();
-    const int32_t n_rec = trig::uniform_i(wave_nrec[w]);
     if (n_rec <= kWaveRecords) {
         // The wave's list is complete (the count kernel's condition): its
         // records, 64 at a time.  Lane i takes record i: its event (the
         // wave's event whose record range holds i), layer counts and, by a
         // wave scan, its first output position per layer; then two records
         // per round, one per half-wave, lane b of a half on hit h0 + b.
-        const u32x4r* wrec = wave_recs + ((int64_t)blockIdx.x * kFilterWaves + w) * kWaveRecords;
         ScatterRec* rl = work[w].recs;
         int32_t carry[3] = {0, 0, 0};  // layer-l hits of the wave's earlier chunks
         for (int32_t cb = 0; cb < n_rec; cb += trig::kWave) {
             const int32_t i = cb + lane;
             const bool valid = i < n_rec;
-            const u32x4r R = valid ? wrec[i] : u32x4r{0u, 0u, 0u, 0u};
-            int j = w;
-            for (int k = w + kFilterWaves; k < kFilterEvents; k += kFilterWaves)
+            const u32x4r R = !valid ? u32x4r{0u, 0u, 0u, 0u} : (cb == 0 ? first : wrec[i]);
+            int j = 0;  // the wave's event (index among its kPer) that holds record i
+            for (int k = 1; k < kPer; ++k)
                 if (ev[k].nrec > 0 && ev[k].rec0 <= i) j = k;
             const uint32_t m[3] = {R.y, R.z, R.w};
             ScatterRec v;
@@ -416,14 +479,13 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
             trig::wave_lds_sync();
             const int32_t nc = min(trig::kWave, n_rec - cb);
             const int half = lane >> 5, b = lane & 31;
-            const uint32_t below = (1u << b) - 1u;
+            const uint32_t bit = 1u << tpos(b), below = tupto(b);  // hit b, hits before b
 #pragma unroll 4
             for (int32_t q = 0; q < nc; q += 2) {
                 const int32_t k = q + half;
                 if (k < nc) {
                     const ScatterRec& u = rl[k];
                     const uint32_t m0 = u.m[0], m1 = u.m[1], m2 = u.m[2];
-                    const uint32_t bit = 1u << b;
                     if ((m0 | m1 | m2) & bit) {
                         const int l = (m0 & bit) ? 0 : ((m1 & bit) ? 1 : 2);
                         const uint32_t ml = l == 0 ? m0 : (l == 1 ? m1 : m2);
@@ -445,8 +507,9 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
     for (int j = w; j < kFilterEvents; j += kFilterWaves) {
         const int e = e_first + j;
         if (e >= n_events) break;
-        if (!ev[j].ok) continue;
-        int64_t s[3] = {ev[j].s[0], ev[j].s[1], ev[j].s[2]};
+        const ScatterEvent& v = ev[j / kFilterWaves];
+        if (!v.ok) continue;
+        int64_t s[3] = {v.s[0], v.s[1], v.s[2]};
         const Range r = event_range(off, e, n_hits);
         int64_t base = r.a & ~(int64_t)15;
         LaneStations cur, nxt;

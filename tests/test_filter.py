@@ -66,3 +66,41 @@ def test_swar_byte_match_identity():
         want = sum(((((w >> np.uint64(8 * k)) & np.uint64(255)) == v).astype(np.uint64) << np.uint64(k))
                    for k in range(4))
         assert np.array_equal(got, want), v
+
+
+def test_transposed_window_masks():
+    """The count kernel's records hold transposed masks: bit 8 k + q for hit
+    4 q + k of a 32-hit window.  Word q's byte flags (bit 7 of each byte)
+    shifted right by 7 - q land there; the hits [0, h) are, per byte row k,
+    the words q < (h - k + 3) // 4; the scatter tests hit b at bit
+    8 (b % 4) + b // 4 and ranks it by the masked bits of [0, b).  All three
+    against the natural bit order, on random windows and every h."""
+    def tpos(n):
+        return 8 * (n & 3) + (n >> 2)
+
+    def tupto(h):
+        return sum(((1 << ((h - k + 3) >> 2)) - 1) << (8 * k) for k in range(4))
+
+    def transpose(nat):
+        return sum(1 << tpos(n) for n in range(32) if nat >> n & 1)
+
+    for h in range(33):
+        assert tupto(h) == transpose((1 << h) - 1), h
+    rng = np.random.default_rng(11)
+    for _ in range(3000):
+        st = rng.choice(np.array([13, 14, 15, 3, 200, 0, 255]), 32)
+        v = int(rng.choice([13, 14, 15, 0, 255]))
+        acc = 0
+        for q in range(8):
+            w = int(st[4 * q]) | int(st[4 * q + 1]) << 8 | int(st[4 * q + 2]) << 16 | int(st[4 * q + 3]) << 24
+            x = w ^ (v * 0x01010101)
+            t = (((x & 0x7F7F7F7F) + 0x7F7F7F7F) | x) & 0xFFFFFFFF
+            acc |= ((~t) & 0x80808080) >> (7 - q)
+        nat = sum(1 << n for n in range(32) if st[n] == v)
+        assert acc == transpose(nat)
+        lo, hi = sorted(int(a) for a in rng.integers(0, 33, 2))
+        m = acc & (tupto(hi) & ~tupto(lo))
+        inside = nat & (((1 << hi) - 1) & ~((1 << lo) - 1))
+        for b in range(32):
+            assert (m >> tpos(b)) & 1 == (inside >> b) & 1
+            assert bin(m & tupto(b)).count("1") == bin(inside & ((1 << b) - 1)).count("1")
