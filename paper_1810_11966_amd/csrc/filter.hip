@@ -57,11 +57,19 @@ constexpr int64_t kStepHits = (int64_t)kLaneHits * trig::kWave;
 typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
 
 // Station numbers of hits h0 .. h0 + 31 (h0 a multiple of 16 when vec) as 8
-// words of 4; 0xFF bytes where a hit is past the array (the caller masks
-// hits outside the event, so a padding byte never counts).
+// words of 4; 0xFF bytes where a hit is past the array, and for a lane whose
+// window holds no hit of the event [a, b) (not read: a step's lanes past the
+// event's end would otherwise fetch the next event's station numbers).  The
+// caller masks hits outside the event, so a padding byte never counts.
 struct LaneStations {
     uint32_t w[kLaneHits / 4];
-    __device__ __forceinline__ void load(const uint8_t* __restrict__ st, int64_t h0, int64_t n_hits, bool vec) {
+    __device__ __forceinline__ void load(const uint8_t* __restrict__ st, int64_t h0, int64_t a, int64_t b,
+                                         int64_t n_hits, bool vec) {
+        if (h0 >= b || h0 + kLaneHits <= a) {
+#pragma unroll
+            for (int q = 0; q < kLaneHits / 4; ++q) w[q] = 0xFFFFFFFFu;
+            return;
+        }
         if (vec && h0 + kLaneHits <= n_hits) {
             const u32x4 a = *reinterpret_cast<const u32x4*>(st + h0);
             const u32x4 b = *reinterpret_cast<const u32x4*>(st + h0 + 16);
@@ -227,7 +235,7 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_count(const int64_t* 
     if (k < kPer) {
         int64_t base = ra[k] & ~(int64_t)15;
         LaneStations cur, nxt;
-        cur.load(st, base + (int64_t)kLaneHits * lane, n_hits, vec != 0);
+        cur.load(st, base + (int64_t)kLaneHits * lane, ra[k], rb[k], n_hits, vec != 0);
         uint32_t c[3] = {0u, 0u, 0u};
         int32_t recs = 0;  // this event's records
         for (;;) {
@@ -240,7 +248,7 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_count(const int64_t* 
             }
             k1 = trig::uniform_i(k1);
             base1 = uniform64(base1);
-            if (k1 < kPer) nxt.load(st, base1 + (int64_t)kLaneHits * lane, n_hits, vec != 0);
+            if (k1 < kPer) nxt.load(st, base1 + (int64_t)kLaneHits * lane, ra[k1], rb[k1], n_hits, vec != 0);
             const int64_t h0 = base + (int64_t)kLaneHits * lane;
             // the lane's hits of event k: all of them unless the step
             // straddles an end of the event
@@ -513,10 +521,10 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
         const Range r = event_range(off, e, n_hits);
         int64_t base = r.a & ~(int64_t)15;
         LaneStations cur, nxt;
-        cur.load(st, base + (int64_t)kLaneHits * lane, n_hits, vec != 0);
+        cur.load(st, base + (int64_t)kLaneHits * lane, r.a, r.b, n_hits, vec != 0);
         for (; base < r.b; base += kStepHits) {
             const int64_t h0 = base + (int64_t)kLaneHits * lane;
-            if (base + kStepHits < r.b) nxt.load(st, h0 + kStepHits, n_hits, vec != 0);  // wave-uniform
+            if (base + kStepHits < r.b) nxt.load(st, h0 + kStepHits, r.a, r.b, n_hits, vec != 0);  // wave-uniform
             const LaneMatch m = match_lane(cur, h0, r.a, r.b, layers);
             cur = nxt;
             // Each matched hit's place in the step's list (layer 0's hits, then
