@@ -313,6 +313,28 @@ int trig_autotune(const trig_events_csr *ev, const trig_hits *hits, const trig_p
  * built-in rule again. */
 void trig_autotune_reset(void);
 
+/* Autotune cache file (host).  trig_autotune_save writes every recorded
+ * shape to the text file `path` (replacing it): a header line, then one line
+ * per record with the device's architecture name and compute-unit count,
+ * test, multiplicity class, form (batched or binned), block_hits,
+ * block_waves, block fill and block stealing.  trig_autotune_load reads such
+ * a file and records each line for every device of this process whose
+ * architecture name and compute-unit count match (replacing the shape held
+ * for that device, test and class); *n_recorded (may be NULL) receives the
+ * number of (line, device) pairs recorded, 0 on a machine without a match.
+ * The whole file is checked before anything is recorded.  Returns TRIG_OK,
+ * or TRIG_EINVAL for a NULL path, a file that cannot be opened, read or
+ * written, or a malformed line (detail in trig_last_error_detail). */
+int trig_autotune_save(const char *path);
+int trig_autotune_load(const char *path, int32_t *n_recorded);
+
+/* The shape recorded for the current device, `test` and multiplicity class
+ * (host).  *found = 1 and *out filled (block_events 0: it depends on the
+ * batch; n_candidates, ms_best and ms_rule 0) if there is one, else
+ * *found = 0.  Returns TRIG_OK, or TRIG_EINVAL for NULL pointers or a test
+ * or class out of range. */
+int trig_autotune_lookup(int32_t test, int32_t mult_class, int32_t *found, trig_autotune_result *out);
+
 /* Profiling hook (host, per calling thread): the following trig_select calls
  * of this thread record `start` immediately before and `stop` immediately
  * after the launch of their dominant kernel (the triplet kernel of the chosen

@@ -911,6 +911,20 @@ int current_device() {
     return d;
 }
 
+// A device as the autotune cache names it: architecture name and number of
+// compute units (a record made on one MI355X holds for another).
+bool device_key(int dev, std::string& key) {
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, dev) != hipSuccess) return false;
+    std::string arch(prop.gcnArchName);
+    for (char& ch : arch)
+        if (ch == ' ') ch = '_';
+    key = arch + "/" + std::to_string(prop.multiProcessorCount) + "cu";
+    return true;
+}
+
+constexpr const char* kCacheHeader = "trig-autotune-cache 1";
+
 // Effective parameters of a TRIG_EXEC_AUTOTUNE call: the recorded form and
 // shape of the batch's class, else the batched form with the built-in rule.
 // Block fields the caller set explicitly win over the record and select the
@@ -1044,6 +1058,116 @@ int trig_select(const trig_events_csr* ev, const trig_hits* hits, const trig_par
 void trig_autotune_reset(void) {
     std::lock_guard<std::mutex> lock(g_tune_mu);
     g_tuned.clear();
+}
+
+int trig_autotune_save(const char* path) {
+    if (!path) return fail(TRIG_EINVAL, "NULL path");
+    std::vector<std::string> lines;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        for (const auto& kv : g_tuned) {
+            std::string key;
+            if (!device_key(std::get<0>(kv.first), key)) return fail(TRIG_EHIP, "hipGetDeviceProperties failed");
+            const TunedShape& t = kv.second;
+            char buf[256];
+            std::snprintf(buf, sizeof buf, "%s %d %d %s %d %d %.17g %d", key.c_str(), std::get<1>(kv.first),
+                          std::get<2>(kv.first), t.binned ? "binned" : "batched", t.binned ? 0 : t.hb,
+                          t.binned ? 0 : t.nw, t.binned ? 0.0 : t.fill, t.persistent ? 1 : 0);
+            lines.push_back(buf);
+        }
+    }
+    FILE* f = std::fopen(path, "w");
+    if (!f) return fail(TRIG_EINVAL, std::string("cannot write ") + path);
+    bool ok = std::fprintf(f, "%s\n", kCacheHeader) > 0;
+    for (const auto& l : lines) ok = ok && std::fprintf(f, "%s\n", l.c_str()) > 0;
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok) return fail(TRIG_EINVAL, std::string("cannot write ") + path);
+    g_detail.clear();
+    return TRIG_OK;
+}
+
+int trig_autotune_load(const char* path, int32_t* n_recorded) {
+    if (!path) return fail(TRIG_EINVAL, "NULL path");
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(TRIG_EINVAL, std::string("cannot open ") + path);
+    struct Line {
+        std::string key;
+        int test, cls;
+        TunedShape t;
+    };
+    std::vector<Line> recs;
+    char buf[512];
+    int line_no = 0;
+    bool header = false;
+    std::string bad;
+    while (std::fgets(buf, sizeof buf, f)) {
+        ++line_no;
+        std::string line(buf);
+        while (!line.empty() && (line.back() == '\n' || line.back() == '\r')) line.pop_back();
+        if (!header) {
+            if (line != kCacheHeader) { bad = "not an autotune cache (header)"; break; }
+            header = true;
+            continue;
+        }
+        if (line.empty()) continue;
+        char key[256], form[16];
+        int test = -1, cls = -1, hb = -1, nw = -1, pers = -1;
+        double fill = -1.0;
+        char tail = 0;
+        const int n = std::sscanf(line.c_str(), "%255s %d %d %15s %d %d %lf %d %c", key, &test, &cls, form, &hb, &nw,
+                                  &fill, &pers, &tail);
+        const bool binned = std::strcmp(form, "binned") == 0;
+        const bool ok = n == 8 && test >= 0 && test <= 2 && cls >= 0 && cls <= 31 && (pers == 0 || pers == 1) &&
+                        (binned ? (hb == 0 && nw == 0 && fill == 0.0)
+                                : (std::strcmp(form, "batched") == 0 && (hb == 1024 || hb == 2048 || hb == 4096) &&
+                                   (nw == 1 || nw == 2 || nw == 4) && fill > 0.0 && fill <= 1.0));
+        if (!ok) { bad = "malformed line " + std::to_string(line_no); break; }
+        recs.push_back({key, test, cls, TunedShape{hb, nw, fill, pers == 1, binned}});
+    }
+    const bool read_error = std::ferror(f) != 0;
+    std::fclose(f);
+    if (read_error) return fail(TRIG_EINVAL, std::string("cannot read ") + path);
+    if (bad.empty() && !header) bad = "empty file";
+    if (!bad.empty()) return fail(TRIG_EINVAL, std::string(path) + ": " + bad);
+    int n_dev = 0;
+    if (hipGetDeviceCount(&n_dev) != hipSuccess) n_dev = 0;
+    std::vector<std::string> keys;
+    for (int d = 0; d < n_dev; ++d) {
+        std::string k;
+        keys.push_back(device_key(d, k) ? k : std::string());
+    }
+    int32_t n = 0;
+    {
+        std::lock_guard<std::mutex> lock(g_tune_mu);
+        for (const Line& r : recs)
+            for (int d = 0; d < n_dev; ++d)
+                if (!keys[d].empty() && keys[d] == r.key) {
+                    g_tuned[{d, r.test, r.cls}] = r.t;
+                    ++n;
+                }
+    }
+    if (n_recorded) *n_recorded = n;
+    g_detail.clear();
+    return TRIG_OK;
+}
+
+int trig_autotune_lookup(int32_t test, int32_t mult_class, int32_t* found, trig_autotune_result* out) {
+    if (!found || !out) return fail(TRIG_EINVAL, "NULL pointer");
+    if (test < 0 || test > 2 || mult_class < 0 || mult_class > 31) return fail(TRIG_EINVAL, "test or class out of range");
+    std::lock_guard<std::mutex> lock(g_tune_mu);
+    auto it = g_tuned.find({current_device(), test, mult_class});
+    *found = it != g_tuned.end();
+    *out = trig_autotune_result{};
+    out->mult_class = mult_class;
+    if (*found) {
+        const TunedShape& t = it->second;
+        out->block_hits = t.binned ? 0 : t.hb;
+        out->block_waves = t.binned ? 0 : t.nw;
+        out->persistent = t.persistent ? 1 : 0;
+        out->binned = t.binned ? 1 : 0;
+    }
+    g_detail.clear();
+    return TRIG_OK;
 }
 
 int trig_autotune(const trig_events_csr* ev, const trig_hits* hits, const trig_params* p,

@@ -50,7 +50,8 @@ FORMS = {
 
 # Every symbol include/trig.h declares.
 EXPORTED = ("trig_params_init", "trig_params_check", "trig_workspace_bytes", "trig_select", "trig_select_noalloc",
-            "trig_autotune", "trig_autotune_reset", "trig_set_kernel_events", "trig_strerror", "trig_last_error_detail", "trig_probe_valu",
+            "trig_autotune", "trig_autotune_reset", "trig_autotune_save", "trig_autotune_load",
+            "trig_autotune_lookup", "trig_set_kernel_events", "trig_strerror", "trig_last_error_detail", "trig_probe_valu",
             "trig_probe_copy", "trig_server_create", "trig_server_submit", "trig_server_poll",
             "trig_server_release", "trig_server_pause", "trig_server_stats_get", "trig_server_now", "trig_server_destroy",
             "trig_filter_workspace_bytes", "trig_filter_stations")
@@ -117,6 +118,13 @@ def load(path: str = LIB_PATH):
                                   ctypes.c_int32, ctypes.POINTER(TrigAutotuneResult), ctypes.c_void_p]
     lib.trig_autotune_reset.restype = None
     lib.trig_autotune_reset.argtypes = []
+    lib.trig_autotune_save.restype = ctypes.c_int
+    lib.trig_autotune_save.argtypes = [ctypes.c_char_p]
+    lib.trig_autotune_load.restype = ctypes.c_int
+    lib.trig_autotune_load.argtypes = [ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]
+    lib.trig_autotune_lookup.restype = ctypes.c_int
+    lib.trig_autotune_lookup.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                         ctypes.POINTER(TrigAutotuneResult)]
     lib.trig_set_kernel_events.restype = ctypes.c_int
     lib.trig_set_kernel_events.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     lib.trig_strerror.restype = ctypes.c_char_p
@@ -202,6 +210,36 @@ def trig_autotune(events: TrigEventsCsr, hits: TrigHits, params: TrigParams, out
 
 def trig_autotune_reset() -> None:
     load().trig_autotune_reset()
+
+
+def autotune_save(path: str) -> None:
+    """Write the recorded shapes to the cache file ``path``."""
+    rc = load().trig_autotune_save(str(path).encode())
+    if rc:
+        raise TrigError(rc, trig_last_error_detail())
+
+
+def autotune_load(path: str) -> int:
+    """Record the shapes of the cache file ``path`` for this process's
+    matching devices; returns the number recorded."""
+    n = ctypes.c_int32(0)
+    rc = load().trig_autotune_load(str(path).encode(), ctypes.byref(n))
+    if rc:
+        raise TrigError(rc, trig_last_error_detail())
+    return int(n.value)
+
+
+def autotune_lookup(test: str, mult_class: int):
+    """The shape recorded for the current device, test and class, or None."""
+    found = ctypes.c_int32(0)
+    res = TrigAutotuneResult()
+    rc = load().trig_autotune_lookup(TESTS[test], int(mult_class), ctypes.byref(found), ctypes.byref(res))
+    if rc:
+        raise TrigError(rc, trig_last_error_detail())
+    if not found.value:
+        return None
+    return {"block_hits": res.block_hits, "block_waves": res.block_waves, "persistent": res.persistent,
+            "binned": res.binned}
 
 
 def trig_set_kernel_events(start: int, stop: int) -> int:

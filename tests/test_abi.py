@@ -247,6 +247,56 @@ def test_autotune_argument_checks(lib):
     trig.trig_autotune_reset()
 
 
+def test_autotune_cache_file_errors_and_round_trip(tmp_path):
+    """trig_autotune_save / _load without a GPU: an empty table saves as the
+    header alone and loads back with nothing recorded; a well-formed record
+    for some device is read (and recorded only for a matching device, of
+    which there is none here); missing files, bad headers and malformed
+    lines are refused with TRIG_EINVAL before anything is recorded."""
+    trig.trig_autotune_reset()
+    f = tmp_path / "cache.txt"
+    trig.autotune_save(str(f))
+    assert f.read_text() == "trig-autotune-cache 1\n"
+    assert trig.autotune_load(str(f)) == 0
+    good = ("trig-autotune-cache 1\n"
+            "gfx950:sramecc+:xnack-/256cu 0 6 batched 2048 4 0.84999999999999998 0\n"
+            "gfx950:sramecc+:xnack-/256cu 0 9 binned 0 0 0 1\n\n")
+    f.write_text(good)
+    assert trig.autotune_load(str(f)) == 0  # no device of this process matches
+    bad_files = [
+        "",                                                           # empty
+        "trig-autotune-cache 2\n",                                    # header
+        good + "gfx950/256cu 0 6 batched 2048 4 0.85\n",              # missing field
+        good + "gfx950/256cu 3 6 batched 2048 4 0.85 0\n",            # test
+        good + "gfx950/256cu 0 32 batched 2048 4 0.85 0\n",           # class
+        good + "gfx950/256cu 0 6 batched 3000 4 0.85 0\n",            # block_hits
+        good + "gfx950/256cu 0 6 batched 2048 3 0.85 0\n",            # block_waves
+        good + "gfx950/256cu 0 6 batched 2048 4 1.5 0\n",             # fill
+        good + "gfx950/256cu 0 6 binned 2048 0 0 0\n",                # binned with a shape
+        good + "gfx950/256cu 0 6 batched 2048 4 0.85 2\n",            # stealing flag
+        good + "gfx950/256cu 0 6 batched 2048 4 0.85 0 extra\n",      # trailing field
+    ]
+    for text in bad_files:
+        f.write_text(text)
+        with pytest.raises(trig.TrigError) as e:
+            trig.autotune_load(str(f))
+        assert e.value.code == trig.TRIG_EINVAL, text
+    with pytest.raises(trig.TrigError):
+        trig.autotune_load(str(tmp_path / "missing.txt"))
+    with pytest.raises(trig.TrigError):
+        trig.autotune_save(str(tmp_path / "no_such_dir" / "c.txt"))
+    lib = trig.load()
+    assert lib.trig_autotune_save(None) == trig.TRIG_EINVAL
+    assert lib.trig_autotune_load(None, None) == trig.TRIG_EINVAL
+    found = ctypes.c_int32(7)
+    res = trig.TrigAutotuneResult()
+    assert lib.trig_autotune_lookup(0, 6, None, ctypes.byref(res)) == trig.TRIG_EINVAL
+    assert lib.trig_autotune_lookup(3, 6, ctypes.byref(found), ctypes.byref(res)) == trig.TRIG_EINVAL
+    assert lib.trig_autotune_lookup(0, 32, ctypes.byref(found), ctypes.byref(res)) == trig.TRIG_EINVAL
+    assert lib.trig_autotune_lookup(0, 6, ctypes.byref(found), ctypes.byref(res)) == trig.TRIG_OK
+    assert found.value == 0
+
+
 def test_lane_division_identity():
     """The batched kernel's lane division: floor(lane / n) = (lane *
     ceil(2^16 / n)) >> 16 for every lane < 64 and 1 <= n <= 64, with the

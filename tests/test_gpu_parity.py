@@ -492,6 +492,33 @@ def test_autotune_records_and_matches_oracle(gpu, test):
     assert_parity(gpu, s, test, "auto", "rule after reset")
 
 
+def test_autotune_cache_file_round_trip(gpu, tmp_path):
+    """A record made by trig_autotune survives trig_autotune_save, a reset
+    and trig_autotune_load: the same shape is recorded again for this
+    device, and autotuned calls with it match the oracle."""
+    from paper_1810_11966_amd import trig
+    trig.trig_autotune_reset()
+    s = synth.make_event_set(synth.SMALL_10K, n_events=4000)
+    off, x, y = to_dev(gpu, s)
+    print(f"[autotune cache] events={s.n_events}", flush=True)
+    _, info = trig.autotune(off, x, y, test="msd", reps=1)
+    gpu.cuda.synchronize()
+    rec = trig.autotune_lookup("msd", info.mult_class)
+    assert rec is not None and rec["binned"] == info.binned and rec["persistent"] == info.persistent
+    if not info.binned:
+        assert (rec["block_hits"], rec["block_waves"]) == (info.block_hits, info.block_waves)
+    path = tmp_path / "autotune.txt"
+    trig.autotune_save(str(path))
+    lines = path.read_text().splitlines()
+    assert lines[0] == "trig-autotune-cache 1" and len(lines) == 2
+    trig.trig_autotune_reset()
+    assert trig.autotune_lookup("msd", info.mult_class) is None
+    assert trig.autotune_load(str(path)) >= 1
+    assert trig.autotune_lookup("msd", info.mult_class) == rec
+    assert_parity(gpu, s, "msd", "auto", "autotuned from the cache file")
+    trig.trig_autotune_reset()
+
+
 # ---------------------------------------- two particles, decision only ---
 
 def two_particle_oracle(s, test, **kw):
