@@ -390,7 +390,7 @@ def filter_leg(n_events, reps=20, seed=0):
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record()
     for _ in range(reps):
-        F.filter_stations(*t, raw.layers, base.n_hits, workspace=ws)
+        F.filter_stations(*t, raw.layers, base.n_hits, workspace=ws, out=r)  # outputs reused: only the kernels
     b.record()
     torch.cuda.synchronize()
     ms = a.elapsed_time(b) / reps
@@ -404,6 +404,50 @@ def filter_leg(n_events, reps=20, seed=0):
             "roofline": {"kernel": "k_filter_count + k_filter_scan + k_filter_scatter", "bound": "hbm",
                          "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
                          "algorithmic_bytes": nbytes}}
+
+
+def events_leg(n_events, reps=20, seed=0, gap_ns=5):
+    """Event building (include/trig_events.h) on a free-streaming timeslice:
+    the filter leg's kind of events (about 5000 hits on 16 stations) as
+    interactions at Poisson times of 10 MHz, each hit at its interaction's
+    time plus U{0..10} ns, ordered by time; built with a 5 ns gap (pile up
+    merges some interactions).  The time of one call (three kernels),
+    bit-exact against the oracle's whole-array definition, and HBM bytes
+    per call (8 B per hit of times, 8 B per event of offsets) against 8 TB/s."""
+    import torch
+    from oracle import reference as R
+    from paper_1810_11966_amd import events as EB
+    from paper_1810_11966_amd import synth
+    base = synth.make_event_set(synth.MEDIUM_1M, n_events=n_events)
+    raw = synth.embed_raw(base, other_mean=378.0, shuffle=False, square=True, seed=seed)
+    s = synth.free_stream(raw, rate_hz=1e7, spread_ns=10, seed=seed)
+    want, wst = R.build_events_numpy(s.t, gap_ns)
+    d = torch.device("cuda:0")
+    t = torch.from_numpy(s.t).to(d)
+    ws = torch.empty(EB.workspace_bytes(s.n_hits) + 256, dtype=torch.uint8, device=d)
+    r = None
+    for _ in range(3):
+        r = EB.build_events(t, gap_ns, workspace=ws)
+    torch.cuda.synchronize()
+    n_ev = int(r.n_events.cpu().numpy()[0])
+    if not (n_ev == len(want) - 1 and np.array_equal(r.offsets[:n_ev + 1].cpu().numpy(), want)
+            and int(r.status.cpu()[0]) == wst):
+        print("bench.py: event building differs from the oracle", file=sys.stderr)
+        sys.exit(1)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        EB.build_events(t, gap_ns, workspace=ws, out=r)  # outputs reused: only the library's kernels
+    b.record()
+    torch.cuda.synchronize()
+    ms = a.elapsed_time(b) / reps
+    nbytes = 8 * s.n_hits + 8 * (n_ev + 1) + 8
+    gbs = nbytes / (ms * 1e-3) / 1e9
+    return {"workload": f"{raw.n_events} interactions at 10 MHz, {s.n_hits} hits ({s.n_hits / raw.n_events:.0f} "
+                        f"per interaction, 10 ns time spread), gap {gap_ns} ns: {n_ev} events built",
+            "ms": ms, "hits_per_s": s.n_hits / (ms * 1e-3), "events_per_s": n_ev / (ms * 1e-3), "bit_exact": True,
+            "roofline": {"kernel": "k_eb_count + k_scan_i64 + k_eb_scatter", "bound": "hbm", "achieved": gbs,
+                         "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0, "algorithmic_bytes": nbytes}}
 
 
 def main():
@@ -522,6 +566,13 @@ def main():
         log(f"[bench] filter: {filt['ms']:.3f} ms, {filt['events_per_s']:.4g} events/s, "
             f"{filt['roofline']['achieved']:.0f} GB/s")
 
+    building = None
+    if args.filter_events > 0 and not args.only_form:
+        log(f"[bench] event building leg: {args.filter_events // 5} interactions")
+        building = events_leg(args.filter_events // 5)
+        log(f"[bench] event building: {building['ms']:.3f} ms, {building['hits_per_s']:.4g} hits/s, "
+            f"{building['roofline']['achieved']:.0f} GB/s")
+
     probes = None
     if not args.only_form:
         from paper_1810_11966_amd import probe
@@ -568,6 +619,7 @@ def main():
         "p99_slice_latency_ms": serving["p99_ms"] if serving else None,
         "serving": serving,
         "station_filter": filt,
+        "event_building": building,
         "two_particles": two,
         "per_hit_z": hz,
         "device_probes": probes,

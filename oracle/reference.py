@@ -26,6 +26,10 @@ Contents
   * ``filter_stations``          trigger-station filtering, the step before the
                                  selection: per event the hits of the three
                                  trigger layers, in input order.
+  * ``build_events``             event building from a time-ordered stream
+                                 (time-gap clustering), the step before the
+                                 filter; ``build_events_numpy`` the same over
+                                 whole arrays.
 
 The fp32 decision contract, MSD test (default): the fit of Sec. 3.2 step 2
 written out, per plane c in {x, y} with the hits c_i, c_j, c_k of layers 0, 1,
@@ -476,3 +480,42 @@ def filter_stations(offsets, station, x, y, layers):
     cat = (lambda parts: np.concatenate(parts).astype(np.float32) if parts else np.zeros(0, np.float32))
     return np.asarray(starts, dtype=np.int64).astype(np.int32), cat(xs), cat(ys), status
 
+
+def build_events(t, gap):
+    """Event building from a time-ordered hit stream (the paper's outlook,
+    Sec. 8: free-streaming data, hits with times and no hardware trigger; it
+    gives no algorithm).  Reading: time-gap clustering.  Written from its
+    definition, hit by hit: a new event starts at the first hit and at every
+    hit whose time exceeds the previous hit's by more than gap (times are
+    Python integers here, so the difference is exact); a hit whose time is
+    below the previous hit's sets status bit 1 and starts no event.
+
+    Returns (offsets int64[E+1] over the stream's order, status)."""
+    t = [int(v) for v in np.asarray(t, dtype=np.int64)]
+    gap = int(gap)
+    starts, status = [], 0
+    for h, th in enumerate(t):
+        if h == 0:
+            starts.append(0)
+            continue
+        if th < t[h - 1]:
+            status |= 1
+        elif th - t[h - 1] > gap:
+            starts.append(h)
+    offsets = starts + [len(t)] if t else [0]
+    return np.asarray(offsets, dtype=np.int64), status
+
+
+def build_events_numpy(t, gap):
+    """build_events with numpy over whole arrays (same definition; for the
+    full-size checks): the unsigned 64-bit difference of two int64 times is
+    the true difference whenever the later time is the larger one."""
+    t = np.asarray(t, dtype=np.int64)
+    if len(t) == 0:
+        return np.zeros(1, np.int64), 0
+    up = t[1:] > t[:-1]
+    diff = t[1:].view(np.uint64) - t[:-1].view(np.uint64)
+    new = up & (diff > np.uint64(gap))
+    status = 1 if bool((t[1:] < t[:-1]).any()) else 0
+    offsets = np.concatenate([[0], np.flatnonzero(new) + 1, [len(t)]]).astype(np.int64)
+    return offsets, status

@@ -23,11 +23,12 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libtrig.so")
 ISA = os.path.join(ROOT, "_build", "trig-gfx950.s")
 SOURCES = [os.path.join(CSRC, "trig.hip"), os.path.join(CSRC, "probe.hip"), os.path.join(CSRC, "serve.hip"),
-           os.path.join(CSRC, "filter.hip")]
+           os.path.join(CSRC, "filter.hip"), os.path.join(CSRC, "events.hip")]
 HEADERS = [os.path.join(CSRC, "trig_device.hpp"), os.path.join(CSRC, "trig_block.hpp"),
            os.path.join(CSRC, "serve_core.hpp"), os.path.join(INCLUDE, "trig.h"),
            os.path.join(INCLUDE, "trig_probe.h"), os.path.join(INCLUDE, "trig_serve.h"),
-           os.path.join(INCLUDE, "trig_filter.h")]
+           os.path.join(INCLUDE, "trig_filter.h"), os.path.join(INCLUDE, "trig_events.h"),
+           os.path.join(CSRC, "scan_i64.hpp")]
 ARCH = "gfx950"
 
 COMMON = ["-std=c++17", "-O3", f"--offload-arch={ARCH}", "-ffp-contract=off",

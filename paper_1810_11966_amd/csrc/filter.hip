@@ -29,6 +29,7 @@
 #include "trig.h"
 #include "trig_device.hpp"
 #include "trig_filter.h"
+#include "scan_i64.hpp"
 
 namespace {
 
@@ -304,44 +305,6 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_count(const int64_t* 
     }
 }
 
-// In-place exclusive scan of partials[0..n) (int64); partials[n] = total.
-// One workgroup of kScanThreads: thread t sums its run of ceil(n / threads)
-// consecutive partials (loads of a run issued together), one block scan of
-// those sums (Hillis-Steele in LDS), then each thread rewrites its run from
-// its prefix.
-constexpr int kScanThreads = 1024;
-constexpr int kScanUnroll = 8;
-
-__global__ __launch_bounds__(kScanThreads) void k_filter_scan(int64_t* partials, int n) {
-    __shared__ int64_t buf[kScanThreads];
-    const int t = (int)threadIdx.x;
-    const int per = (n + kScanThreads - 1) / kScanThreads;
-    const int lo = min(n, t * per), hi = min(n, lo + per);
-    int64_t sum = 0;
-    for (int i0 = lo; i0 < hi; i0 += kScanUnroll) {
-        int64_t v[kScanUnroll];
-#pragma unroll
-        for (int u = 0; u < kScanUnroll; ++u) v[u] = i0 + u < hi ? partials[i0 + u] : 0;
-#pragma unroll
-        for (int u = 0; u < kScanUnroll; ++u) sum += v[u];
-    }
-    buf[t] = sum;
-    __syncthreads();
-    for (int d = 1; d < kScanThreads; d <<= 1) {  // inclusive
-        const int64_t o = t >= d ? buf[t - d] : 0;
-        __syncthreads();
-        buf[t] += o;
-        __syncthreads();
-    }
-    int64_t run = buf[t] - sum;  // exclusive prefix of this run
-    for (int i = lo; i < hi; ++i) {
-        const int64_t v = partials[i];
-        partials[i] = run;
-        run += v;
-    }
-    if (t == kScanThreads - 1) partials[n] = buf[t];
-}
-
 // Per-event data of the scatter's workgroup, in LDS.
 struct ScatterEvent {
     int64_t s[3];   // first output position of the event's layer-l hits
@@ -609,7 +572,7 @@ int trig_filter_stations(const trig_raw_events* ev, const trig_filter_params* p,
     hipLaunchKernelGGL(k_filter_count, dim3(nb), dim3(kFilterThreads), 0, s, ev->offsets, n, ev->n_hits,
                        ev->station, layers, vec, counts, partials, wave_recs, ev_recs, p->out_status);
     if (hipGetLastError() != hipSuccess) return TRIG_EHIP;
-    hipLaunchKernelGGL(k_filter_scan, dim3(1), dim3(kScanThreads), 0, s, partials, nb);
+    hipLaunchKernelGGL(k_scan_i64, dim3(1), dim3(kScanThreads), 0, s, partials, (int64_t)nb);
     if (hipGetLastError() != hipSuccess) return TRIG_EHIP;
     hipLaunchKernelGGL(k_filter_scatter, dim3(nb), dim3(kFilterThreads), 0, s, ev->offsets, n, ev->n_hits,
                        ev->station, ev->x, ev->y, layers, vec, counts, partials, wave_recs, ev_recs, nb, p->out_capacity,

@@ -54,21 +54,31 @@ class FilterResult:
 
 
 def filter_stations(offsets, station, x, y, layers: Sequence[int], capacity: int,
-                    stream: Optional[int] = None, workspace=None) -> FilterResult:
+                    stream: Optional[int] = None, workspace=None,
+                    out: Optional[FilterResult] = None) -> FilterResult:
     """offsets int64[E+1], station uint8[H], x/y fp32[H] (cuda tensors);
     layers: the three trigger station numbers; capacity: length of the x/y
-    outputs (at least the number of trigger hits)."""
+    outputs (at least the number of trigger hits).  ``out``: a previous
+    result for the same batch whose tensors are written again (its status
+    keeps its bits: they are OR-ed in)."""
     import torch
 
     dev = offsets.device
     n = offsets.numel() - 1
     ev = TrigRawEvents(n, offsets.data_ptr(), station.numel(), station.data_ptr() if station.numel() else None,
                        x.data_ptr() if x.numel() else None, y.data_ptr() if y.numel() else None)
-    out_off = torch.empty(3 * n + 1, dtype=torch.int32, device=dev)
     cap = int(capacity)
-    out_x = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
-    out_y = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
-    status = torch.zeros(1, dtype=torch.int32, device=dev)
+    if out is not None:
+        out_off, out_x, out_y, status = out.layer_offsets, out.x, out.y, out.status
+        if out_off.numel() != 3 * n + 1 or out_x.numel() < max(cap, 1):
+            raise ValueError("out does not fit this batch")
+        if workspace is None:
+            workspace = out.workspace
+    else:
+        out_off = torch.empty(3 * n + 1, dtype=torch.int32, device=dev)
+        out_x = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+        out_y = torch.empty(max(cap, 1), dtype=torch.float32, device=dev)
+        status = torch.zeros(1, dtype=torch.int32, device=dev)
     need = workspace_bytes(n)
     if workspace is None:
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)

@@ -364,3 +364,44 @@ def embed_raw(base: EventSet, other_mean: float = 30.0, shuffle: bool = True, se
         x[sel] = base.x[base_layer == l]
         y[sel] = base.y[base_layer == l]
     return RawEventSet(offsets, station, x, y, tuple(layers))
+
+
+@dataclass
+class HitStream:
+    """A free-streaming timeslice (input of event building): int64 times t[H]
+    in non-decreasing order, with each hit's station number and x, y, and the
+    generating event of each hit (int64 event[H], for tests)."""
+    t: np.ndarray
+    station: np.ndarray
+    x: np.ndarray
+    y: np.ndarray
+    event: np.ndarray
+
+    @property
+    def n_hits(self) -> int:
+        return int(len(self.t))
+
+
+def free_stream(raw: RawEventSet, rate_hz: float = 1e7, spread_ns: int = 10, min_spacing_ns: int = 0,
+                seed: int = 0, t0: int = 0) -> HitStream:
+    """The events of ``raw`` as a free-streaming timeslice: interactions at
+    Poisson times (rate ``rate_hz``, integer nanoseconds from ``t0``, each
+    at least ``min_spacing_ns`` after the previous one), every hit at its
+    interaction's time plus U{0..spread_ns} ns, and the whole stream ordered
+    by time (a stable sort, so hits of one event at the same time keep their
+    order).  With min_spacing_ns > spread_ns + gap the events do not mix,
+    and building events with that gap gives back ``raw``'s events."""
+    rng = np.random.default_rng(np.random.SeedSequence([seed, 0x7153]))
+    n = raw.n_events
+    dt = np.rint(rng.exponential(1e9 / rate_hz, n)).astype(np.int64) + int(min_spacing_ns)
+    dt[0] = 0
+    t_event = int(t0) + np.cumsum(dt)
+    per = np.diff(raw.offsets.astype(np.int64))
+    event = np.repeat(np.arange(n, dtype=np.int64), per)
+    t = t_event[event] + rng.integers(0, int(spread_ns) + 1, raw.n_hits, dtype=np.int64)
+    if min_spacing_ns > spread_ns:
+        # events do not overlap: ordering each event's hits is enough
+        order = np.lexsort((t, event))
+    else:
+        order = np.argsort(t, kind="stable")
+    return HitStream(t[order], raw.station[order], raw.x[order], raw.y[order], event[order])

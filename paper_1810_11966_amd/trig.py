@@ -54,7 +54,8 @@ EXPORTED = ("trig_params_init", "trig_params_check", "trig_workspace_bytes", "tr
             "trig_autotune_lookup", "trig_set_kernel_events", "trig_strerror", "trig_last_error_detail", "trig_probe_valu",
             "trig_probe_copy", "trig_server_create", "trig_server_submit", "trig_server_poll",
             "trig_server_release", "trig_server_pause", "trig_server_stats_get", "trig_server_now", "trig_server_destroy",
-            "trig_filter_workspace_bytes", "trig_filter_stations")
+            "trig_filter_workspace_bytes", "trig_filter_stations", "trig_build_events_workspace_bytes",
+            "trig_build_events")
 
 
 class TrigEventsCsr(ctypes.Structure):

@@ -12,7 +12,8 @@ import pytest
 from paper_1810_11966_amd import build, trig
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADERS = [os.path.join(ROOT, "include", h) for h in ("trig.h", "trig_probe.h", "trig_serve.h", "trig_filter.h")]
+HEADERS = [os.path.join(ROOT, "include", h)
+           for h in ("trig.h", "trig_probe.h", "trig_serve.h", "trig_filter.h", "trig_events.h")]
 
 
 @pytest.fixture(scope="module")
