@@ -375,11 +375,17 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
         Range r{0, 0, false};
         const bool mine = j < kFilterEvents && j % kFilterWaves == w;
         if (in) {
-            c[0] = counts[3 * (int64_t)e];
-            c[1] = counts[3 * (int64_t)e + 1];
-            c[2] = counts[3 * (int64_t)e + 2];
+            // every load first (one round trip), then their uses
+            const int64_t oa = off[e], ob = off[e + 1];
+            const int32_t c0 = counts[3 * (int64_t)e], c1 = counts[3 * (int64_t)e + 1];
+            const int32_t c2 = counts[3 * (int64_t)e + 2];
             nr = ev_recs[e];
-            if (mine) r = event_range(off, e, n_hits);
+            c[0] = c0;
+            c[1] = c1;
+            c[2] = c2;
+            r.a = oa;
+            r.b = ob;
+            r.ok = 0 <= oa && oa <= ob && ob <= n_hits && ob - oa <= (int64_t)INT32_MAX;
         }
         if (j < kFilterEvents) {
             cnt[j][0] = c[0];
@@ -451,23 +457,42 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
             const int32_t nc = min(trig::kWave, n_rec - cb);
             const int half = lane >> 5, b = lane & 31;
             const uint32_t bit = 1u << tpos(b), below = tupto(b);  // hit b, hits before b
-#pragma unroll 4
-            for (int32_t q = 0; q < nc; q += 2) {
-                const int32_t k = q + half;
-                if (k < nc) {
-                    const ScatterRec& u = rl[k];
-                    const uint32_t m0 = u.m[0], m1 = u.m[1], m2 = u.m[2];
-                    if ((m0 | m1 | m2) & bit) {
-                        const int l = (m0 & bit) ? 0 : ((m1 & bit) ? 1 : 2);
-                        const uint32_t ml = l == 0 ? m0 : (l == 1 ? m1 : m2);
-                        const int64_t p = u.base[l] + __builtin_popcount(ml & below);
-                        if (p >= 0 && p < cap) {  // positions past an int32 block prefix are never written
-                            const int64_t h = u.h0 + b;
-                            out_x[p] = x[h];
-                            out_y[p] = y[h];
+            // kRoundBatch rounds at a time: every lane's loads of the batch go
+            // out together (a lane without a hit to move reads hit 0), then
+            // the stores, so that a batch costs one round trip
+            constexpr int kRoundBatch = 4;
+            for (int32_t q0 = 0; q0 < nc; q0 += 2 * kRoundBatch) {
+                float vx[kRoundBatch], vy[kRoundBatch];
+                int64_t pos[kRoundBatch];
+                bool put[kRoundBatch];
+#pragma unroll
+                for (int r = 0; r < kRoundBatch; ++r) {
+                    const int32_t k = q0 + 2 * r + half;
+                    int64_t p = 0, h = 0;
+                    bool ok = false;
+                    if (k < nc) {
+                        const ScatterRec& u = rl[k];
+                        const uint32_t m0 = u.m[0], m1 = u.m[1], m2 = u.m[2];
+                        if ((m0 | m1 | m2) & bit) {
+                            const int l = (m0 & bit) ? 0 : ((m1 & bit) ? 1 : 2);
+                            const uint32_t ml = l == 0 ? m0 : (l == 1 ? m1 : m2);
+                            p = u.base[l] + __builtin_popcount(ml & below);
+                            h = u.h0 + b;
+                            ok = p >= 0 && p < cap;  // positions past an int32 block prefix are never written
                         }
                     }
+                    const int64_t hh = ok ? h : 0;  // a record exists, so n_hits > 0
+                    vx[r] = x[hh];
+                    vy[r] = y[hh];
+                    pos[r] = p;
+                    put[r] = ok;
                 }
+#pragma unroll
+                for (int r = 0; r < kRoundBatch; ++r)
+                    if (put[r]) {
+                        out_x[pos[r]] = vx[r];
+                        out_y[pos[r]] = vy[r];
+                    }
             }
             trig::wave_lds_sync();  // the next chunk rewrites rl
         }
