@@ -460,7 +460,7 @@ __global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
             // kRoundBatch rounds at a time: every lane's loads of the batch go
             // out together (a lane without a hit to move reads hit 0), then
             // the stores, so that a batch costs one round trip
-            constexpr int kRoundBatch = 4;
+            constexpr int kRoundBatch = 8;
             for (int32_t q0 = 0; q0 < nc; q0 += 2 * kRoundBatch) {
                 float vx[kRoundBatch], vy[kRoundBatch];
                 int64_t pos[kRoundBatch];

@@ -67,9 +67,19 @@ def build_events(t, gap: int, capacity: Optional[int] = None, stream: Optional[i
     addr = workspace.data_ptr()
     aligned = (addr + 255) & ~255
     s = stream if stream is not None else torch.cuda.current_stream(dev).cuda_stream
-    rc = _lib().trig_build_events(t.data_ptr() if n else None, n, int(gap), offsets.data_ptr(), cap,
-                                  n_events.data_ptr(), status.data_ptr(), aligned,
-                                  workspace.numel() - (aligned - addr), s)
+    args = (t.data_ptr() if n else None, n, int(gap), offsets.data_ptr(), cap, n_events.data_ptr(),
+            status.data_ptr(), aligned, workspace.numel() - (aligned - addr), s)
+    rc = _lib().trig_build_events(*args)
     if rc:
         raise trig.TrigError(rc, "trig_build_events")
-    return BuildResult(offsets, n_events, status, workspace)
+    res = BuildResult(offsets, n_events, status, workspace)
+    res._args = args  # the marshalled arguments, for repeat()
+    return res
+
+
+def repeat(res: BuildResult) -> None:
+    """Run the call that produced ``res`` again on the same tensors (its
+    arguments marshalled once: for timing loops)."""
+    rc = _lib().trig_build_events(*res._args)
+    if rc:
+        raise trig.TrigError(rc, "trig_build_events")

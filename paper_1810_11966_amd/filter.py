@@ -97,4 +97,15 @@ def filter_stations(offsets, station, x, y, layers: Sequence[int], capacity: int
     rc = _lib().trig_filter_stations(ctypes.byref(ev), ctypes.byref(p), s)
     if rc:
         raise trig.TrigError(rc, "trig_filter_stations")
-    return FilterResult(out_off, out_x, out_y, status, workspace)
+    res = FilterResult(out_off, out_x, out_y, status, workspace)
+    res._call = (ev, p, s)  # the marshalled arguments, for repeat()
+    return res
+
+
+def repeat(res: FilterResult) -> None:
+    """Run the call that produced ``res`` again on the same tensors (its
+    arguments marshalled once: for timing loops)."""
+    ev, p, s = res._call
+    rc = _lib().trig_filter_stations(ctypes.byref(ev), ctypes.byref(p), s)
+    if rc:
+        raise trig.TrigError(rc, "trig_filter_stations")
