@@ -420,7 +420,7 @@ def filter_leg(n_events, reps=20, seed=0):
     return {"workload": f"{raw.n_events} events, {raw.n_hits} hits on 16 stations in detector order "
                         f"({raw.n_hits / raw.n_events:.0f} per event), {base.n_hits} of them on the trigger layers",
             "ms": ms, "events_per_s": raw.n_events / (ms * 1e-3), "bit_exact": True,
-            "roofline": {"kernel": "k_filter_count + k_filter_scan + k_filter_scatter", "bound": "hbm",
+            "roofline": {"kernel": "k_filter_count + k_scan_i64 + k_filter_scatter", "bound": "hbm",
                          "achieved": gbs, "peak": 8000.0, "unit": "GB/s", "frac": gbs / 8000.0,
                          "algorithmic_bytes": nbytes}}
 

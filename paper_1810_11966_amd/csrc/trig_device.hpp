@@ -75,14 +75,14 @@ __device__ __forceinline__ float select_uniform(int cond, float a, float b) {
 
 __device__ __forceinline__ unsigned lane_id() { return threadIdx.x & (kWave - 1); }
 
-// Order this wave's LDS writes before its later LDS reads (and keep the
-// compiler from moving memory operations across).  Within one wave only the
-// LDS counter has to drain (s_waitcnt lgkmcnt(0); vmcnt and expcnt left at
-// their maxima, the gfx9 encoding): global loads in flight, such as the next
-// block's prefetch, keep flying.  A workgroup fence would wait for those too.
+// Order this wave's LDS writes before its later LDS reads, and its reads
+// before later writes, across lanes of the wave.  The LDS performs one
+// wave's operations in issue order, so nothing has to drain (no s_waitcnt:
+// the LDS counter only orders LDS against other memory and other waves);
+// only the compiler must be kept from moving memory operations across.
+// Global loads in flight, such as the next block's prefetch, keep flying.
 __device__ __forceinline__ void wave_lds_sync() {
     asm volatile("" ::: "memory");
-    __builtin_amdgcn_s_waitcnt(0xC07F);
     __builtin_amdgcn_wave_barrier();
     asm volatile("" ::: "memory");
 }
