@@ -55,20 +55,11 @@ __device__ __forceinline__ int div_small(int a, int n) {
 // floor(lane / n) for 0 <= lane < 64 and 1 <= n <= 64: (lane * r) >> 16 with
 // r = ceil(2^16 / n) (a 24-bit multiply and a shift).  With r n = 2^16 + d,
 // 0 <= d < n, the product is 2^16 lane / n + lane d / n, and lane d / n < 64
-// < 2^16 / n, which never reaches the next multiple of 2^16 / n.  The
-// table is read with a scalar load (n is wave-uniform).
-struct Recip16Table {
-    uint32_t r[kWave + 1];
-    constexpr Recip16Table() : r() {
-        for (int n = 1; n <= kWave; ++n) r[n] = (65536u + (uint32_t)n - 1u) / (uint32_t)n;
-    }
-};
-__constant__ constexpr Recip16Table kRecip16{};
-
-__device__ __forceinline__ int div_lane(int lane, int n) {
-    const uint32_t r = kRecip16.r[uniform_i(n)];
-    return (int)(__umul24((unsigned)lane, r) >> 16);
-}
+// < 2^16 / n, which never reaches the next multiple of 2^16 / n.  r is
+// computed once per event in the descriptor pass (recip16) and travels with
+// the event's descriptor.
+__device__ __forceinline__ uint32_t recip16(int n) { return (65536u + (uint32_t)n - 1u) / (uint32_t)n; }
+__device__ __forceinline__ int div_lane(int lane, uint32_t r) { return (int)(__umul24((unsigned)lane, r) >> 16); }
 
 // Hits of the current sub-block in LDS (structure of arrays), indexed
 // relative to the staged range's 4-aligned start.
@@ -624,12 +615,12 @@ __device__ uint32_t wave_event_pruned(const Consts& c, const PairBounds& pb, con
 // not change a count.
 template <class P, class H>
 __device__ __forceinline__ void fast_setup(const Consts& c, const H& hits, int oB, int nB, int oL, int nL, int S,
-                                           int R, int T, float* __restrict__ px, float* __restrict__ py, int& g,
-                                           int& j, float2& q) {
+                                           int R, int T, uint32_t r, float* __restrict__ px, float* __restrict__ py,
+                                           int& g, int& j, float2& q) {
     const int lane = (int)lane_id();
-    // floor(lane / nL) for every R: with R = 1 (nL > 32) lanes past nL get
-    // g = 1 and no hit
-    g = div_lane(lane, nL);
+    // floor(lane / nL) for every R (r = recip16(nL)): with R = 1 (nL > 32)
+    // lanes past nL get g = 1 and no hit
+    g = div_lane(lane, r);
     j = lane - g * nL;
     const bool jv = (g < R) && (j < nL);
     if (!jv) g = 0;
@@ -692,13 +683,13 @@ __device__ uint32_t fast_exact(const Consts& c, const PairBounds& pb, const H& h
 // vote.  R, T and S come from the per-event descriptor (event_layout).
 template <class P, class H>
 __device__ uint32_t wave_event_fast(const Consts& c, const PairBounds& pb, const H& hits, int o0, int n0, int o1,
-                                    int n1, int o2, int n2, int R, int T, int S, float* __restrict__ px,
-                                    float* __restrict__ py) {
+                                    int n1, int o2, int n2, int R, int T, int S, uint32_t r,
+                                    float* __restrict__ px, float* __restrict__ py) {
     const int oB = S ? o1 : o0, nB = S ? n1 : n0;
     const int oL = S ? o0 : o1, nL = S ? n0 : n1;
     int g, j;
     float2 q;
-    fast_setup<P>(c, hits, oB, nB, oL, nL, S, R, T, px, py, g, j, q);
+    fast_setup<P>(c, hits, oB, nB, oL, nL, S, R, T, r, px, py, g, j, q);
     wave_lds_sync();
     const float4* ppx = reinterpret_cast<const float4*>(px + g * T);
     const float4* ppy = reinterpret_cast<const float4*>(py + g * T);
@@ -846,7 +837,8 @@ struct BlockLds {
     // Event descriptors, 13-bit fields (local hit indices < HB + 8 <= 4104,
     // layer sizes <= HB <= 4096): da = o0 | n0 << 13 | R << 26 (R <= 16) |
     // S << 31, db = o1 | n1 << 13 | (T / 4) << 26 (T <= 64), dc = o2 | n2 << 13.
-    uint32_t da[kMaxEB], db[kMaxEB], dc[kMaxEB];
+    // dr = recip16 of the lane layer's size (fast-path events only).
+    uint32_t da[kMaxEB], db[kMaxEB], dc[kMaxEB], dr[kMaxEB];
     int32_t soff[3 * kMaxEB + 1];
     int32_t sres[kMaxEB];
     float wmag[NW];  // per wave: largest |x|, |y| it staged (TRIG_TEST_MSD bounds)
@@ -912,6 +904,7 @@ __device__ void block_descriptors(BlockLds<HB, NW>& L, int cur, int nsub, int a0
                    ((uint32_t)S << 31);
         L.db[te] = (uint32_t)(b1 - a0) | ((uint32_t)n1 << 13) | ((uint32_t)(T >> 2) << 26);
         L.dc[te] = (uint32_t)(b2 - a0) | ((uint32_t)n2 << 13);
+        L.dr[te] = T > 0 ? recip16(S ? n0 : n1) : 0u;
         L.sres[te] = res;
     }
     __syncthreads();
@@ -947,6 +940,7 @@ __device__ __forceinline__ void block_check_describe(BlockLds<HB, NW>& L, const 
                    ((uint32_t)S << 31);
         L.db[te] = (uint32_t)(b1 - a0) | ((uint32_t)n1 << 13) | ((uint32_t)(T >> 2) << 26);
         L.dc[te] = (uint32_t)(b2 - a0) | ((uint32_t)n2 << 13);
+        L.dr[te] = T > 0 ? recip16(S ? n0 : n1) : 0u;
         L.sres[te] = res;
     }
 }
@@ -965,17 +959,33 @@ __device__ void block_count(BlockLds<HB, NW>& L, const Consts& c, int e_first, i
     float M = 0.0f;
     if constexpr (P::kMag) M = block_mag(L);
     const PairBounds pb = P::bounds(c, M);
+    // The wave's next descriptor is read while the current event is
+    // counted (its LDS round trip off the per-event chain).
+    uint32_t nda = 0u, ndb = 0u, ndc = 0u, ndr = 0u;
+    if (w < nsub) {
+        nda = L.da[w];
+        ndb = L.db[w];
+        ndc = L.dc[w];
+        ndr = L.dr[w];
+    }
     for (int te = w; te < nsub; te += NW) {
-        const uint32_t da = (uint32_t)uniform_i((int)L.da[te]);
-        const uint32_t db = (uint32_t)uniform_i((int)L.db[te]);
-        const uint32_t dc = (uint32_t)uniform_i((int)L.dc[te]);
+        const uint32_t da = (uint32_t)uniform_i((int)nda);
+        const uint32_t db = (uint32_t)uniform_i((int)ndb);
+        const uint32_t dc = (uint32_t)uniform_i((int)ndc);
+        const uint32_t dr = (uint32_t)uniform_i((int)ndr);
+        if (te + NW < nsub) {
+            nda = L.da[te + NW];
+            ndb = L.db[te + NW];
+            ndc = L.dc[te + NW];
+            ndr = L.dr[te + NW];
+        }
         constexpr uint32_t kF = (1u << 13) - 1;
         const int o0 = (int)(da & kF), n0 = (int)((da >> 13) & kF), R = (int)((da >> 26) & 31u);
         const int S = (int)(da >> 31);
         const int o1 = (int)(db & kF), n1 = (int)((db >> 13) & kF), T = (int)(db >> 26) * 4;
         const int o2 = (int)(dc & kF), n2 = (int)((dc >> 13) & kF);
         if (R == 0) continue;  // decided in the descriptor pass
-        const uint32_t cnt = T > 0 ? wave_event_fast<P>(c, pb, lh, o0, n0, o1, n1, o2, n2, R, T, S, px, py)
+        const uint32_t cnt = T > 0 ? wave_event_fast<P>(c, pb, lh, o0, n0, o1, n1, o2, n2, R, T, S, dr, px, py)
                                    : wave_event_pruned<P>(c, pb, lh, o0, n0, o1, n1, o2, n2, px, py);
         L.sres[te] = (int32_t)cnt;  // uniform: every lane stores the same value
     }
@@ -1093,10 +1103,19 @@ struct HitPrefetch {
     int nq_full;
     __device__ __forceinline__ void issue(const float* __restrict__ x, const float* __restrict__ y, int base,
                                           int nh, int n_hits) {
+        nq_full = full_groups(base, nh, n_hits);
+        if (nq_full > 0) g.load(x, y, base & ~3, nq_full);
+    }
+    // The float4 groups of [base, base + nh) that lie entirely below n_hits.
+    __device__ static __forceinline__ int full_groups(int base, int nh, int n_hits) {
         const int a0 = base & ~3;
-        const int nq = (base + nh - a0 + 3) >> 2;
-        nq_full = min(nq, (n_hits - a0) >> 2);
-        if (nq_full > 0) g.load(x, y, a0, nq_full);
+        return min((base + nh - a0 + 3) >> 2, (n_hits - a0) >> 2);
+    }
+    // issue() for a block known to have nq = full_groups(...) >= 1 (no branch).
+    __device__ __forceinline__ void issue_full(const float* __restrict__ x, const float* __restrict__ y, int base,
+                                               int nq) {
+        nq_full = nq;
+        g.load(x, y, base & ~3, nq);
     }
     // Stores the block's hits; returns the largest |x|, |y| this thread
     // stored (the groups of a block with nq_full <= 0 are not loaded: 0).
@@ -1133,25 +1152,52 @@ __global__ __launch_bounds__(NW * kWave) void k_block(const int32_t* __restrict_
     if (b >= n_blocks) return;
     const int e0 = b * eb;
     const int ne = min(eb, n_events - e0);
-    for (int t = threadIdx.x; t <= 3 * ne; t += NT) L.soff[t] = off[3 * (int64_t)e0 + t];
-    if (threadIdx.x == 0) L.s_bad = 0;
-    __syncthreads();
-    const int base = uniform_i(L.soff[0]), end = uniform_i(L.soff[3 * ne]);
+    // The block's offsets go out into registers first, then (the hit range
+    // read by two scalar loads) its hits, so that neither waits for the
+    // offsets to pass through LDS and a barrier; the offsets are stored
+    // once they arrive, while the hits are still in flight.
+    constexpr int OQ = (3 * kMaxEB + 1 + NT - 1) / NT;
+    int ov[OQ];
+#pragma unroll
+    for (int k = 0; k < OQ; ++k) {
+        const int q = (int)threadIdx.x + k * NT;
+        ov[k] = off[3 * (int64_t)e0 + min(q, 3 * ne)];  // clamped: every load in range, no branch
+    }
+    const int base = uniform_i(off[3 * (int64_t)e0]), end = uniform_i(off[3 * (int64_t)(e0 + ne)]);
     using Prefetch = HitPrefetch<HB, NT>;
-    const bool whole = vec && 0 <= base && base <= end && end <= c.n_hits && end - base <= Prefetch::kCap;
-    Prefetch pf;
-    if (whole) pf.issue(x, y, base, end - base, c.n_hits);
-    block_check_describe(L, c, e0, ne, base & ~3, counts, accept, status);
+    const bool whole = vec && 0 <= base && base <= end && end <= c.n_hits && end - base <= Prefetch::kCap &&
+                       Prefetch::full_groups(base, end - base, c.n_hits) > 0;
+    auto stage_offsets = [&] {
+#pragma unroll
+        for (int k = 0; k < OQ; ++k) {
+            const int q = (int)threadIdx.x + k * NT;
+            if (q <= 3 * ne) L.soff[q] = ov[k];
+        }
+        if (threadIdx.x == 0) L.s_bad = 0;
+        __syncthreads();
+    };
+    // The two sides share no code after the branch: where they joined, the
+    // compiler could only wait for the offsets by waiting for every load,
+    // the hits' included.
     if (whole) {
+        Prefetch pf;
+        pf.issue_full(x, y, base, Prefetch::full_groups(base, end - base, c.n_hits));
+        stage_offsets();
+        block_check_describe(L, c, e0, ne, base & ~3, counts, accept, status);
         const uint32_t mag = pf.store(x, y, base, end - base, L.stage_x, L.stage_y);
         if constexpr (P::kMag) publish_mag(L, mag);
+        __syncthreads();
+        const bool bad = uniform_i(L.s_bad) != 0;
+        if (!bad)
+            block_count<P>(L, c, e0, ne, counts, accept, status);
+        else
+            block_general<P>(L, c, x, y, e0, ne, true, vec != 0, counts, accept, status);
+    } else {
+        stage_offsets();
+        block_check_describe(L, c, e0, ne, base & ~3, counts, accept, status);
+        __syncthreads();
+        block_general<P>(L, c, x, y, e0, ne, uniform_i(L.s_bad) != 0, vec != 0, counts, accept, status);
     }
-    __syncthreads();
-    const bool bad = uniform_i(L.s_bad) != 0;
-    if (whole && !bad)
-        block_count<P>(L, c, e0, ne, counts, accept, status);
-    else
-        block_general<P>(L, c, x, y, e0, ne, bad, vec != 0, counts, accept, status);
 }
 
 // Persistent block kernel with a software pipeline: workgroups take chunks
