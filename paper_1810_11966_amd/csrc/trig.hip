@@ -347,7 +347,7 @@ __global__ __launch_bounds__(kScanBlock) void k_finalize(int n_events, Consts c,
 // --------------------------------------------------------------- binned ---
 
 constexpr int kBinWaves = 4;     // waves (one event each) per workgroup
-constexpr int kBinResident = 6;  // persistent binned workgroups per CU (LDS bound)
+constexpr int kBinResident = 7;  // persistent binned workgroups per CU (LDS bound)
 
 // One wave per event, events [4 b, 4 b + 4) for workgroup block b.
 // Non-persistent when block_counter == nullptr (b = blockIdx.x); otherwise

@@ -59,12 +59,20 @@ __device__ __forceinline__ float widen_up(float f) {
 
 // LDS of one wave: cell ends and the two payload floats per hit, in cell
 // order, for layers 1 and 2.  Float arrays first (16-byte aligned: the
-// fallback path reuses a1/b1 as its layer-0 buffers).
+// fallback path reuses a1/b1 as its layer-0 buffers).  A cell end is at most
+// kBinCap = 256, so the ends are 16-bit, two cells per 32-bit word (cell t in
+// the half t & 1 of word t >> 1): 5 KB per wave, seven workgroups per CU.
 struct BinLds {
     float a1[kBinCap], b1[kBinCap];
     float a2[kBinCap], b2[kBinCap];
-    int end1[kBinCap], end2[kBinCap];
+    uint32_t end1[kBinCap / 2], end2[kBinCap / 2];
 };
+static_assert(kBinCap < 65536, "cell ends fit in 16 bits");
+
+// Cell t's 16-bit entry of a packed end array.
+__device__ __forceinline__ int cell_end(const uint32_t* end, int t) {
+    return (int)reinterpret_cast<const uint16_t*>(end)[t];
+}
 
 // Cells over [kmin, kmax] of one layer.  cell(v) is non-decreasing in v
 // (binary32 subtraction, multiplication and floor are monotone, the clamps
@@ -77,10 +85,10 @@ struct Bins {
         return (int)__builtin_fminf(__builtin_fmaxf(t, 0.0f), (float)(n_cells - 1));
     }
     // Index range [first, last) of the hits in cells cell(lo) .. cell(hi).
-    __device__ __forceinline__ void range(const int* end, float lo, float hi, int& first, int& last) const {
+    __device__ __forceinline__ void range(const uint32_t* end, float lo, float hi, int& first, int& last) const {
         const int cl = cell(lo), ch = cell(hi);
-        first = cl > 0 ? end[cl - 1] : 0;
-        last = end[ch];
+        first = cl > 0 ? cell_end(end, cl - 1) : 0;
+        last = cell_end(end, ch);
     }
 };
 
@@ -106,7 +114,7 @@ struct LayerRegs {
 // Counting sort of the n hits of one layer (held in h, n <= NR kWave) into
 // cells of the key K::key, storing K::payload in cell order.  Whole wave.
 template <class K, int NR>
-__device__ Bins build_bins_r(const Consts& c, const LayerRegs& h, int n, int* end, float* pa, float* pb) {
+__device__ Bins build_bins_r(const Consts& c, const LayerRegs& h, int n, uint32_t* end, float* pa, float* pb) {
     const int lane = (int)lane_id();
     float key[NR];
     float2 pay[NR];
@@ -136,45 +144,52 @@ __device__ Bins build_bins_r(const Consts& c, const LayerRegs& h, int n, int* en
     // Any non-negative scale keeps cell() monotone; the hardware reciprocal
     // is enough to spread the keys over the cells.
     b.inv_w = (width > 0.0f && width < __builtin_inff()) ? __builtin_amdgcn_rcpf(width) * (float)b.n_cells : 0.0f;
-    for (int t = lane; t < b.n_cells; t += kWave) end[t] = 0;
+    for (int t = lane; t < b.n_cells / 2; t += kWave) end[t] = 0u;
     wave_lds_sync();
+    // Histogram: cell t counts in the half t & 1 of word t >> 1 (a half
+    // never exceeds kBinCap, so no carry reaches the other half).
     int cell[NR];
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         cell[r] = -1;
         if (!__builtin_isnan(key[r])) {
             cell[r] = b.cell(key[r]);
-            atomicAdd(&end[cell[r]], 1);
+            atomicAdd(&end[cell[r] >> 1], 1u << (16 * (cell[r] & 1)));
         }
     }
     wave_lds_sync();
     // Exclusive scan of the cell sizes: lane L owns cells [L*per, L*per + per)
-    // (per = 1, 2 or 4), read and written with one vector access per lane
+    // (per = 1, 2 or 4), read and written with one access per lane
     // (consecutive lanes, consecutive addresses: no bank conflicts).
     static_assert(kBinCap <= 4 * kWave, "at most four cells per lane");
     const int per = b.n_cells / kWave;  // n_cells is a multiple of 64
     int4 sz = make_int4(0, 0, 0, 0);
-    if (per == 4)
-        sz = reinterpret_cast<const int4*>(end)[lane];
-    else if (per == 2)
-        sz = make_int4(reinterpret_cast<const int2*>(end)[lane].x, reinterpret_cast<const int2*>(end)[lane].y, 0, 0);
-    else
-        sz.x = end[lane];
+    if (per == 4) {
+        const uint2 v = reinterpret_cast<const uint2*>(end)[lane];
+        sz = make_int4((int)(v.x & 0xFFFFu), (int)(v.x >> 16), (int)(v.y & 0xFFFFu), (int)(v.y >> 16));
+    } else if (per == 2) {
+        const uint32_t v = end[lane];
+        sz = make_int4((int)(v & 0xFFFFu), (int)(v >> 16), 0, 0);
+    } else {
+        sz.x = cell_end(end, lane);
+    }
     const int local = (sz.x + sz.y) + (sz.z + sz.w);
     const int s0 = wave_inclusive_sum(local) - local;  // starts of the lane's cells
     const int4 st = make_int4(s0, s0 + sz.x, s0 + sz.x + sz.y, s0 + sz.x + sz.y + sz.z);
     if (per == 4)
-        reinterpret_cast<int4*>(end)[lane] = st;
+        reinterpret_cast<uint2*>(end)[lane] =
+            make_uint2((uint32_t)st.x | ((uint32_t)st.y << 16), (uint32_t)st.z | ((uint32_t)st.w << 16));
     else if (per == 2)
-        reinterpret_cast<int2*>(end)[lane] = make_int2(st.x, st.y);
+        end[lane] = (uint32_t)st.x | ((uint32_t)st.y << 16);
     else
-        end[lane] = st.x;
+        reinterpret_cast<uint16_t*>(end)[lane] = (uint16_t)st.x;
     wave_lds_sync();
-    // Scatter; afterwards end[cell] is the end of the cell.
+    // Scatter; afterwards cell t's entry is the end of cell t.
 #pragma unroll
     for (int r = 0; r < NR; ++r) {
         if (cell[r] >= 0) {
-            const int pos = atomicAdd(&end[cell[r]], 1);
+            const int sh = 16 * (cell[r] & 1);
+            const int pos = (int)((atomicAdd(&end[cell[r] >> 1], 1u << sh) >> sh) & 0xFFFFu);
             pa[pos] = pay[r].x;
             pb[pos] = pay[r].y;
         }
@@ -186,7 +201,7 @@ __device__ Bins build_bins_r(const Consts& c, const LayerRegs& h, int n, int* en
 // build_bins_r with the fewest rounds that hold the layer (1, 2 or 4 times
 // kWave hits; n <= kBinCap).
 template <class K>
-__device__ __forceinline__ Bins build_bins(const Consts& c, const LayerRegs& h, int n, int* end, float* pa,
+__device__ __forceinline__ Bins build_bins(const Consts& c, const LayerRegs& h, int n, uint32_t* end, float* pa,
                                            float* pb) {
     static_assert(kBinRounds == 4, "round counts 1, 2 and 4");
     if (n <= kWave) return build_bins_r<K, 1>(c, h, n, end, pa, pb);
