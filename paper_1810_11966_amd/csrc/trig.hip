@@ -53,7 +53,7 @@ constexpr int kCompactItems = 4;    // events per thread in compaction
 constexpr int kPersistWaves = 4;    // waves per workgroup, persistent form
 constexpr int kPersistBatch = 4;    // work units taken per atomic
 constexpr int kDefaultTileUnits = 8;  // pair tiles (of 64 pairs) per work unit
-constexpr int kClaimsPerGroup = 8;    // pipelined batched form: block claims per workgroup
+constexpr int kClaimsPerGroup = 8;    // claims per workgroup (pipelined batched form) or per wave (binned)
 constexpr double kRuleFill = 0.85;    // built-in rule: hits per block over the LDS capacity
 
 template <class T>
@@ -347,58 +347,55 @@ __global__ __launch_bounds__(kScanBlock) void k_finalize(int n_events, Consts c,
 // --------------------------------------------------------------- binned ---
 
 constexpr int kBinWaves = 4;     // waves (one event each) per workgroup
-constexpr int kBinResident = 7;  // persistent binned workgroups per CU (LDS bound)
+constexpr int kBinResident = 8;  // binned workgroups per CU (LDS bound)
 
-// One wave per event, events [4 b, 4 b + 4) for workgroup block b.
-// Non-persistent when block_counter == nullptr (b = blockIdx.x); otherwise
-// workgroups take chunks of `chunk` consecutive blocks from *block_counter
-// (zero at launch; one atomic per chunk) until none is left.  Events with
-// more than kBinCap hits in layer 1 or 2 take the pair-pruned path from HBM.
-// The register budget is held to kBinResident waves per SIMD, the occupancy
-// its LDS allows (one wave per SIMD per workgroup).
+// One wave per event.  Non-persistent when block_counter == nullptr:
+// workgroup b takes events [4 b, 4 b + 4), one per wave.  Otherwise every
+// wave on its own takes runs of `chunk` consecutive events from
+// *block_counter (zero at launch; one atomic per run) until none is left:
+// no barrier, and no LDS beyond the waves' cells (8 workgroups fit on a CU).
+// Events with more than kBinCap hits in layer 1 or 2 take the pair-pruned
+// path from HBM.  The register budget is held to kBinResident waves per
+// SIMD, the occupancy its LDS allows (one wave per SIMD per workgroup).
 template <class B>
 __global__ __launch_bounds__(kBinWaves * kWave) __attribute__((amdgpu_waves_per_eu(kBinResident))) void k_binned(
     const int32_t* __restrict__ off, int n_events, const float* __restrict__ x, const float* __restrict__ y,
     Consts c, unsigned* block_counter, int chunk, int32_t* __restrict__ counts, uint8_t* __restrict__ accept,
     uint32_t* status) {
     __shared__ __align__(16) BinLds lds_all[kBinWaves];
-    __shared__ unsigned s_chunk;
     const int w = uniform_i((int)(threadIdx.x / kWave));
     BinLds& L = lds_all[w];
-    const int64_t n_blocks = ((int64_t)n_events + kBinWaves - 1) / kBinWaves;
-    int64_t first = blockIdx.x, last = first + 1;
-    for (;;) {
-        if (block_counter) {
-            // every branch below depends on workgroup-uniform values only
-            if (threadIdx.x == 0) s_chunk = atomicAdd(block_counter, 1u);
-            __syncthreads();
-            first = (int64_t)(unsigned)uniform_i((int)s_chunk) * chunk;
-            last = min(first + chunk, n_blocks);
-            __syncthreads();
-        }
-        if (first >= n_blocks) break;
-        for (int64_t blk = first; blk < last; ++blk) {
-            const int64_t e64 = blk * kBinWaves + w;
-            if (e64 >= n_events) continue;
-            const int e = (int)e64;
-            EventRange ev;
-            int32_t cnt = load_event(off, e, c.n_hits, ev);
-            if (cnt == 0 && ev.n0 > 0 && ev.n1 > 0 && ev.n2 > 0) {
-                if (ev.n1 <= kBinCap && ev.n2 <= kBinCap) {
-                    cnt = (int32_t)wave_event_binned<B>(c, x, y, ev.o0, ev.n0, ev.o1, ev.n1, ev.o2, ev.n2, L);
-                } else {
-                    using P = typename B::Prune;
-                    const GlobalHits gh{x, y};
-                    float M = 0.0f;
-                    if constexpr (P::kMag) M = layer_mag(gh, ev.o1, ev.n1);
-                    cnt = (int32_t)wave_event_pruned<P>(c, P::bounds(c, M), gh, ev.o0, ev.n0, ev.o1, ev.n1, ev.o2,
-                                                        ev.n2, L.a1, L.b1);
-                    wave_lds_sync();
-                }
+    auto one_event = [&](int e) {
+        EventRange ev;
+        int32_t cnt = load_event(off, e, c.n_hits, ev);
+        if (cnt == 0 && ev.n0 > 0 && ev.n1 > 0 && ev.n2 > 0) {
+            if (ev.n1 <= kBinCap && ev.n2 <= kBinCap) {
+                cnt = (int32_t)wave_event_binned<B>(c, x, y, ev.o0, ev.n0, ev.o1, ev.n1, ev.o2, ev.n2, L);
+            } else {
+                using P = typename B::Prune;
+                const GlobalHits gh{x, y};
+                float M = 0.0f;
+                if constexpr (P::kMag) M = layer_mag(gh, ev.o1, ev.n1);
+                cnt = (int32_t)wave_event_pruned<P>(c, P::bounds(c, M), gh, ev.o0, ev.n0, ev.o1, ev.n1, ev.o2,
+                                                    ev.n2, L.a1, L.b1);
+                wave_lds_sync();
             }
-            if (lane_id() == 0) write_result(e, cnt, c, counts, accept, status);
         }
-        if (!block_counter) break;
+        if (lane_id() == 0) write_result(e, cnt, c, counts, accept, status);
+    };
+    if (!block_counter) {
+        const int64_t e = (int64_t)blockIdx.x * kBinWaves + w;
+        if (e < n_events) one_event((int)e);
+        return;
+    }
+    for (;;) {
+        // every branch below depends on wave-uniform values only
+        unsigned claim = 0u;
+        if (lane_id() == 0) claim = atomicAdd(block_counter, 1u);
+        const int64_t first = (int64_t)(unsigned)uniform_i((int)claim) * chunk;
+        if (first >= n_events) break;
+        const int last = (int)min(first + chunk, (int64_t)n_events);
+        for (int e = (int)first; e < last; ++e) one_event(e);
     }
 }
 
@@ -822,8 +819,9 @@ int launch_binned(const trig_events_csr* ev, const trig_hits* h, const trig_para
         if (int r = check_launch("k_zero_u32")) return r;
         grid = (unsigned)std::min<int64_t>(n_blocks, (int64_t)device_cus() * kBinResident);
     }
-    // Persistent: chunks of blocks per claim, about kClaimsPerGroup claims per workgroup.
-    const int chunk = counter ? (int)std::max<int64_t>(1, n_blocks / ((int64_t)grid * kClaimsPerGroup)) : 1;
+    // Persistent: runs of events per claim, about kClaimsPerGroup claims per wave.
+    const int chunk =
+        counter ? (int)std::max<int64_t>(1, (int64_t)n / ((int64_t)grid * kBinWaves * kClaimsPerGroup)) : 1;
     if (mark_start(s)) return fail(TRIG_EHIP, "hipEventRecord(start)");
     hipLaunchKernelGGL(k_binned<B>, dim3(grid), dim3(kBinWaves * kWave), 0, s, ev->layer_offsets, n, h->x, h->y, c,
                        counter, chunk, counts, accept, p->out_status);
