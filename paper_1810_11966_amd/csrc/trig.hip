@@ -764,10 +764,13 @@ int resident_per_cu(BlockKernel kern, int threads) {
     return per_cu;
 }
 
+// The kernel for a shape; blocks of at most kSmallEB events at 2048 hits and
+// four waves take the small event table (eight workgroups per CU).
 template <class P>
-BlockKernel block_kernel(int hb, int nw, bool pipelined) {
+BlockKernel block_kernel(int hb, int nw, bool pipelined, int eb) {
+    if (!pipelined && hb == 2048 && nw == 4 && eb <= kSmallEB) return k_block<P, 2048, 4, kSmallEB>;
 #define TRIG_BLOCK_CASE(H, W) \
-    if (hb == H && nw == W) return pipelined ? k_block_pipe<P, H, W> : k_block<P, H, W>;
+    if (hb == H && nw == W) return pipelined ? k_block_pipe<P, H, W> : k_block<P, H, W, kMaxEB>;
     TRIG_BLOCK_CASE(1024, 1) TRIG_BLOCK_CASE(1024, 2) TRIG_BLOCK_CASE(1024, 4)
     TRIG_BLOCK_CASE(2048, 1) TRIG_BLOCK_CASE(2048, 2) TRIG_BLOCK_CASE(2048, 4)
     TRIG_BLOCK_CASE(4096, 1) TRIG_BLOCK_CASE(4096, 2) TRIG_BLOCK_CASE(4096, 4)
@@ -784,7 +787,7 @@ int launch_block(const trig_events_csr* ev, const trig_hits* h, const trig_param
     // Block stealing uses the pipelined kernel, which needs 16-byte aligned
     // hit arrays; otherwise one workgroup per block.
     const bool pipelined = (p->flags & TRIG_EXEC_PERSISTENT) && vec;
-    const BlockKernel kern = block_kernel<P>(bs.hb, bs.nw, pipelined);
+    const BlockKernel kern = block_kernel<P>(bs.hb, bs.nw, pipelined, bs.eb);
     if (!kern) return fail(TRIG_EINVAL, "block_hits must be 1024, 2048 or 4096 and block_waves 1, 2 or 4");
     const int n_blocks = (int)cdiv(n, bs.eb);
     unsigned* counter = nullptr;

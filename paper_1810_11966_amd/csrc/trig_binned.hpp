@@ -61,7 +61,7 @@ __device__ __forceinline__ float widen_up(float f) {
 // order, for layers 1 and 2.  Float arrays first (16-byte aligned: the
 // fallback path reuses a1/b1 as its layer-0 buffers).  A cell end is at most
 // kBinCap = 256, so the ends are 16-bit, two cells per 32-bit word (cell t in
-// the half t & 1 of word t >> 1): 5 KB per wave, seven workgroups per CU.
+// the half t & 1 of word t >> 1): 5 KB per wave, eight workgroups per CU.
 struct BinLds {
     float a1[kBinCap], b1[kBinCap];
     float a2[kBinCap], b2[kBinCap];

@@ -750,9 +750,6 @@ __device__ void wave_event(const Consts& c, const H& hits, int h_base, int o0, i
     }
 }
 
-// The block kernel.  Non-persistent when block_counter == nullptr (block =
-// blockIdx.x); otherwise workgroups take blocks from *block_counter until
-// they run out (the counter must be zero at launch).
 // Copies hits [base, base + nh) of x and y into xs/ys (LDS) at local index
 // (h - a0), a0 = base rounded down to a multiple of 4, with 16-byte loads
 // issued together (every thread's loads are in flight before any LDS write).
@@ -826,8 +823,9 @@ __device__ __forceinline__ uint32_t stage_hits(const float* __restrict__ x, cons
     return mag;
 }
 
-// LDS of the block kernels.
-template <int HB, int NW>
+// LDS of the block kernels: HB staged hits, NW waves, an event table of EB
+// events (a block holds at most EB events).
+template <int HB, int NW, int EB>
 struct BlockLds {
     // HB hits plus up to 3 before the first and 3 after the last (4-aligned copy)
     float stage_x[HB + 8];
@@ -838,22 +836,37 @@ struct BlockLds {
     // layer sizes <= HB <= 4096): da = o0 | n0 << 13 | R << 26 (R <= 16) |
     // S << 31, db = o1 | n1 << 13 | (T / 4) << 26 (T <= 64), dc = o2 | n2 << 13.
     // dr = recip16 of the lane layer's size (fast-path events only).
-    uint32_t da[kMaxEB], db[kMaxEB], dc[kMaxEB], dr[kMaxEB];
-    int32_t soff[3 * kMaxEB + 1];
-    int32_t sres[kMaxEB];
+    uint32_t da[EB], db[EB], dc[EB], dr[EB];
+    int32_t soff[3 * EB + 1];
+    int32_t sres[EB];
     float wmag[NW];  // per wave: largest |x|, |y| it staged (TRIG_TEST_MSD bounds)
     int s_block, s_next, s_bad;
 };
 
+// Waves per SIMD that a workgroup's BlockLds allows on a CU (160 KB of LDS,
+// at most eight waves per SIMD): the register budget k_block is held to.
+template <int HB, int NW, int EB>
+constexpr int block_waves_per_simd() {
+    int wg = (int)(163840 / sizeof(BlockLds<HB, NW, EB>));
+    if (wg * NW > 4 * 8) wg = 4 * 8 / NW;
+    const int w = wg * NW / 4;
+    return w < 1 ? 1 : w;
+}
+// An event table small enough that eight 2048-hit workgroups of four waves
+// fit on a CU (seven with the full kMaxEB table); blocks of at most kSmallEB
+// events use it.
+constexpr int kSmallEB = 52;
+static_assert(block_waves_per_simd<2048, 4, kSmallEB>() == 8, "eight 2048-hit workgroups per CU");
+
 // Each wave's largest staged |x|, |y| into L.wmag (whole waves; read after
 // the next barrier by block_mag).  m: mag4 bits.
-template <int HB, int NW>
-__device__ __forceinline__ void publish_mag(BlockLds<HB, NW>& L, uint32_t m) {
+template <int HB, int NW, int EB>
+__device__ __forceinline__ void publish_mag(BlockLds<HB, NW, EB>& L, uint32_t m) {
     const float wm = wave_max_f(mag_of(m));
     if (lane_id() == 0) L.wmag[threadIdx.x / kWave] = wm;
 }
-template <int HB, int NW>
-__device__ __forceinline__ float block_mag(const BlockLds<HB, NW>& L) {
+template <int HB, int NW, int EB>
+__device__ __forceinline__ float block_mag(const BlockLds<HB, NW, EB>& L) {
     float m = 0.0f;
 #pragma unroll
     for (int w = 0; w < NW; ++w) m = __builtin_fmaxf(m, L.wmag[w]);
@@ -862,8 +875,8 @@ __device__ __forceinline__ float block_mag(const BlockLds<HB, NW>& L) {
 
 // CSR checks of the block's events (offsets in L.soff); malformed events get
 // -1 here.  Returns (workgroup-uniform) whether any event was malformed.
-template <int HB, int NW>
-__device__ bool block_validate(BlockLds<HB, NW>& L, const Consts& c, int e0, int ne, int32_t* counts,
+template <int HB, int NW, int EB>
+__device__ bool block_validate(BlockLds<HB, NW, EB>& L, const Consts& c, int e0, int ne, int32_t* counts,
                                uint8_t* accept, uint32_t* status) {
     constexpr int NT = NW * kWave;
     if (threadIdx.x == 0) L.s_bad = 0;
@@ -885,8 +898,8 @@ __device__ bool block_validate(BlockLds<HB, NW>& L, const Consts& c, int e0, int
 // index = global index - a0), one lane per event; events decided without
 // pairs get their result here (0 for an empty layer, -2 for a count beyond
 // int32).  Ends with a barrier.
-template <int HB, int NW>
-__device__ void block_descriptors(BlockLds<HB, NW>& L, int cur, int nsub, int a0) {
+template <int HB, int NW, int EB>
+__device__ void block_descriptors(BlockLds<HB, NW, EB>& L, int cur, int nsub, int a0) {
     constexpr int NT = NW * kWave;
     for (int te = threadIdx.x; te < nsub; te += NT) {
         const int ev = cur + te;
@@ -914,8 +927,8 @@ __device__ void block_descriptors(BlockLds<HB, NW>& L, int cur, int nsub, int a0
 // event (local hit index = global index - a0): malformed events get -1 and
 // set L.s_bad (zero on entry); the descriptors are used only when no event
 // is malformed and the block is staged whole.  No barrier.
-template <int HB, int NW>
-__device__ __forceinline__ void block_check_describe(BlockLds<HB, NW>& L, const Consts& c, int e0, int ne, int a0,
+template <int HB, int NW, int EB>
+__device__ __forceinline__ void block_check_describe(BlockLds<HB, NW, EB>& L, const Consts& c, int e0, int ne, int a0,
                                                      int32_t* counts, uint8_t* accept, uint32_t* status) {
     constexpr int NT = NW * kWave;
     for (int te = threadIdx.x; te < ne; te += NT) {
@@ -948,8 +961,8 @@ __device__ __forceinline__ void block_check_describe(BlockLds<HB, NW>& L, const 
 // Counts of the described events from the staged hits (events round-robin
 // over the waves, a static assignment), then the results of events
 // [e_first, e_first + nsub) with one lane per event.  Ends with a barrier.
-template <class P, int HB, int NW>
-__device__ void block_count(BlockLds<HB, NW>& L, const Consts& c, int e_first, int nsub, int32_t* counts,
+template <class P, int HB, int NW, int EB>
+__device__ void block_count(BlockLds<HB, NW, EB>& L, const Consts& c, int e_first, int nsub, int32_t* counts,
                             uint8_t* accept, uint32_t* status) {
     constexpr int NT = NW * kWave;
     const int w = uniform_i(threadIdx.x / kWave);
@@ -1003,8 +1016,8 @@ __device__ void block_count(BlockLds<HB, NW>& L, const Consts& c, int e_first, i
 // event by event from HBM; otherwise sub-blocks of consecutive events whose
 // hits fit in LDS are staged and counted (an event larger than LDS is read
 // from HBM by wave 0).  Ends with a barrier.
-template <class P, int HB, int NW>
-__device__ void block_general(BlockLds<HB, NW>& L, const Consts& c, const float* __restrict__ x,
+template <class P, int HB, int NW, int EB>
+__device__ void block_general(BlockLds<HB, NW, EB>& L, const Consts& c, const float* __restrict__ x,
                               const float* __restrict__ y, int e0, int ne, bool bad, bool vec, int32_t* counts,
                               uint8_t* accept, uint32_t* status) {
     constexpr int NT = NW * kWave;
@@ -1133,20 +1146,23 @@ struct HitPrefetch {
     }
 };
 
-// The block kernel (one block of eb consecutive events per workgroup).
+// The block kernel (one block of eb <= EB consecutive events per workgroup;
+// EB sizes the event table in LDS, and the registers are held to the waves
+// per SIMD that this LDS allows).
 // `vec`: x and y are 16-byte aligned (the pipelined kernel's same argument
 // slot carries its claim chunk instead).  A block whose hits fit in LDS is
 // staged whole: its hit loads are issued first, the events are checked and
 // described while they are in flight, and one barrier later the counting
 // starts.  Other blocks take the general path.
-template <class P, int HB, int NW>
-__global__ __launch_bounds__(NW * kWave) void k_block(const int32_t* __restrict__ off, int n_events,
+template <class P, int HB, int NW, int EB>
+__global__ __launch_bounds__(NW * kWave) __attribute__((amdgpu_waves_per_eu(block_waves_per_simd<HB, NW, EB>())))
+void k_block(const int32_t* __restrict__ off, int n_events,
                                                          const float* __restrict__ x,
                                                          const float* __restrict__ y, Consts c, int eb,
                                                          int n_blocks, unsigned* /*unused*/, int vec,
                                                          int32_t* __restrict__ counts,
                                                          uint8_t* __restrict__ accept, uint32_t* status) {
-    __shared__ __align__(16) BlockLds<HB, NW> L;
+    __shared__ __align__(16) BlockLds<HB, NW, EB> L;
     constexpr int NT = NW * kWave;
     const int b = blockIdx.x;
     if (b >= n_blocks) return;
@@ -1156,7 +1172,7 @@ __global__ __launch_bounds__(NW * kWave) void k_block(const int32_t* __restrict_
     // read by two scalar loads) its hits, so that neither waits for the
     // offsets to pass through LDS and a barrier; the offsets are stored
     // once they arrive, while the hits are still in flight.
-    constexpr int OQ = (3 * kMaxEB + 1 + NT - 1) / NT;
+    constexpr int OQ = (3 * EB + 1 + NT - 1) / NT;
     int ov[OQ];
 #pragma unroll
     for (int k = 0; k < OQ; ++k) {
@@ -1213,7 +1229,7 @@ __global__ __launch_bounds__(NW * kWave) void k_block_pipe(const int32_t* __rest
                                                               int n_blocks, unsigned* block_counter, int chunk,
                                                               int32_t* __restrict__ counts,
                                                               uint8_t* __restrict__ accept, uint32_t* status) {
-    __shared__ __align__(16) BlockLds<HB, NW> L;
+    __shared__ __align__(16) BlockLds<HB, NW, kMaxEB> L;
     constexpr int NT = NW * kWave;
     const int t = (int)threadIdx.x;
     HitPrefetch<HB, NT> pf;
