@@ -324,7 +324,7 @@ struct ScatterRec {
     uint32_t pad;
 };
 
-__global__ __launch_bounds__(kFilterThreads) void k_filter_scatter(
+__global__ __launch_bounds__(kFilterThreads) __attribute__((amdgpu_waves_per_eu(8))) void k_filter_scatter(
     const int64_t* __restrict__ off, int n_events, int64_t n_hits, const uint8_t* __restrict__ st,
     const float* __restrict__ x, const float* __restrict__ y, uint32_t layers, int vec,
     const int32_t* __restrict__ counts, const int64_t* __restrict__ partials,
