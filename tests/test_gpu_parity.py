@@ -154,19 +154,21 @@ def test_block_shapes_and_large_events(gpu):
 
 def test_block_hit_range_edges(gpu):
     """Batched form at the edges of its whole-block staging: blocks of exactly
-    the LDS capacity less one float4 group (1020 hits at 1024) and one hit
-    more, block ranges starting at every offset within a 16-byte group, and
-    a last block whose hits all lie in the final partial float4 group of the
-    hit arrays (n_hits = 4k + 1, 2, 3)."""
+    the LDS capacity less one float4 group (1020 hits at 1024, 2044 at 2048)
+    and one hit more, block ranges starting at every offset within a 16-byte
+    group, and a last block whose hits all lie in the final partial float4
+    group of the hit arrays (n_hits = 4k + 1, 2, 3).  Blocks of up to 52
+    events at 2048 hits take the kernel with the small event table."""
     head = [(340, 340, 340), (340, 340, 341), (1, 2, 1), (339, 341, 340), (5, 6, 7)]
     n_head = sum(a + b + c for a, b, c in head)
     for tail, last in ((1, (1, 0, 0)), (2, (1, 1, 0)), (3, (1, 1, 1))):
         pad = (4 - (n_head + 3) % 4) % 4  # the hits before the last event: a multiple of 4
         s = helpers.ragged_sizes_set(head + [(1, 1, 1 + pad), last], seed=20 + tail)
         assert s.n_hits % 4 == tail and s.offsets[-4] == s.n_hits - tail
-        for eb in (1, 2, 3):
-            assert_parity(gpu, s, "msd", "pruned", f"hit range edges tail={tail} block_events={eb}",
-                          block_events=eb, block_hits=1024)
+        for hb in (1024, 2048):  # at 2048 hits the first two events fill 2041 of 2044, three 2045
+            for eb in (1, 2, 3):
+                assert_parity(gpu, s, "msd", "pruned", f"hit range edges tail={tail} block_hits={hb} "
+                              f"block_events={eb}", block_events=eb, block_hits=hb)
         assert_parity(gpu, s, "msd", "auto", f"hit range edges tail={tail}")
 
 
