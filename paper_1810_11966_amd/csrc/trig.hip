@@ -464,10 +464,22 @@ __global__ __launch_bounds__(kBinWaves * kWave) void k_event_z(const int32_t* __
     if (cnt == 0 && ev.n0 > 0 && ev.n1 > 0 && ev.n2 > 0) {
         const SlopeHits sh{x, y, z};
         const PairBounds pb = event_bounds<P>(c, sh, ev.o0, ev.n0, ev.o1, ev.n1);
-        if (pb.prune)
-            cnt = (int32_t)wave_event_pruned<P>(c, pb, sh, ev.o0, ev.n0, ev.o1, ev.n1, ev.o2, ev.n2, lds, lds + kPBuf);
-        else
+        if (pb.prune) {
+            // An event that fits one lane pass and one buffer fill takes the
+            // fast path (the prefilter folded over all pairs, one vote); the
+            // slope tests are symmetric in the two layers, as the batched
+            // form's are.
+            int R, TB, S;
+            event_layout(ev.n0, ev.n1, R, TB, S);
+            if (TB > 0)
+                cnt = (int32_t)wave_event_fast<P>(c, pb, sh, ev.o0, ev.n0, ev.o1, ev.n1, ev.o2, ev.n2, R, TB, S,
+                                                  recip16(S ? ev.n0 : ev.n1), lds, lds + kPBuf);
+            else
+                cnt = (int32_t)wave_event_pruned<P>(c, pb, sh, ev.o0, ev.n0, ev.o1, ev.n1, ev.o2, ev.n2, lds,
+                                                    lds + kPBuf);
+        } else {
             cnt = (int32_t)wave_count<T, KCH>(x, y, z, ev, 0, pair_tiles(ev), c, lds);
+        }
     }
     if (lane_id() == 0) write_result(e, cnt, c, counts, accept, status);
 }

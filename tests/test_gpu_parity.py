@@ -618,13 +618,16 @@ def test_per_hit_z_all_forms(gpu):
     """Hits on staggered modules, each with its own z (trig_hits.z): every
     form against the oracle's per-triplet fit (Szz and its reciprocal per
     triplet) and slope window, on the 10k workload, near-threshold tracks on
-    all stagger combinations, events with many passing triplets, and events
-    whose z no slope bound covers (0, negative, NaN, infinite, tiny z under
-    huge coordinates: the every-triplet path)."""
+    all stagger combinations, events with many passing triplets, ragged layer
+    sizes on both sides of the one-pass limits (either layer in the lanes, or
+    several passes), and events whose z no slope bound covers (0, negative,
+    NaN, infinite, tiny z under huge coordinates: the every-triplet path)."""
     sets = {"small_10k": synth.staggered(synth.make_event_set(synth.SMALL_10K, n_events=4000)),
             "near": helpers.near_threshold_events_z(300, 6, seed=3, rel=1e-4),
             "near 1e-6": helpers.near_threshold_events_z(200, 6, seed=4, rel=1e-6),
             "two particles": synth.staggered(helpers.two_particle_events(1500, seed=6)),
+            "ragged": synth.staggered(helpers.ragged_sizes_set(
+                [sz for n in (1, 2, 31, 33, 63, 64, 65, 129) for sz in ((n, 5, 7), (5, n, 7), (n, n, 3))], seed=11)),
             "odd z": helpers.odd_z_events(5)}
     for name, s in sets.items():
         for test in ("msd", "window"):
