@@ -316,19 +316,20 @@ def cpu_baseline(s, test, target_s):
 
 
 def _timed_calls(torch, trig, dev_in, n_ev, form, test, steps, extra_flags=0, hit_z=None):
-    """Mean ms of one trig_select call (steps after one warm-up) and its
-    outputs."""
+    """Mean ms of one trig_select call (steps after one call and the GPU's
+    warm-up) and its outputs."""
     off, x, y = dev_in
-    r = None
-    for _ in range(1 + steps):
-        if r is None:
-            r = trig.select(off, x, y, hit_z=hit_z, test=test, form=form, compact=True, extra_flags=extra_flags)
-            torch.cuda.synchronize()
-            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            a.record()
-        else:
-            trig.select(off, x, y, hit_z=hit_z, test=test, form=form, compact=True, extra_flags=extra_flags,
-                        workspace=r.workspace, out=(r.counts, r.accept))
+    r = trig.select(off, x, y, hit_z=hit_z, test=test, form=form, compact=True, extra_flags=extra_flags)
+
+    def again():
+        trig.select(off, x, y, hit_z=hit_z, test=test, form=form, compact=True, extra_flags=extra_flags,
+                    workspace=r.workspace, out=(r.counts, r.accept))
+    torch.cuda.synchronize()
+    warm_gpu(torch, again)
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        again()
     b.record()
     torch.cuda.synchronize()
     return a.elapsed_time(b) / steps, r
